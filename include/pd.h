@@ -1,0 +1,197 @@
+/*
+ * pd.h -- C ABI of the MI355X peridynamic grain-aggregate library.
+ *
+ * One explicit-dynamics step of bond-based peridynamics for lattice-meshed
+ * grains (arxiv 2506.05362):
+ *   - bond force c s (xi+eta)/|xi+eta| over the horizon family of each node,
+ *     with irreversible breaking when the stretch exceeds s0 and damage
+ *     (Sec. 3.1 eq. (pmb), Sec. 3.1.1 eq. (peri-damage));
+ *   - repulsive contact -K_n (R_c - |p_y - p_x|) e(y,x) from nodes of other
+ *     grains (Sec. 3.2 eq. (repulsive-force)), found by a cell-list search;
+ *   - rigid planar walls with the spherical-cap law (Sec. 4.1), several walls
+ *     summed (Sec. 4.1.1); body force (Sec. 5.1 eq. (intra_particle));
+ *   - velocity Verlet (Sec. 6.2).
+ * The problem statement the calls follow is Sec. 2.1 (grains P_i, material
+ * points x with displacement u, initial data u0, v0) and Sec. 5.1 (equation of
+ * motion with F_int = F_intra + F_inter and F_ext = F_wall + b).
+ *
+ * Conventions shared by every call:
+ *   - a "(3,N) field" is SoA FP64: x[0..N), y[N..2N), z[2N..3N);
+ *   - nodes are grouped by grain; node n of grain g sits at
+ *     X = origin[g] + h[g] * ijk[n] with grain-local lattice indices 0..1023;
+ *   - the nodal volume is h[g]^3 (nodal quadrature, Sec. 6.1);
+ *   - lengths in m, forces per volume in N/m^3, time in s.
+ *
+ * Ownership: every pointer passed in is caller-owned, read during the call
+ * only and never retained.  The library owns its device buffers; it allocates
+ * them through the caller's allocator callback (or hipMalloc when none is
+ * given) and enqueues all work on the caller's HIP stream.
+ *
+ * Errors: every call returns a pd_status; no exception crosses the ABI.  A
+ * per-context last-error string carries details.  Call order is
+ * pd_init -> pd_build_bonds -> (pd_step | pd_get | pd_set_wall | state)*;
+ * other orders return PD_ERR_STATE.  A context is single-threaded.
+ */
+#ifndef PD_H
+#define PD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t pd_status;
+enum {
+  PD_OK = 0,
+  PD_ERR_INVALID = -1,     /* bad argument; details in pd_last_error */
+  PD_ERR_STATE = -2,       /* call out of order */
+  PD_ERR_OOM = -3,         /* allocation failed */
+  PD_ERR_HIP = -4,         /* a HIP runtime call failed */
+  PD_ERR_UNSTABLE = -5,    /* NaN/Inf force, wall penetration (d <= -R_c), Verlet skin
+                              exceeded, or contact-candidate capacity exceeded */
+  PD_ERR_UNSUPPORTED = -6, /* valid request this build does not implement */
+  PD_ERR_CORRUPT = -7      /* checkpoint blob failed its size/magic/CRC check */
+};
+
+typedef struct pd_ctx pd_ctx;
+
+/* Device allocator hooks (for example PyTorch's caching allocator).  alloc
+   returns device memory of at least `bytes` bytes or NULL; free releases it. */
+typedef void* (*pd_alloc_fn)(size_t bytes, void* user);
+typedef void (*pd_free_fn)(void* ptr, void* user);
+
+typedef struct {
+  double bulk_modulus;    /* K [Pa]; Poisson ratio is 1/4 in bond-based PD (Sec. 3.1.1) */
+  double density;         /* rho [kg/m^3] */
+  double fracture_energy; /* G_c [J/m^2], sets the critical stretch (Sec. 3.1.1) */
+} pd_material;
+
+typedef struct {
+  int32_t n_grains;
+  const int64_t* node_begin; /* [n_grains+1]: grain g owns nodes [node_begin[g], node_begin[g+1]) */
+  const int32_t* material;   /* [n_grains] index into the material table */
+  const double* h;           /* [n_grains] lattice spacing > 0 */
+  const double* origin;      /* (3, n_grains) SoA lattice origin */
+} pd_grains;
+
+typedef struct {
+  int64_t n_nodes;
+  const double* X;      /* (3,N) reference positions; must equal origin + h*ijk to 1e-9 h */
+  const int32_t* ijk;   /* (3,N) grain-local lattice indices in [0, 1023] */
+  const double* u0;     /* (3,N) initial displacement, or NULL for zero */
+  const double* v0;     /* (3,N) initial velocity, or NULL for zero */
+  const uint8_t* fixed; /* [N] nonzero = node keeps its displacement and has v = a = 0; or NULL */
+} pd_mesh;
+
+enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 */
+       PD_FLAG_ABS_STRETCH = 2    /* break on |s| > s0 instead of s > s0 */ };
+
+typedef struct {
+  int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with
+                              0 < |d ijk|^2 <= m^2 (1 <= m <= 6) */
+  int32_t flags;           /* PD_FLAG_* */
+  double contact_radius;   /* R_c [m] (Sec. 3.2) */
+  double contact_horizon;  /* eps in K_n = 18 k / (pi eps^5) [m] */
+  double skin;             /* Verlet skin [m]: candidates are other-grain nodes within R_c + skin */
+  int32_t rebuild_every;   /* candidate rebuild cadence in steps (>= 1) */
+  int32_t candidate_capacity_per_node; /* capacity of the candidate list, per node (0 = 16) */
+  double dt;               /* time step [s] */
+  double gravity[3];       /* body force per unit mass [m/s^2] */
+} pd_params;
+
+enum { PD_WALL_FIXED = 0, PD_WALL_VELOCITY = 1, PD_WALL_SERVO = 2 };
+
+typedef struct {
+  double normal[3];      /* unit normal pointing into the domain */
+  double offset;         /* wall plane at t = 0: n . p = offset */
+  double velocity;       /* PD_WALL_VELOCITY: offset(t) = offset + velocity * t */
+  double lo[3], hi[3];   /* patch: node acted on only if lo <= p <= hi componentwise */
+  int32_t mode;          /* PD_WALL_* */
+  double target_stress;  /* PD_WALL_SERVO: target of sigma = -(P . n) / area [Pa] */
+  double servo_gain;     /* PD_WALL_SERVO: d(offset)/dt = gain * (target - sigma) [m/s/Pa] */
+  double area;           /* area that turns the reaction force into a stress [m^2] */
+} pd_wall;
+
+enum { PD_CUT_NOTCH = 0, PD_CUT_CAVITY_ENDPOINT = 1, PD_CUT_CAVITY_CHORD = 2 };
+
+/* Bond removal (Sec. 6.3).  Coordinates are half-lattice integers of the grain:
+   node ijk sits at (2i, 2j, 2k).  |lo|, |hi| >= 2^50 mean "unbounded".
+   NOTCH: remove the bond P1->P2 when the plane a X + b Y + c Z + d = 0 cuts it
+          at 0 < t < 1 and the crossing point lies in [lo, hi] (Sec. 6.3.1).
+   CAVITY_ENDPOINT: remove when an endpoint is strictly inside the sphere (Sec. 6.3.2).
+   CAVITY_CHORD: remove when the segment passes strictly inside the sphere. */
+typedef struct {
+  int32_t kind;
+  int32_t grain;
+  int64_t plane[4];
+  int64_t lo[3], hi[3];
+  int64_t center[3];
+  int64_t radius2;
+} pd_cut;
+
+typedef enum {
+  PD_DISPLACEMENT = 0,    /* (3,N) f64 u */
+  PD_VELOCITY = 1,        /* (3,N) f64 v */
+  PD_ACCEL = 2,           /* (3,N) f64 a = F/rho + g (0 on fixed nodes) */
+  PD_FORCE_DENSITY = 3,   /* (3,N) f64 F = F_intra + F_inter + F_wall at the current u */
+  PD_DAMAGE = 4,          /* [N] f64 1 - intact/initial (0 where initial = 0) */
+  PD_INTACT_COUNT = 5,    /* [N] i32 intact bonds */
+  PD_INITIAL_COUNT = 6,   /* [N] i32 bonds after cuts, before any breaking */
+  PD_BOND_ROWPTR = 7,     /* [N+1] i64 CSR row pointer, rows in node order */
+  PD_BOND_COL = 8,        /* [nnz] i32 CSR columns, ascending in each row */
+  PD_BOND_BROKEN = 9,     /* [nnz] u8 1 = broken, aligned with PD_BOND_COL */
+  PD_CONTACT_ROWPTR = 10, /* [N+1] i64 candidate rows of the last rebuild */
+  PD_CONTACT_COL = 11,    /* [n_candidates] i32 candidate columns, ascending */
+  PD_WALL_FORCE = 12,     /* [n_walls][3] f64 reaction P_w = -sum_i V_i F_wall,i (last evaluation) */
+  PD_WALL_OFFSET = 13,    /* [n_walls] f64 wall offset used by the last evaluation */
+  PD_ENERGY = 14,         /* [4] f64 kinetic, elastic (bonds), contact, gravity potential [J] */
+  PD_STEP = 15            /* [1] i64 completed steps */
+} pd_field;
+
+/* Create a context: validates and copies the problem to the device.
+   materials[n_mat]; walls[n_walls] (may be NULL when 0); stream = hipStream_t or NULL.
+   alloc/free may be NULL (then hipMalloc/hipFree are used). */
+pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
+                  const pd_material* materials, int32_t n_mat, const pd_params* params,
+                  const pd_wall* walls, int32_t n_walls, pd_alloc_fn alloc, pd_free_fn free_fn,
+                  void* alloc_user, void* stream);
+
+/* Build the bond family (Sec. 3.1, inclusive integer horizon shell) minus the cuts,
+   the first contact candidate list and the initial force F^0 / acceleration a^0.
+   cuts may be NULL when n_cuts == 0. */
+pd_status pd_build_bonds(pd_ctx* ctx, const pd_cut* cuts, int32_t n_cuts);
+
+/* Advance n_steps velocity-Verlet steps.  Enqueues on the context stream and
+   waits for the device status word at the end; PD_ERR_UNSTABLE reports a flag
+   raised during these steps (the state is the last completed step). */
+pd_status pd_step(pd_ctx* ctx, int64_t n_steps);
+
+/* Bytes a field occupies (for sizing dst). */
+pd_status pd_field_bytes(pd_ctx* ctx, pd_field field, int64_t* bytes);
+
+/* Copy a field into dst (host memory, or device memory when dst_on_device != 0).
+   dst_bytes smaller than the field gives PD_ERR_INVALID.  Synchronises the stream. */
+pd_status pd_get(pd_ctx* ctx, pd_field field, void* dst, int64_t dst_bytes, int32_t dst_on_device);
+
+/* Replace wall w (for example to change a servo target between steps). */
+pd_status pd_set_wall(pd_ctx* ctx, int32_t w, const pd_wall* wall);
+
+/* Checkpoint: blob = header, u, v, a, broken bits, intact counts, walls, step
+   counters, CRC32.  With blob == NULL, *bytes receives the size needed. */
+pd_status pd_get_state(pd_ctx* ctx, void* blob, int64_t* bytes);
+/* Restore a checkpoint taken from a context built from the same inputs. */
+pd_status pd_set_state(pd_ctx* ctx, const void* blob, int64_t bytes);
+
+/* Counts: n_nodes, nnz (real bonds), padded slots, candidates, steps. */
+pd_status pd_info(pd_ctx* ctx, int64_t* out5);
+
+void pd_destroy(pd_ctx* ctx);
+const char* pd_last_error(const pd_ctx* ctx);
+const char* pd_status_string(pd_status status);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

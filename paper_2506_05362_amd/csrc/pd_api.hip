@@ -1,0 +1,950 @@
+// Host runtime of the peridynamic grain-aggregate library: validation, device
+// buffers, the step sequence and the C ABI declared in pd.h.
+
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pd_internal.h"
+
+using namespace pdk;
+
+namespace {
+
+constexpr double kPi = 3.14159265358979323846;
+constexpr uint64_t kMagic = 0x3130536b4450554dull;  // checkpoint magic
+constexpr int64_t kUnboundedCut = ((int64_t)1) << 50;
+
+}  // namespace
+
+struct pd_ctx {
+  // configuration
+  int64_t n = 0;
+  int32_t n_grains = 0, n_mat = 0, n_walls = 0;
+  int32_t m = 3, flags = 0, rebuild_every = 1, cap_per_node = 16;
+  double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0};
+  hipStream_t stream = nullptr;
+  pd_alloc_fn alloc = nullptr;
+  pd_free_fn free_fn = nullptr;
+  void* user = nullptr;
+  std::string err;
+  int built = 0;
+  int64_t step = 0;
+  int cur = 0;  // u4[cur] holds u_n, u4[cur^1] holds the drift to u_{n+1}
+  // host copies needed by the bond build
+  std::vector<int64_t> grain_begin;
+  std::vector<int32_t> ijk_h;  // (3,N)
+  std::vector<GrainC> grains_h;
+  std::vector<WallDev> walls_h;
+  std::vector<void*> owned;
+  // device state
+  double4* u4[2] = {nullptr, nullptr};
+  double *v = nullptr, *a = nullptr, *X = nullptr, *F = nullptr;
+  uint8_t* fixed = nullptr;
+  GrainC* grains = nullptr;
+  double* inv_len = nullptr;
+  double* Kn = nullptr;
+  WallDev* walls = nullptr;
+  double* wall_partial = nullptr;
+  int64_t* step_d = nullptr;
+  uint32_t* status = nullptr;
+  // bonds
+  int64_t nslices = 0, padded = 0, nnz = 0;
+  int32_t* rowlen = nullptr;
+  int64_t* slice_off = nullptr;
+  int32_t* colE = nullptr;
+  uint64_t* maskE = nullptr;
+  int32_t* intact = nullptr;
+  // contact
+  uint32_t T = 0;
+  int64_t capacity = 0;
+  int32_t *cellc = nullptr, *bucket_count = nullptr, *bucket_start = nullptr,
+          *bucket_fill = nullptr, *sorted = nullptr, *cand_ptr = nullptr, *cand = nullptr;
+  uint32_t* cellh = nullptr;
+  double* u_build = nullptr;
+  int32_t* scan32 = nullptr;
+  int64_t* scan64 = nullptr;
+  double* energy_partial = nullptr;
+  double* energy_out = nullptr;
+};
+
+namespace {
+
+pd_status fail(pd_ctx* c, pd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (c) c->err = buf;
+  return st;
+}
+
+#define HIPCHK(ctx, call)                                                                      \
+  do {                                                                                         \
+    hipError_t e_ = (call);                                                                    \
+    if (e_ != hipSuccess)                                                                      \
+      return fail((ctx), PD_ERR_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorName(e_),      \
+                  __FILE__, __LINE__);                                                         \
+  } while (0)
+
+void* dev_alloc(pd_ctx* c, size_t bytes) {
+  if (bytes == 0) bytes = 8;
+  bytes = (bytes + 255) & ~size_t(255);
+  void* p = nullptr;
+  if (c->alloc) {
+    p = c->alloc(bytes, c->user);
+  } else if (hipMalloc(&p, bytes) != hipSuccess) {
+    p = nullptr;
+  }
+  if (p) c->owned.push_back(p);
+  return p;
+}
+
+void dev_free(pd_ctx* c, void* p) {
+  if (!p) return;
+  auto it = std::find(c->owned.begin(), c->owned.end(), p);
+  if (it != c->owned.end()) c->owned.erase(it);
+  if (c->free_fn)
+    c->free_fn(p, c->user);
+  else
+    (void)hipFree(p);
+}
+
+template <typename T>
+pd_status alloc_n(pd_ctx* c, T** out, int64_t count, const char* what) {
+  *out = static_cast<T*>(dev_alloc(c, sizeof(T) * (size_t)(count > 0 ? count : 1)));
+  if (!*out) return fail(c, PD_ERR_OOM, "device allocation of %s (%lld elements) failed", what, (long long)count);
+  return PD_OK;
+}
+
+#define TRY(expr)                 \
+  do {                            \
+    pd_status s_ = (expr);        \
+    if (s_ != PD_OK) return s_;   \
+  } while (0)
+
+void micro_constants(double K, double Gc, double delta, int flags, double* c, double* s0) {
+  if (flags & PD_FLAG_TABLE_LITERAL) {
+    const double nu = 0.25, E = 3.0 * K * (1.0 - 2.0 * nu);
+    *c = 12.0 * E / (kPi * delta * delta * delta * delta * (1.0 - nu));
+    *s0 = sqrt(5.0 * kPi * Gc / (12.0 * E * delta));
+  } else {
+    // energy-consistent 3-D constants: pi c delta^4 / 4 = 9K/2 and pi c s0^2 delta^5 / 10 = G_c
+    *c = 18.0 * K / (kPi * delta * delta * delta * delta);
+    *s0 = sqrt(5.0 * Gc / (9.0 * K * delta));
+  }
+}
+
+WallDev to_dev(const pd_wall& w, int64_t next_step, double dt) {
+  WallDev d{};
+  for (int q = 0; q < 3; ++q) {
+    d.n[q] = w.normal[q];
+    d.lo[q] = w.lo[q];
+    d.hi[q] = w.hi[q];
+  }
+  d.vel = w.velocity;
+  d.off = w.offset;
+  d.off_used = w.offset;
+  d.off0 = w.mode == PD_WALL_VELOCITY ? w.offset - w.velocity * ((double)next_step * dt) : w.offset;
+  d.target = w.target_stress;
+  d.gain = w.servo_gain;
+  d.area = w.area;
+  d.mode = w.mode;
+  return d;
+}
+
+pd_status check_wall(pd_ctx* c, const pd_wall& w, int k) {
+  const double nn = w.normal[0] * w.normal[0] + w.normal[1] * w.normal[1] + w.normal[2] * w.normal[2];
+  if (!(fabs(nn - 1.0) < 1e-12)) return fail(c, PD_ERR_INVALID, "wall %d: normal is not a unit vector", k);
+  if (w.mode < 0 || w.mode > 2) return fail(c, PD_ERR_INVALID, "wall %d: mode %d", k, w.mode);
+  if (!(w.area > 0)) return fail(c, PD_ERR_INVALID, "wall %d: area must be > 0", k);
+  if (!isfinite(w.offset)) return fail(c, PD_ERR_INVALID, "wall %d: offset not finite", k);
+  return PD_OK;
+}
+
+StepArgs step_args(pd_ctx* c) {
+  StepArgs A{};
+  A.ucur = c->u4[c->cur];
+  A.unext = c->u4[c->cur ^ 1];
+  A.v = c->v;
+  A.a = c->a;
+  A.Fout = c->F;
+  A.fixed = c->fixed;
+  A.grains = c->grains;
+  A.inv_len = c->inv_len;
+  A.slice_off = c->slice_off;
+  A.rowlen = c->rowlen;
+  A.colE = c->colE;
+  A.maskE = c->maskE;
+  A.intact = c->intact;
+  A.cand_ptr = c->cand_ptr;
+  A.cand = c->cand;
+  A.cand_capacity = c->capacity;
+  A.X = c->X;
+  A.Kn = c->Kn;
+  A.walls = c->walls;
+  A.wall_partial = c->wall_partial;
+  A.status = c->status;
+  A.n = c->n;
+  A.nslices = c->nslices;
+  A.n_walls = c->n_walls;
+  A.n_mat = c->n_mat;
+  A.Rc = c->Rc;
+  A.Rc2 = c->Rc * c->Rc;
+  A.dt = c->dt;
+  for (int q = 0; q < 3; ++q) A.g[q] = c->g[q];
+  A.abs_stretch = (c->flags & PD_FLAG_ABS_STRETCH) ? 1 : 0;
+  return A;
+}
+
+ContactArgs contact_args(pd_ctx* c, int buf) {
+  ContactArgs C{};
+  C.u = c->u4[buf];
+  C.X = c->X;
+  C.cellc = c->cellc;
+  C.cellh = c->cellh;
+  C.bucket_count = c->bucket_count;
+  C.bucket_start = c->bucket_start;
+  C.bucket_fill = c->bucket_fill;
+  C.sorted = c->sorted;
+  C.cand_count = c->cand_ptr;
+  C.cand = c->cand;
+  C.u_build = c->u_build;
+  C.scan_scratch = c->scan32;
+  C.status = c->status;
+  C.n = c->n;
+  C.T = c->T;
+  C.capacity = c->capacity;
+  const double cut = c->Rc + c->skin;
+  C.inv_cell = 1.0 / (cut * 1.01);
+  C.cut2 = cut * cut;
+  C.skin_half2 = 0.25 * c->skin * c->skin;
+  return C;
+}
+
+// one step on the device: rebuild on cadence, force+Verlet, walls
+pd_status enqueue_step(pd_ctx* c, int64_t s) {
+  const int nxt = c->cur ^ 1;
+  if (s % c->rebuild_every == 0) {
+    ContactArgs C = contact_args(c, nxt);
+    HIPCHK(c, launch_contact_rebuild(C, 1, c->stream));
+  }
+  c->cur = nxt;  // the drifted positions are the current ones now
+  StepArgs A = step_args(c);
+  HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+  HIPCHK(c, launch_wall_finalize(c->walls, c->wall_partial, step_grid_blocks(c->nslices), c->n_walls,
+                                 c->step_d, 1, c->dt, c->stream));
+  return PD_OK;
+}
+
+pd_status read_status(pd_ctx* c, uint32_t* st) {
+  HIPCHK(c, hipMemcpyAsync(st, c->status, sizeof(uint32_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return PD_OK;
+}
+
+pd_status report_status(pd_ctx* c) {
+  uint32_t st = 0;
+  TRY(read_status(c, &st));
+  if (!st) return PD_OK;
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  std::string why;
+  if (st & ST_NAN) why += " non-finite force;";
+  if (st & ST_PENETRATION) why += " node at or beyond -R_c behind a wall;";
+  if (st & ST_SKIN) why += " displacement since the last candidate rebuild exceeded skin/2;";
+  if (st & ST_CAND_OVERFLOW) why += " contact candidate capacity exceeded;";
+  return fail(c, PD_ERR_UNSTABLE, "instability flagged:%s", why.c_str());
+}
+
+uint32_t crc32_update(uint32_t crc, const void* data, size_t n) {
+  static uint32_t table[256];
+  static bool init = false;
+  if (!init) {
+    for (uint32_t i = 0; i < 256; ++i) {
+      uint32_t r = i;
+      for (int k = 0; k < 8; ++k) r = (r & 1) ? 0xEDB88320u ^ (r >> 1) : r >> 1;
+      table[i] = r;
+    }
+    init = true;
+  }
+  const uint8_t* p = static_cast<const uint8_t*>(data);
+  crc = ~crc;
+  for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xff] ^ (crc >> 8);
+  return ~crc;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+
+extern "C" {
+
+const char* pd_status_string(pd_status s) {
+  switch (s) {
+    case PD_OK: return "ok";
+    case PD_ERR_INVALID: return "invalid argument";
+    case PD_ERR_STATE: return "call out of order";
+    case PD_ERR_OOM: return "out of device memory";
+    case PD_ERR_HIP: return "HIP runtime error";
+    case PD_ERR_UNSTABLE: return "instability flagged";
+    case PD_ERR_UNSUPPORTED: return "unsupported";
+    case PD_ERR_CORRUPT: return "corrupt checkpoint";
+    default: return "unknown status";
+  }
+}
+
+const char* pd_last_error(const pd_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
+                  const pd_material* materials, int32_t n_mat, const pd_params* params,
+                  const pd_wall* walls, int32_t n_walls, pd_alloc_fn alloc, pd_free_fn free_fn,
+                  void* alloc_user, void* stream) {
+  if (!out) return PD_ERR_INVALID;
+  *out = nullptr;
+  if (!grains || !mesh || !materials || !params) return PD_ERR_INVALID;
+  if ((alloc == nullptr) != (free_fn == nullptr)) return PD_ERR_INVALID;
+  pd_ctx* c = new (std::nothrow) pd_ctx();
+  if (!c) return PD_ERR_OOM;
+  *out = c;
+  c->alloc = alloc;
+  c->free_fn = free_fn;
+  c->user = alloc_user;
+  c->stream = static_cast<hipStream_t>(stream);
+
+  const int64_t N = mesh->n_nodes;
+  const int32_t G = grains->n_grains;
+  if (N < 0 || N > INT32_MAX - 64) return fail(c, PD_ERR_INVALID, "n_nodes %lld out of range", (long long)N);
+  if (G < 1) return fail(c, PD_ERR_INVALID, "n_grains must be >= 1");
+  if (!grains->node_begin || !grains->material || !grains->h || !grains->origin)
+    return fail(c, PD_ERR_INVALID, "grain arrays must not be NULL");
+  if (N > 0 && (!mesh->X || !mesh->ijk)) return fail(c, PD_ERR_INVALID, "mesh X/ijk must not be NULL");
+  if (n_mat < 1) return fail(c, PD_ERR_INVALID, "n_mat must be >= 1");
+  if (n_walls < 0 || n_walls > kMaxWalls) return fail(c, PD_ERR_INVALID, "n_walls must be in [0, %d]", kMaxWalls);
+  if (n_walls > 0 && !walls) return fail(c, PD_ERR_INVALID, "walls must not be NULL");
+  if (grains->node_begin[0] != 0 || grains->node_begin[G] != N)
+    return fail(c, PD_ERR_INVALID, "node_begin must start at 0 and end at n_nodes");
+  for (int32_t g = 0; g < G; ++g) {
+    if (grains->node_begin[g + 1] < grains->node_begin[g])
+      return fail(c, PD_ERR_INVALID, "node_begin not monotone at grain %d", g);
+    if (!(grains->h[g] > 0)) return fail(c, PD_ERR_INVALID, "grain %d: h must be > 0", g);
+    if (grains->material[g] < 0 || grains->material[g] >= n_mat)
+      return fail(c, PD_ERR_INVALID, "grain %d: material %d out of range", g, grains->material[g]);
+  }
+  for (int32_t k = 0; k < n_mat; ++k) {
+    const pd_material& mt = materials[k];
+    if (!(mt.bulk_modulus > 0 && mt.density > 0 && mt.fracture_energy > 0))
+      return fail(c, PD_ERR_INVALID, "material %d: K, rho and G_c must be > 0", k);
+  }
+  const pd_params& P = *params;
+  if (P.horizon_factor < 1 || P.horizon_factor > kMaxHorizon)
+    return fail(c, PD_ERR_INVALID, "horizon_factor must be in [1, %d]", kMaxHorizon);
+  if (!(P.contact_radius > 0) || !(P.contact_horizon > 0) || !(P.skin >= 0))
+    return fail(c, PD_ERR_INVALID, "contact radius/horizon must be > 0 and skin >= 0");
+  if (!(P.dt > 0)) return fail(c, PD_ERR_INVALID, "dt must be > 0");
+  if (P.rebuild_every < 1) return fail(c, PD_ERR_INVALID, "rebuild_every must be >= 1");
+  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH))
+    return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
+  for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
+
+  c->n = N;
+  c->n_grains = G;
+  c->n_mat = n_mat;
+  c->n_walls = n_walls;
+  c->m = P.horizon_factor;
+  c->flags = P.flags;
+  c->Rc = P.contact_radius;
+  c->eps = P.contact_horizon;
+  c->skin = P.skin;
+  c->dt = P.dt;
+  c->rebuild_every = P.rebuild_every;
+  c->cap_per_node = P.candidate_capacity_per_node > 0 ? P.candidate_capacity_per_node : 16;
+  for (int q = 0; q < 3; ++q) c->g[q] = P.gravity[q];
+  c->grain_begin.assign(grains->node_begin, grains->node_begin + G + 1);
+
+  // lattice indices and the X = origin + h ijk consistency the kernels rely on
+  c->ijk_h.assign(mesh->ijk, mesh->ijk + 3 * N);
+  for (int32_t g = 0; g < G; ++g) {
+    const double h = grains->h[g];
+    for (int64_t i = c->grain_begin[g]; i < c->grain_begin[g + 1]; ++i)
+      for (int q = 0; q < 3; ++q) {
+        const int32_t v = c->ijk_h[q * N + i];
+        if (v < 0 || v > 1023) return fail(c, PD_ERR_INVALID, "node %lld: ijk out of [0, 1023]", (long long)i);
+        const double x = grains->origin[q * G + g] + h * (double)v;
+        if (!(fabs(mesh->X[q * N + i] - x) <= 1e-9 * h))
+          return fail(c, PD_ERR_INVALID, "node %lld: X does not match origin + h*ijk", (long long)i);
+      }
+  }
+
+  // per-grain constants
+  c->grains_h.resize(G);
+  for (int32_t g = 0; g < G; ++g) {
+    const pd_material& mt = materials[grains->material[g]];
+    const double h = grains->h[g], delta = P.horizon_factor * h;
+    double cc, s0;
+    micro_constants(mt.bulk_modulus, mt.fracture_energy, delta, P.flags, &cc, &s0);
+    GrainC& gc = c->grains_h[g];
+    gc.V = h * h * h;
+    gc.cV = cc * gc.V;
+    gc.thr = h * h * (1.0 + s0) * (1.0 + s0);
+    gc.thr_lo = (P.flags & PD_FLAG_ABS_STRETCH) ? h * h * (1.0 - s0) * (1.0 - s0) : -1.0;
+    gc.h = h;
+    gc.inv_h = 1.0 / h;
+    gc.rho = mt.density;
+    for (int q = 0; q < 3; ++q) gc.origin[q] = grains->origin[q * G + g];
+    gc.mat = grains->material[g];
+  }
+  std::vector<double> kn((size_t)n_mat * n_mat);
+  for (int32_t a = 0; a < n_mat; ++a)
+    for (int32_t b = 0; b < n_mat; ++b) {
+      const double ka = materials[a].bulk_modulus, kb = materials[b].bulk_modulus;
+      const double keff = 2.0 * ka * kb / (ka + kb);
+      kn[(size_t)a * n_mat + b] = 18.0 * keff / (kPi * pow(P.contact_horizon, 5));
+    }
+  std::vector<double> inv_len(kMaxD2 + 1, 0.0);
+  for (int d2 = 1; d2 <= kMaxD2; ++d2) inv_len[d2] = 1.0 / sqrt((double)d2);
+  c->walls_h.resize(n_walls);
+  for (int32_t w = 0; w < n_walls; ++w) c->walls_h[w] = to_dev(walls[w], 0, P.dt);
+
+  // device buffers
+  TRY(alloc_n(c, &c->u4[0], N, "u"));
+  TRY(alloc_n(c, &c->u4[1], N, "u'"));
+  TRY(alloc_n(c, &c->v, 3 * N, "v"));
+  TRY(alloc_n(c, &c->a, 3 * N, "a"));
+  TRY(alloc_n(c, &c->X, 3 * N, "X"));
+  TRY(alloc_n(c, &c->grains, G, "grain constants"));
+  TRY(alloc_n(c, &c->inv_len, kMaxD2 + 1, "inverse lengths"));
+  TRY(alloc_n(c, &c->Kn, (int64_t)n_mat * n_mat, "K_n"));
+  TRY(alloc_n(c, &c->walls, kMaxWalls, "walls"));
+  TRY(alloc_n(c, &c->step_d, 1, "step"));
+  TRY(alloc_n(c, &c->status, 1, "status"));
+  if (mesh->fixed) TRY(alloc_n(c, &c->fixed, N, "fixed"));
+  hipStream_t s = c->stream;
+  HIPCHK(c, hipMemcpyAsync(c->X, mesh->X, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->grains, c->grains_h.data(), sizeof(GrainC) * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->inv_len, inv_len.data(), sizeof(double) * inv_len.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->Kn, kn.data(), sizeof(double) * kn.size(), hipMemcpyHostToDevice, s));
+  if (n_walls)
+    HIPCHK(c, hipMemcpyAsync(c->walls, c->walls_h.data(), sizeof(WallDev) * n_walls, hipMemcpyHostToDevice, s));
+  if (mesh->fixed) HIPCHK(c, hipMemcpyAsync(c->fixed, mesh->fixed, (size_t)N, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemsetAsync(c->step_d, 0, sizeof(int64_t), s));
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), s));
+  if (mesh->v0)
+    HIPCHK(c, hipMemcpyAsync(c->v, mesh->v0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+  else
+    HIPCHK(c, hipMemsetAsync(c->v, 0, sizeof(double) * 3 * N, s));
+  HIPCHK(c, hipMemsetAsync(c->a, 0, sizeof(double) * 3 * N, s));
+  // packed u buffers: (u0, ijk | grain << 32)
+  {
+    double* u0d;
+    int32_t* ijkd;
+    int64_t* gofd;
+    TRY(alloc_n(c, &u0d, 3 * N, "u0 staging"));
+    TRY(alloc_n(c, &ijkd, 3 * N, "ijk staging"));
+    TRY(alloc_n(c, &gofd, N, "grain staging"));
+    std::vector<int64_t> gof((size_t)N);
+    for (int32_t g = 0; g < G; ++g)
+      for (int64_t i = c->grain_begin[g]; i < c->grain_begin[g + 1]; ++i) gof[(size_t)i] = g;
+    if (mesh->u0)
+      HIPCHK(c, hipMemcpyAsync(u0d, mesh->u0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+    else
+      HIPCHK(c, hipMemsetAsync(u0d, 0, sizeof(double) * 3 * N, s));
+    HIPCHK(c, hipMemcpyAsync(ijkd, mesh->ijk, sizeof(int32_t) * 3 * N, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(gofd, gof.data(), sizeof(int64_t) * N, hipMemcpyHostToDevice, s));
+    HIPCHK(c, launch_fill_u4(c->u4[0], u0d, ijkd, gofd, N, s));
+    HIPCHK(c, hipMemcpyAsync(c->u4[1], c->u4[0], sizeof(double4) * N, hipMemcpyDeviceToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    dev_free(c, u0d);
+    dev_free(c, ijkd);
+    dev_free(c, gofd);
+  }
+  return PD_OK;
+}
+
+pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
+  if (!c) return PD_ERR_INVALID;
+  if (c->built) return fail(c, PD_ERR_STATE, "bonds already built");
+  if (c->grains_h.empty()) return fail(c, PD_ERR_STATE, "context not initialised");
+  if (n_cuts < 0 || (n_cuts > 0 && !cuts)) return fail(c, PD_ERR_INVALID, "bad cut array");
+  const int64_t N = c->n;
+  const int32_t G = c->n_grains;
+  hipStream_t s = c->stream;
+
+  // cuts grouped by grain
+  std::vector<CutDev> cd;
+  std::vector<int32_t> cut_begin(G + 1, 0);
+  for (int32_t k = 0; k < n_cuts; ++k) {
+    if (cuts[k].kind < 0 || cuts[k].kind > 2) return fail(c, PD_ERR_INVALID, "cut %d: kind %d", k, cuts[k].kind);
+    if (cuts[k].grain < 0 || cuts[k].grain >= G) return fail(c, PD_ERR_INVALID, "cut %d: grain out of range", k);
+    if (cuts[k].kind != 0 && cuts[k].radius2 < 0) return fail(c, PD_ERR_INVALID, "cut %d: radius2 < 0", k);
+    for (int q = 0; q < 3; ++q) {
+      const bool lo_b = cuts[k].lo[q] > -kUnboundedCut, hi_b = cuts[k].hi[q] < kUnboundedCut;
+      if ((lo_b && llabs(cuts[k].lo[q]) > (1 << 20)) || (hi_b && llabs(cuts[k].hi[q]) > (1 << 20)) ||
+          llabs(cuts[k].center[q]) > (1 << 20))
+        return fail(c, PD_ERR_INVALID, "cut %d: coordinates beyond +-2^20 half-cells", k);
+    }
+    for (int q = 0; q < 4; ++q)
+      if (llabs(cuts[k].plane[q]) > (1 << 20)) return fail(c, PD_ERR_INVALID, "cut %d: plane coefficient too large", k);
+    cut_begin[cuts[k].grain + 1]++;
+  }
+  for (int32_t g = 0; g < G; ++g) cut_begin[g + 1] += cut_begin[g];
+  cd.resize(n_cuts);
+  {
+    std::vector<int32_t> fill(cut_begin.begin(), cut_begin.end() - 1);
+    for (int32_t k = 0; k < n_cuts; ++k) {
+      const pd_cut& u = cuts[k];
+      CutDev& d = cd[fill[u.grain]++];
+      d.kind = u.kind;
+      d.grain = u.grain;
+      for (int q = 0; q < 4; ++q) d.plane[q] = u.plane[q];
+      for (int q = 0; q < 3; ++q) {
+        d.lo[q] = u.lo[q];
+        d.hi[q] = u.hi[q];
+        d.c[q] = u.center[q];
+      }
+      d.r2 = u.radius2;
+    }
+  }
+
+  // per-grain lattice maps over the bounding box of its indices
+  std::vector<int64_t> gmap_off(G + 1, 0);
+  std::vector<int32_t> gdim(3 * G, 1), glo(3 * G, 0);
+  for (int32_t g = 0; g < G; ++g) {
+    int32_t lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {-1, -1, -1};
+    for (int64_t i = c->grain_begin[g]; i < c->grain_begin[g + 1]; ++i)
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = std::min(lo[q], c->ijk_h[q * N + i]);
+        hi[q] = std::max(hi[q], c->ijk_h[q * N + i]);
+      }
+    int64_t vol = 1;
+    for (int q = 0; q < 3; ++q) {
+      if (hi[q] < lo[q]) {
+        lo[q] = 0;
+        hi[q] = 0;
+      }
+      glo[3 * g + q] = lo[q];
+      gdim[3 * g + q] = hi[q] - lo[q] + 1;
+      vol *= gdim[3 * g + q];
+    }
+    gmap_off[g + 1] = gmap_off[g] + vol;
+  }
+  // lexicographic horizon stencil 0 < |d|^2 <= m^2
+  std::vector<int32_t> stencil;
+  for (int dx = -c->m; dx <= c->m; ++dx)
+    for (int dy = -c->m; dy <= c->m; ++dy)
+      for (int dz = -c->m; dz <= c->m; ++dz) {
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 == 0 || d2 > c->m * c->m) continue;
+        stencil.push_back((dx + 8) | ((dy + 8) << 8) | ((dz + 8) << 16));
+      }
+
+  int64_t *gmap_off_d, *scan_scratch64;
+  int32_t *gdim_d, *glo_d, *gmap_d, *cut_begin_d, *stencil_d;
+  CutDev* cuts_d;
+  TRY(alloc_n(c, &gmap_off_d, G + 1, "grain map offsets"));
+  TRY(alloc_n(c, &gdim_d, 3 * G, "grain map dims"));
+  TRY(alloc_n(c, &glo_d, 3 * G, "grain map origin"));
+  TRY(alloc_n(c, &gmap_d, gmap_off[G], "grain maps"));
+  TRY(alloc_n(c, &cut_begin_d, G + 1, "cut offsets"));
+  TRY(alloc_n(c, &stencil_d, (int64_t)stencil.size(), "stencil"));
+  TRY(alloc_n(c, &cuts_d, std::max<int64_t>(n_cuts, 1), "cuts"));
+  c->nslices = (N + kWave - 1) / kWave;
+  TRY(alloc_n(c, &c->rowlen, N, "row lengths"));
+  TRY(alloc_n(c, &c->slice_off, c->nslices + 1, "slice offsets"));
+  TRY(alloc_n(c, &c->intact, N, "intact counts"));
+  TRY(alloc_n(c, &scan_scratch64, scan_scratch_elems(c->nslices + 1), "scan scratch"));
+  HIPCHK(c, hipMemcpyAsync(gmap_off_d, gmap_off.data(), sizeof(int64_t) * (G + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(gdim_d, gdim.data(), sizeof(int32_t) * 3 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(glo_d, glo.data(), sizeof(int32_t) * 3 * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(cut_begin_d, cut_begin.data(), sizeof(int32_t) * (G + 1), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(stencil_d, stencil.data(), sizeof(int32_t) * stencil.size(), hipMemcpyHostToDevice, s));
+  if (n_cuts) HIPCHK(c, hipMemcpyAsync(cuts_d, cd.data(), sizeof(CutDev) * n_cuts, hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_fill_i32(gmap_d, -1, gmap_off[G], s));
+
+  BuildArgs B{};
+  B.u = c->u4[0];
+  B.gmap_off = gmap_off_d;
+  B.gmap_dim = gdim_d;
+  B.gmap_lo = glo_d;
+  B.gmap = gmap_d;
+  B.cuts = cuts_d;
+  B.cut_begin = cut_begin_d;
+  B.stencil = stencil_d;
+  B.n_stencil = (int32_t)stencil.size();
+  B.n = N;
+  B.rowlen = c->rowlen;
+  B.slice_off = c->slice_off;
+  B.nslices = c->nslices;
+  HIPCHK(c, launch_map_fill(B, s));
+  HIPCHK(c, launch_bond_count(B, s));
+  HIPCHK(c, launch_slice_width(B, s));
+  HIPCHK(c, scan_i64(c->slice_off, c->slice_off, c->nslices, scan_scratch64, s));
+  HIPCHK(c, hipMemcpyAsync(&c->padded, c->slice_off + c->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  TRY(alloc_n(c, &c->colE, c->padded, "bond columns"));
+  TRY(alloc_n(c, &c->maskE, c->padded / kWave, "broken masks"));
+  B.colE = c->colE;
+  B.maskE = c->maskE;
+  HIPCHK(c, launch_bond_fill(B, s));
+  HIPCHK(c, hipMemcpyAsync(c->intact, c->rowlen, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
+  {
+    std::vector<int32_t> rl((size_t)N);
+    HIPCHK(c, hipMemcpyAsync(rl.data(), c->rowlen, sizeof(int32_t) * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    int64_t nnz = 0;
+    for (int32_t x : rl) nnz += x;
+    c->nnz = nnz;
+  }
+  dev_free(c, gmap_off_d);
+  dev_free(c, gdim_d);
+  dev_free(c, glo_d);
+  dev_free(c, gmap_d);
+  dev_free(c, cut_begin_d);
+  dev_free(c, stencil_d);
+  dev_free(c, cuts_d);
+  dev_free(c, scan_scratch64);
+
+  // contact structures
+  uint32_t T = 1024;
+  while ((int64_t)T < 2 * N) T <<= 1;
+  c->T = T;
+  c->capacity = std::max<int64_t>((int64_t)c->cap_per_node * N, 1 << 16);
+  TRY(alloc_n(c, &c->cellc, 3 * N, "cell coordinates"));
+  TRY(alloc_n(c, &c->cellh, N, "cell hashes"));
+  TRY(alloc_n(c, &c->bucket_count, T, "bucket counts"));
+  TRY(alloc_n(c, &c->bucket_start, (int64_t)T + 1, "bucket starts"));
+  TRY(alloc_n(c, &c->bucket_fill, T, "bucket fill"));
+  TRY(alloc_n(c, &c->sorted, N, "binned nodes"));
+  TRY(alloc_n(c, &c->cand_ptr, N + 1, "candidate rows"));
+  TRY(alloc_n(c, &c->cand, c->capacity, "candidates"));
+  TRY(alloc_n(c, &c->u_build, 3 * N, "positions at rebuild"));
+  TRY(alloc_n(c, &c->scan32, scan_scratch_elems(std::max<int64_t>(T, N)), "scan scratch"));
+  const int32_t nblocks = step_grid_blocks(c->nslices);
+  TRY(alloc_n(c, &c->wall_partial, (int64_t)std::max(nblocks, 1) * 3 * std::max(c->n_walls, 1), "wall partials"));
+
+  // first candidate list at u0, then F^0 and a^0 (velocity untouched)
+  ContactArgs C = contact_args(c, c->cur);
+  HIPCHK(c, launch_contact_rebuild(C, 0, s));
+  StepArgs A = step_args(c);
+  HIPCHK(c, launch_step(A, MODE_FIRST, s));
+  HIPCHK(c, launch_wall_finalize(c->walls, c->wall_partial, nblocks, c->n_walls, c->step_d, 0, c->dt, s));
+  c->built = 1;
+  c->step = 0;
+  return report_status(c);
+}
+
+pd_status pd_step(pd_ctx* c, int64_t n_steps) {
+  if (!c) return PD_ERR_INVALID;
+  if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  if (n_steps < 0) return fail(c, PD_ERR_INVALID, "n_steps < 0");
+  for (int64_t k = 0; k < n_steps; ++k) {
+    TRY(enqueue_step(c, c->step + 1));
+    c->step += 1;
+  }
+  return report_status(c);
+}
+
+pd_status pd_info(pd_ctx* c, int64_t* out5) {
+  if (!c || !out5) return PD_ERR_INVALID;
+  out5[0] = c->n;
+  out5[1] = c->nnz;
+  out5[2] = c->padded;
+  out5[3] = 0;
+  if (c->built) {
+    int32_t nc = 0;
+    HIPCHK(c, hipMemcpyAsync(&nc, c->cand_ptr + c->n, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    out5[3] = nc;
+  }
+  out5[4] = c->step;
+  return PD_OK;
+}
+
+pd_status pd_field_bytes(pd_ctx* c, pd_field f, int64_t* bytes) {
+  if (!c || !bytes) return PD_ERR_INVALID;
+  const int64_t N = c->n;
+  switch (f) {
+    case PD_DISPLACEMENT: case PD_VELOCITY: case PD_ACCEL: case PD_FORCE_DENSITY:
+      *bytes = 24 * N; return PD_OK;
+    case PD_DAMAGE: *bytes = 8 * N; return PD_OK;
+    case PD_INTACT_COUNT: case PD_INITIAL_COUNT: *bytes = 4 * N; return PD_OK;
+    case PD_BOND_ROWPTR: case PD_CONTACT_ROWPTR: *bytes = 8 * (N + 1); return PD_OK;
+    case PD_BOND_COL: *bytes = 4 * c->nnz; return PD_OK;
+    case PD_BOND_BROKEN: *bytes = c->nnz; return PD_OK;
+    case PD_CONTACT_COL: {
+      int64_t info[5];
+      TRY(pd_info(c, info));
+      *bytes = 4 * std::min<int64_t>(info[3], c->capacity);
+      return PD_OK;
+    }
+    case PD_WALL_FORCE: *bytes = 24 * c->n_walls; return PD_OK;
+    case PD_WALL_OFFSET: *bytes = 8 * c->n_walls; return PD_OK;
+    case PD_ENERGY: *bytes = 32; return PD_OK;
+    case PD_STEP: *bytes = 8; return PD_OK;
+  }
+  return fail(c, PD_ERR_INVALID, "unknown field %d", (int)f);
+}
+
+pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t dst_on_device) {
+  if (!c || !dst) return PD_ERR_INVALID;
+  const bool needs_build = !(f == PD_STEP || f == PD_WALL_OFFSET);
+  if (needs_build && !c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  int64_t need = 0;
+  TRY(pd_field_bytes(c, f, &need));
+  if (dst_bytes < need) return fail(c, PD_ERR_INVALID, "dst too small: field needs %lld bytes", (long long)need);
+  const int64_t N = c->n;
+  hipStream_t s = c->stream;
+  std::vector<uint8_t> host((size_t)need);
+  auto deliver = [&](const void* src_host) -> pd_status {
+    if (dst_on_device)
+      HIPCHK(c, hipMemcpyAsync(dst, src_host, (size_t)need, hipMemcpyHostToDevice, s));
+    else
+      memcpy(dst, src_host, (size_t)need);
+    HIPCHK(c, hipStreamSynchronize(s));
+    return PD_OK;
+  };
+  auto soa_from_dev = [&](const double* d) -> pd_status {
+    HIPCHK(c, hipMemcpyAsync(host.data(), d, (size_t)need, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return deliver(host.data());
+  };
+  switch (f) {
+    case PD_DISPLACEMENT: {
+      std::vector<double4> u4((size_t)N);
+      HIPCHK(c, hipMemcpyAsync(u4.data(), c->u4[c->cur], sizeof(double4) * N, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      double* o = reinterpret_cast<double*>(host.data());
+      for (int64_t i = 0; i < N; ++i) {
+        o[i] = u4[i].x;
+        o[N + i] = u4[i].y;
+        o[2 * N + i] = u4[i].z;
+      }
+      return deliver(host.data());
+    }
+    case PD_VELOCITY: return soa_from_dev(c->v);
+    case PD_ACCEL: return soa_from_dev(c->a);
+    case PD_FORCE_DENSITY: {
+      if (!c->F) TRY(alloc_n(c, &c->F, 3 * N, "force output"));
+      StepArgs A = step_args(c);
+      HIPCHK(c, launch_step(A, MODE_FORCE_ONLY, s));
+      return soa_from_dev(c->F);
+    }
+    case PD_DAMAGE: case PD_INTACT_COUNT: case PD_INITIAL_COUNT: {
+      std::vector<int32_t> it((size_t)N), n0((size_t)N);
+      HIPCHK(c, hipMemcpyAsync(it.data(), c->intact, 4 * N, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(n0.data(), c->rowlen, 4 * N, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (f == PD_INTACT_COUNT) return deliver(it.data());
+      if (f == PD_INITIAL_COUNT) return deliver(n0.data());
+      double* o = reinterpret_cast<double*>(host.data());
+      for (int64_t i = 0; i < N; ++i) o[i] = n0[i] > 0 ? 1.0 - (double)it[i] / (double)n0[i] : 0.0;
+      return deliver(host.data());
+    }
+    case PD_BOND_ROWPTR: case PD_BOND_COL: case PD_BOND_BROKEN: {
+      std::vector<int32_t> rl((size_t)N), col((size_t)c->padded);
+      std::vector<int64_t> so((size_t)c->nslices + 1);
+      std::vector<uint64_t> mk((size_t)(c->padded / kWave));
+      HIPCHK(c, hipMemcpyAsync(rl.data(), c->rowlen, 4 * N, hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipMemcpyAsync(so.data(), c->slice_off, 8 * (c->nslices + 1), hipMemcpyDeviceToHost, s));
+      if (f != PD_BOND_ROWPTR) {
+        HIPCHK(c, hipMemcpyAsync(col.data(), c->colE, 4 * c->padded, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipMemcpyAsync(mk.data(), c->maskE, 8 * (c->padded / kWave), hipMemcpyDeviceToHost, s));
+      }
+      HIPCHK(c, hipStreamSynchronize(s));
+      int64_t e = 0;
+      for (int64_t i = 0; i < N; ++i) {
+        const int64_t sl = i / kWave, lane = i % kWave;
+        if (f == PD_BOND_ROWPTR) reinterpret_cast<int64_t*>(host.data())[i] = e;
+        for (int k = 0; k < rl[(size_t)i]; ++k, ++e) {
+          const int64_t slot = so[(size_t)sl] + (int64_t)k * kWave + lane;
+          if (f == PD_BOND_COL) reinterpret_cast<int32_t*>(host.data())[e] = col[(size_t)slot];
+          if (f == PD_BOND_BROKEN)
+            host[(size_t)e] = (uint8_t)((mk[(size_t)(so[(size_t)sl] / kWave + k)] >> lane) & 1ull);
+        }
+      }
+      if (f == PD_BOND_ROWPTR) reinterpret_cast<int64_t*>(host.data())[N] = e;
+      return deliver(host.data());
+    }
+    case PD_CONTACT_ROWPTR: case PD_CONTACT_COL: {
+      std::vector<int32_t> cp((size_t)N + 1);
+      HIPCHK(c, hipMemcpyAsync(cp.data(), c->cand_ptr, 4 * (N + 1), hipMemcpyDeviceToHost, s));
+      HIPCHK(c, hipStreamSynchronize(s));
+      if (f == PD_CONTACT_ROWPTR) {
+        int64_t* o = reinterpret_cast<int64_t*>(host.data());
+        for (int64_t i = 0; i <= N; ++i) o[i] = cp[(size_t)i];
+        return deliver(host.data());
+      }
+      if (need > 0) {
+        HIPCHK(c, hipMemcpyAsync(host.data(), c->cand, (size_t)need, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+      return deliver(host.data());
+    }
+    case PD_WALL_FORCE: case PD_WALL_OFFSET: {
+      std::vector<WallDev> w((size_t)std::max(c->n_walls, 1));
+      if (c->n_walls) {
+        HIPCHK(c, hipMemcpyAsync(w.data(), c->walls, sizeof(WallDev) * c->n_walls, hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+      }
+      double* o = reinterpret_cast<double*>(host.data());
+      for (int32_t k = 0; k < c->n_walls; ++k) {
+        if (f == PD_WALL_FORCE)
+          for (int q = 0; q < 3; ++q) o[3 * k + q] = w[(size_t)k].force[q];
+        else
+          o[k] = c->built ? w[(size_t)k].off_used : w[(size_t)k].off;
+      }
+      return deliver(host.data());
+    }
+    case PD_ENERGY: {
+      const int32_t nb = (int32_t)((N + kBlock - 1) / kBlock);
+      if (!c->energy_partial) {
+        TRY(alloc_n(c, &c->energy_partial, 4 * (int64_t)std::max(nb, 1), "energy partials"));
+        TRY(alloc_n(c, &c->energy_out, 4, "energy"));
+      }
+      StepArgs A = step_args(c);
+      HIPCHK(c, launch_energy(A, c->energy_partial, nb, s));
+      HIPCHK(c, launch_reduce_energy(c->energy_partial, nb, c->energy_out, s));
+      return soa_from_dev(c->energy_out);
+    }
+    case PD_STEP: {
+      memcpy(host.data(), &c->step, 8);
+      return deliver(host.data());
+    }
+  }
+  return fail(c, PD_ERR_INVALID, "unknown field %d", (int)f);
+}
+
+pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
+  if (!c || !wall) return PD_ERR_INVALID;
+  if (w < 0 || w >= c->n_walls) return fail(c, PD_ERR_INVALID, "wall index %d out of range", w);
+  TRY(check_wall(c, *wall, w));
+  WallDev old;
+  HIPCHK(c, hipMemcpyAsync(&old, c->walls + w, sizeof(WallDev), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  WallDev d = to_dev(*wall, c->built ? c->step + 1 : 0, c->dt);
+  d.off_used = old.off_used;
+  for (int q = 0; q < 3; ++q) d.force[q] = old.force[q];
+  HIPCHK(c, hipMemcpyAsync(c->walls + w, &d, sizeof(WallDev), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->walls_h[(size_t)w] = d;
+  return PD_OK;
+}
+
+// checkpoint layout: header[8] (magic, n, padded, n_walls, step, cur, nnz, crc-less size),
+// then u4[cur], u4[cur^1], v, a, maskE, intact, u_build, walls, crc32
+pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
+  if (!c || !bytes) return PD_ERR_INVALID;
+  if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  const int64_t N = c->n;
+  const int64_t words = c->padded / kWave;
+  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 8 * words + 4 * N + 24 * N +
+                       (int64_t)sizeof(WallDev) * c->n_walls;
+  const int64_t total = body + 4;
+  if (!blob) {
+    *bytes = total;
+    return PD_OK;
+  }
+  if (*bytes < total) return fail(c, PD_ERR_INVALID, "checkpoint buffer needs %lld bytes", (long long)total);
+  uint8_t* p = static_cast<uint8_t*>(blob);
+  const int64_t hdr[8] = {(int64_t)kMagic, N, c->padded, c->n_walls, c->step, 0, c->nnz, body};
+  memcpy(p, hdr, sizeof hdr);
+  int64_t o = sizeof hdr;
+  hipStream_t s = c->stream;
+  auto grab = [&](const void* d, int64_t n) -> pd_status {
+    if (n) HIPCHK(c, hipMemcpyAsync(p + o, d, (size_t)n, hipMemcpyDeviceToHost, s));
+    o += n;
+    return PD_OK;
+  };
+  TRY(grab(c->u4[c->cur], 32 * N));
+  TRY(grab(c->u4[c->cur ^ 1], 32 * N));
+  TRY(grab(c->v, 24 * N));
+  TRY(grab(c->a, 24 * N));
+  TRY(grab(c->maskE, 8 * words));
+  TRY(grab(c->intact, 4 * N));
+  TRY(grab(c->u_build, 24 * N));
+  TRY(grab(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));
+  HIPCHK(c, hipStreamSynchronize(s));
+  const uint32_t crc = crc32_update(0, p, (size_t)body);
+  memcpy(p + body, &crc, 4);
+  *bytes = total;
+  return PD_OK;
+}
+
+pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
+  if (!c || !blob) return PD_ERR_INVALID;
+  if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  const uint8_t* p = static_cast<const uint8_t*>(blob);
+  if (bytes < 68) return fail(c, PD_ERR_CORRUPT, "checkpoint too short");
+  int64_t hdr[8];
+  memcpy(hdr, p, sizeof hdr);
+  const int64_t N = c->n, words = c->padded / kWave;
+  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 8 * words + 4 * N + 24 * N +
+                       (int64_t)sizeof(WallDev) * c->n_walls;
+  if (hdr[0] != (int64_t)kMagic || hdr[1] != N || hdr[2] != c->padded || hdr[3] != c->n_walls ||
+      hdr[6] != c->nnz || hdr[7] != body || bytes != body + 4)
+    return fail(c, PD_ERR_CORRUPT, "checkpoint does not match this context");
+  uint32_t crc;
+  memcpy(&crc, p + body, 4);
+  if (crc32_update(0, p, (size_t)body) != crc) return fail(c, PD_ERR_CORRUPT, "checkpoint CRC mismatch");
+  hipStream_t s = c->stream;
+  int64_t o = sizeof hdr;
+  auto put = [&](void* d, int64_t n) -> pd_status {
+    if (n) HIPCHK(c, hipMemcpyAsync(d, p + o, (size_t)n, hipMemcpyHostToDevice, s));
+    o += n;
+    return PD_OK;
+  };
+  c->cur = 0;
+  TRY(put(c->u4[0], 32 * N));
+  TRY(put(c->u4[1], 32 * N));
+  TRY(put(c->v, 24 * N));
+  TRY(put(c->a, 24 * N));
+  TRY(put(c->maskE, 8 * words));
+  TRY(put(c->intact, 4 * N));
+  TRY(put(c->u_build, 24 * N));
+  TRY(put(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));
+  c->step = hdr[4];
+  HIPCHK(c, hipMemcpyAsync(c->step_d, &c->step, 8, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  // the candidate list of the last rebuild, rebuilt from the positions it was made from
+  {
+    double4* tmp;
+    TRY(alloc_n(c, &tmp, N, "rebuild staging"));
+    ContactArgs C = contact_args(c, 0);
+    std::vector<double4> ub((size_t)N);
+    HIPCHK(c, hipMemcpyAsync(ub.data(), c->u4[0], 32 * N, hipMemcpyDeviceToHost, s));
+    std::vector<double> bld((size_t)(3 * N));
+    HIPCHK(c, hipMemcpyAsync(bld.data(), c->u_build, 24 * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int64_t i = 0; i < N; ++i) {
+      ub[(size_t)i].x = bld[(size_t)i];
+      ub[(size_t)i].y = bld[(size_t)(N + i)];
+      ub[(size_t)i].z = bld[(size_t)(2 * N + i)];
+    }
+    HIPCHK(c, hipMemcpyAsync(tmp, ub.data(), 32 * N, hipMemcpyHostToDevice, s));
+    C.u = tmp;
+    HIPCHK(c, launch_contact_rebuild(C, 0, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    dev_free(c, tmp);
+  }
+  return report_status(c);
+}
+
+void pd_destroy(pd_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  std::vector<void*> all = c->owned;
+  for (void* p : all) dev_free(c, p);
+  delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,158 @@
+// Internal declarations shared by the host runtime and the HIP kernels of the
+// peridynamic grain-aggregate library.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "pd.h"
+
+namespace pdk {
+
+constexpr int kWave = 64;           // CDNA wavefront
+constexpr int kBlock = 256;         // 4 waves = 4 SELL slices per workgroup
+constexpr int kSlicesPerBlock = kBlock / kWave;
+constexpr int kMaxWalls = 8;
+constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
+constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
+constexpr int kCellDirs = 27;
+
+// per-grain constants, one 96-byte record
+struct GrainC {
+  double cV;      // c * V (micromodulus times nodal volume of the same grain)
+  double thr;     // h^2 (1 + s0)^2: bond breaks when |y|^2 > thr * |d|^2
+  double thr_lo;  // h^2 (1 - s0)^2 with the |s| reading, else -1
+  double h, inv_h;
+  double V;       // h^3
+  double rho;
+  double origin[3];
+  int32_t mat;
+  int32_t pad;
+};
+
+struct WallDev {
+  double n[3];
+  double off0;      // offset at t = 0
+  double off;       // offset used by the next force evaluation
+  double off_used;  // offset used by the last force evaluation
+  double vel;
+  double lo[3], hi[3];
+  double target, gain, area;
+  double force[3];  // reaction of the last evaluation
+  int32_t mode;
+  int32_t pad;
+};
+
+struct CutDev {
+  int64_t kind, grain, plane[4], lo[3], hi[3], c[3], r2;
+};
+
+// status word bits
+enum : uint32_t {
+  ST_NAN = 1u,
+  ST_PENETRATION = 2u,
+  ST_SKIN = 4u,
+  ST_CAND_OVERFLOW = 8u,
+};
+
+enum ForceMode { MODE_FIRST = 0, MODE_STEP = 1, MODE_FORCE_ONLY = 2 };
+
+// everything the fused step kernel reads
+struct StepArgs {
+  const double4* ucur;  // (x,y,z, packed ijk | grain<<32)
+  double4* unext;
+  double* v;            // SoA
+  double* a;            // SoA
+  double* Fout;         // MODE_FORCE_ONLY output (SoA)
+  const uint8_t* fixed;
+  const GrainC* grains;
+  const double* inv_len;  // 1/sqrt(d2), d2 = 0..kMaxD2
+  const int64_t* slice_off;
+  const int32_t* rowlen;
+  const int32_t* colE;
+  uint64_t* maskE;
+  int32_t* intact;
+  const int32_t* cand_ptr;
+  const int32_t* cand;
+  int64_t cand_capacity;
+  const double* X;      // SoA, contact path only
+  const double* Kn;     // [n_mat * n_mat]
+  WallDev* walls;
+  double* wall_partial;  // [nblocks][n_walls][3]
+  uint32_t* status;
+  int64_t n;
+  int64_t nslices;
+  int32_t n_walls;
+  int32_t n_mat;
+  double Rc, Rc2;
+  double dt;
+  double g[3];
+  int32_t abs_stretch;
+};
+
+struct BuildArgs {
+  const double4* u;
+  const int64_t* gmap_off;   // [G]
+  const int32_t* gmap_dim;   // [3G]
+  const int32_t* gmap_lo;    // [3G]
+  int32_t* gmap;
+  const CutDev* cuts;
+  const int32_t* cut_begin;  // [G+1]
+  const int32_t* stencil;    // [n_stencil] packed (dx+8) | (dy+8)<<8 | (dz+8)<<16, lexicographic
+  int32_t n_stencil;
+  int64_t n;
+  int32_t* rowlen;
+  int64_t* slice_off;
+  int32_t* colE;
+  uint64_t* maskE;
+  int64_t nslices;
+};
+
+struct ContactArgs {
+  const double4* u;
+  const double* X;
+  int32_t* cellc;        // [3N]
+  uint32_t* cellh;       // [N]
+  int32_t* bucket_count;  // [T]
+  int32_t* bucket_start;  // [T+1]
+  int32_t* bucket_fill;   // [T]
+  int32_t* sorted;        // [N]
+  int32_t* cand_count;    // [N+1] (scanned in place to cand_ptr)
+  int32_t* cand;
+  double* u_build;        // SoA
+  int32_t* scan_scratch;  // >= scan_scratch_elems(max(T, N))
+  uint32_t* status;
+  int64_t n;
+  uint32_t T;             // power of two
+  int64_t capacity;
+  double inv_cell;
+  double cut2;            // (R_c + skin)^2
+  double skin_half2;
+};
+
+// ---- launchers (pd_kernels.hip) ----
+hipError_t launch_map_fill(const BuildArgs& b, hipStream_t s);
+hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s);
+hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s);
+hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s);
+hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s);
+hipError_t launch_wall_finalize(WallDev* walls, const double* partial, int32_t nblocks,
+                                int32_t n_walls, int64_t* step, int32_t advance, double dt,
+                                hipStream_t s);
+hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s);
+hipError_t launch_energy(const StepArgs& a, double* partial4, int32_t nblocks, hipStream_t s);
+hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double* out4,
+                                hipStream_t s);
+hipError_t launch_fill_u4(double4* u4, const double* u, const int32_t* ijk, const int64_t* grain_of,
+                          int64_t n, hipStream_t s);
+// exclusive scans with a total in out[n]; scratch >= scan_scratch_elems(n) elements
+int64_t scan_scratch_elems(int64_t n);
+hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s);
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
+int32_t step_grid_blocks(int64_t nslices);
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+
+}  // namespace pdk

@@ -1,0 +1,830 @@
+// HIP kernels (gfx950) of the peridynamic grain-aggregate step.
+//
+// Layout in HBM
+//   u      : two buffers of double4 (x, y, z, w); w carries the node's packed
+//            grain-local lattice index (10 bits per axis) in its low 32 bits
+//            and its grain id in the high 32 bits, so one 32-byte gather per
+//            bond brings both the neighbour displacement and its lattice offset.
+//   v, a   : SoA FP64, touched only by the owning lane.
+//   bonds  : sliced-ELL (SELL-64) CSR.  Slice s = nodes [64 s, 64 s + 64) (one
+//            wavefront); entry k of lane l sits at colE[slice_off[s] + 64 k + l],
+//            so the column loads of a wavefront are one coalesced 256-byte read.
+//            The broken flags of entry k of a slice are one 64-bit word
+//            maskE[slice_off[s]/64 + k] (bit l = lane l); padding entries are
+//            permanently set so they are skipped like broken bonds.
+//
+// Each lane owns one node and evaluates its row in order (gather formulation,
+// Sec. 3.1 eq. (peri-damage) with nodal quadrature, Sec. 6.1): no atomics, so
+// results are bitwise reproducible run to run.
+
+#include "pd_internal.h"
+
+namespace pdk {
+
+// Workgroups are dispatched round-robin over the 8 XCDs of the MI355X; map them
+// so each XCD walks one contiguous range of slices (its L2 then holds that
+// range's neighbourhood instead of every eighth slice of the whole mesh).
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+  const int64_t x = b & 7, q = nb >> 3, r = nb & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}
+
+__device__ __forceinline__ int unpack_x(int p) { return p & 1023; }
+__device__ __forceinline__ int unpack_y(int p) { return (p >> 10) & 1023; }
+__device__ __forceinline__ int unpack_z(int p) { return (p >> 20) & 1023; }
+__device__ __forceinline__ int packed_ijk(double w) { return (int)(__double_as_longlong(w) & 0xffffffffll); }
+__device__ __forceinline__ int packed_grain(double w) { return (int)(__double_as_longlong(w) >> 32); }
+
+// reference position origin + h*ijk evaluated exactly as the input lays it out
+__device__ __forceinline__ double lattice_pos(double origin, double h, int idx) {
+  return __dadd_rn(origin, __dmul_rn(h, (double)idx));
+}
+
+// 1/sqrt(x) to full double precision: hardware estimate refined by one
+// Newton step with the cubic term, r (1 + e/2 + 3e^2/8), e = 1 - x r^2.
+__device__ __forceinline__ double rsqrt_full(double x) {
+  double r = __builtin_amdgcn_rsq(x);
+  const double t = x * r;
+  const double e = fma(-t, r, 1.0);
+  return fma(r * e, fma(0.375, e, 0.5), r);
+}
+
+// ---------------------------------------------------------------------------
+// bond family (Sec. 3.1) and bond removal (Sec. 6.3)
+// ---------------------------------------------------------------------------
+
+constexpr int64_t kUnbounded = ((int64_t)1) << 50;
+
+// The notch plane cuts the segment A->B strictly inside (0 < t < 1) exactly
+// when the plane function changes sign between the endpoints; the crossing
+// point A + t (B - A), t = fA / (fA - fB), is tested against the bounds with
+// everything multiplied by the positive denominator.
+__device__ bool notch_cuts(const CutDev& c, const int64_t A[3], const int64_t B[3]) {
+  const int64_t fa = c.plane[0] * A[0] + c.plane[1] * A[1] + c.plane[2] * A[2] + c.plane[3];
+  const int64_t fb = c.plane[0] * B[0] + c.plane[1] * B[1] + c.plane[2] * B[2] + c.plane[3];
+  if (fa == 0 || fb == 0 || ((fa < 0) == (fb < 0))) return false;
+  int64_t num = fa, den = fa - fb;
+  if (den < 0) {
+    num = -num;
+    den = -den;
+  }
+  for (int q = 0; q < 3; ++q) {
+    const int64_t qs = A[q] * den + num * (B[q] - A[q]);
+    if (c.lo[q] > -kUnbounded && qs < c.lo[q] * den) return false;
+    if (c.hi[q] < kUnbounded && qs > c.hi[q] * den) return false;
+  }
+  return true;
+}
+
+__device__ __forceinline__ int64_t sq_dist(const int64_t A[3], const int64_t C[3]) {
+  const int64_t a = A[0] - C[0], b = A[1] - C[1], d = A[2] - C[2];
+  return a * a + b * b + d * d;
+}
+
+// closest point of segment A->B to the centre, all in integers
+__device__ bool chord_cuts(const CutDev& c, const int64_t A[3], const int64_t B[3]) {
+  int64_t D[3], W[3];
+  for (int q = 0; q < 3; ++q) {
+    D[q] = B[q] - A[q];
+    W[q] = c.c[q] - A[q];
+  }
+  const int64_t dd = D[0] * D[0] + D[1] * D[1] + D[2] * D[2];
+  const int64_t wd = W[0] * D[0] + W[1] * D[1] + W[2] * D[2];
+  if (wd <= 0) return sq_dist(A, c.c) < c.r2;
+  if (wd >= dd) return sq_dist(B, c.c) < c.r2;
+  const int64_t ww = W[0] * W[0] + W[1] * W[1] + W[2] * W[2];
+  return ww * dd - wd * wd < c.r2 * dd;
+}
+
+__device__ bool bond_cut(const BuildArgs& b, int g, int pi, int pj) {
+  const int c0 = b.cut_begin[g], c1 = b.cut_begin[g + 1];
+  if (c0 == c1) return false;
+  const int64_t A[3] = {2 * (int64_t)unpack_x(pi), 2 * (int64_t)unpack_y(pi), 2 * (int64_t)unpack_z(pi)};
+  const int64_t B[3] = {2 * (int64_t)unpack_x(pj), 2 * (int64_t)unpack_y(pj), 2 * (int64_t)unpack_z(pj)};
+  for (int k = c0; k < c1; ++k) {
+    const CutDev& c = b.cuts[k];
+    if (c.kind == 0 && notch_cuts(c, A, B)) return true;
+    if (c.kind == 1 && (sq_dist(A, c.c) < c.r2 || sq_dist(B, c.c) < c.r2)) return true;
+    if (c.kind == 2 && chord_cuts(c, A, B)) return true;
+  }
+  return false;
+}
+
+// node index at lattice point ijk + d of grain g, or -1
+__device__ __forceinline__ int lookup(const BuildArgs& b, int g, int p, int s) {
+  const int dx = (s & 255) - 8, dy = ((s >> 8) & 255) - 8, dz = ((s >> 16) & 255) - 8;
+  const int lx = unpack_x(p) - b.gmap_lo[3 * g] + dx;
+  const int ly = unpack_y(p) - b.gmap_lo[3 * g + 1] + dy;
+  const int lz = unpack_z(p) - b.gmap_lo[3 * g + 2] + dz;
+  const int ex = b.gmap_dim[3 * g], ey = b.gmap_dim[3 * g + 1], ez = b.gmap_dim[3 * g + 2];
+  if (lx < 0 || ly < 0 || lz < 0 || lx >= ex || ly >= ey || lz >= ez) return -1;
+  return b.gmap[b.gmap_off[g] + ((int64_t)lx * ey + ly) * ez + lz];
+}
+
+__global__ void k_map_fill(BuildArgs b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const double w = b.u[i].w;
+  const int p = packed_ijk(w), g = packed_grain(w);
+  const int lx = unpack_x(p) - b.gmap_lo[3 * g];
+  const int ly = unpack_y(p) - b.gmap_lo[3 * g + 1];
+  const int lz = unpack_z(p) - b.gmap_lo[3 * g + 2];
+  const int ey = b.gmap_dim[3 * g + 1], ez = b.gmap_dim[3 * g + 2];
+  b.gmap[b.gmap_off[g] + ((int64_t)lx * ey + ly) * ez + lz] = (int32_t)i;
+}
+
+__global__ void k_bond_count(BuildArgs b) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= b.n) return;
+  const double w = b.u[i].w;
+  const int p = packed_ijk(w), g = packed_grain(w);
+  int cnt = 0;
+  for (int k = 0; k < b.n_stencil; ++k) {
+    const int j = lookup(b, g, p, b.stencil[k]);
+    if (j < 0) continue;
+    if (bond_cut(b, g, p, packed_ijk(b.u[j].w))) continue;
+    ++cnt;
+  }
+  b.rowlen[i] = cnt;
+}
+
+// padded slot count (64 * widest row) of every slice
+__global__ void k_slice_width(BuildArgs b) {
+  const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (s >= b.nslices) return;
+  int w = 0;
+  for (int l = 0; l < kWave; ++l) {
+    const int64_t i = s * kWave + l;
+    if (i < b.n) w = max(w, b.rowlen[i]);
+  }
+  b.slice_off[s] = (int64_t)w * kWave;
+}
+
+// one wavefront per slice: write the row (stencil order), sort it ascending,
+// pad it with the node itself and write the slice's padding masks
+__global__ __launch_bounds__(kBlock) void k_bond_fill(BuildArgs b) {
+  const int lane = threadIdx.x & 63;
+  const int64_t s = (int64_t)blockIdx.x * kSlicesPerBlock + (threadIdx.x >> 6);
+  if (s >= b.nslices) return;  // whole wavefront leaves together
+  const int64_t i = s * kWave + lane;
+  const bool valid = i < b.n;
+  const int64_t off = b.slice_off[s];
+  const int W = (int)((b.slice_off[s + 1] - off) / kWave);
+  int32_t* col = b.colE + off + lane;
+  int len = 0;
+  if (valid) {
+    const double w = b.u[i].w;
+    const int p = packed_ijk(w), g = packed_grain(w);
+    for (int k = 0; k < b.n_stencil; ++k) {
+      const int j = lookup(b, g, p, b.stencil[k]);
+      if (j < 0) continue;
+      if (bond_cut(b, g, p, packed_ijk(b.u[j].w))) continue;
+      col[(int64_t)len * kWave] = j;
+      ++len;
+    }
+    // insertion sort (rows come out nearly sorted from the lexicographic stencil)
+    for (int k = 1; k < len; ++k) {
+      const int32_t x = col[(int64_t)k * kWave];
+      int q = k - 1;
+      while (q >= 0 && col[(int64_t)q * kWave] > x) {
+        col[(int64_t)(q + 1) * kWave] = col[(int64_t)q * kWave];
+        --q;
+      }
+      col[(int64_t)(q + 1) * kWave] = x;
+    }
+    for (int k = len; k < W; ++k) col[(int64_t)k * kWave] = (int32_t)i;
+  } else {
+    for (int k = 0; k < W; ++k) col[(int64_t)k * kWave] = 0;
+  }
+  uint64_t* mask = b.maskE + off / kWave;
+  for (int k = 0; k < W; ++k) {
+    const uint64_t pad = __ballot(!valid || k >= len);
+    if (lane == 0) mask[k] = pad;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// the fused step: bond force + break + damage, contact, walls, velocity Verlet
+// ---------------------------------------------------------------------------
+
+// contact distance exactly as p_j - p_i = (X_j - X_i) + (u_j - u_i), no contraction
+__device__ __forceinline__ double contact_d2(double xj, double xi, double uj, double ui, double yj,
+                                             double yi, double vj, double vi, double zj, double zi,
+                                             double wj, double wi, double& dx, double& dy,
+                                             double& dz) {
+  dx = __dadd_rn(__dsub_rn(xj, xi), __dsub_rn(uj, ui));
+  dy = __dadd_rn(__dsub_rn(yj, yi), __dsub_rn(vj, vi));
+  dz = __dadd_rn(__dsub_rn(zj, zi), __dsub_rn(wj, wi));
+  return __dadd_rn(__dadd_rn(__dmul_rn(dx, dx), __dmul_rn(dy, dy)), __dmul_rn(dz, dz));
+}
+
+__device__ __forceinline__ double wave_sum(double x) {
+  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, kWave);
+  return x;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+  __shared__ double s_inv[kMaxD2 + 1];
+  __shared__ double s_wall[kSlicesPerBlock][kMaxWalls * 3];
+  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  if (tid <= kMaxD2) s_inv[tid] = A.inv_len[tid];
+  __syncthreads();
+
+  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
+  const int64_t slice = blk * kSlicesPerBlock + wid;
+  const bool slice_ok = slice < A.nslices;
+  const int64_t i = slice * kWave + lane;
+  const bool valid = slice_ok && i < A.n;
+
+  double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (valid) ui = A.ucur[i];
+  const int pi = packed_ijk(ui.w);
+  const int gi = valid ? packed_grain(ui.w) : 0;
+  const GrainC* G = A.grains + gi;
+  const double h = G->h, inv_h = G->inv_h, cV = G->cV, thr = G->thr, thr_lo = G->thr_lo;
+  const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
+
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  int nbroke = 0;
+
+  // ---- peridynamic bonds with bond memory ----
+  int64_t off = 0;
+  int W = 0;
+  if (slice_ok) {
+    off = A.slice_off[slice];
+    W = (int)((A.slice_off[slice + 1] - off) >> 6);
+  }
+  const int32_t* cp = A.colE + off + lane;
+  uint64_t* mp = A.maskE + (off >> 6);
+  for (int k = 0; k < W; ++k) {
+    const int j = cp[(int64_t)k * kWave];
+    const uint64_t mw = mp[k];
+    bool brk = false;
+    if (!((mw >> lane) & 1ull)) {
+      const double4 uj = A.ucur[j];
+      const int pj = packed_ijk(uj.w);
+      const int dx = unpack_x(pj) - ix, dy = unpack_y(pj) - iy, dz = unpack_z(pj) - iz;
+      const int d2 = dx * dx + dy * dy + dz * dz;
+      // y = xi + eta with xi = h * (ijk_j - ijk_i) exact inside the fma
+      const double yx = fma(h, (double)dx, uj.x - ui.x);
+      const double yy = fma(h, (double)dy, uj.y - ui.y);
+      const double yz = fma(h, (double)dz, uj.z - ui.z);
+      const double lsq = fma(yx, yx, fma(yy, yy, yz * yz));
+      const double d2f = (double)d2;
+      // s > s0  <=>  |y|^2 > (1+s0)^2 |xi|^2
+      brk = lsq > thr * d2f || lsq < thr_lo * d2f;
+      if (!brk) {
+        // c s V / |y| = c V (1/|xi| - 1/|y|)
+        const double coef = cV * fma(s_inv[d2], inv_h, -rsqrt_full(lsq));
+        fx = fma(coef, yx, fx);
+        fy = fma(coef, yy, fy);
+        fz = fma(coef, yz, fz);
+      }
+    }
+    if (MODE != MODE_FORCE_ONLY) {
+      const uint64_t nb = __ballot(brk);
+      if (nb) {
+        if (lane == 0) mp[k] = mw | nb;
+        nbroke += brk ? 1 : 0;
+      }
+    }
+  }
+
+  // ---- repulsive contact with candidates of other grains (Sec. 3.2) ----
+  if (valid && A.cand_ptr != nullptr) {
+    // rows past the capacity were not stored (the rebuild flagged it)
+    const int32_t c0 = (int32_t)min((int64_t)A.cand_ptr[i], A.cand_capacity);
+    const int32_t c1 = (int32_t)min((int64_t)A.cand_ptr[i + 1], A.cand_capacity);
+    if (c1 > c0) {
+      const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
+      const int mi = G->mat;
+      for (int32_t e = c0; e < c1; ++e) {
+        const int j = A.cand[e];
+        const double4 uj = A.ucur[j];
+        double yx, yy, yz;
+        const double d2 = contact_d2(A.X[j], Xx, uj.x, ui.x, A.X[A.n + j], Xy, uj.y, ui.y,
+                                     A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
+        if (d2 < A.Rc2 && d2 > 0.0) {
+          const GrainC* Gj = A.grains + packed_grain(uj.w);
+          const double d = sqrt(d2);
+          const double coef = -A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V / d;
+          fx = fma(coef, yx, fx);
+          fy = fma(coef, yy, fy);
+          fz = fma(coef, yz, fz);
+        }
+      }
+    }
+  }
+
+  // ---- rigid walls: spherical-cap law (Sec. 4.1), walls summed ----
+  for (int w = 0; w < A.n_walls; ++w) {
+    const WallDev* Wd = A.walls + w;
+    bool hit = false;
+    double mag = 0.0;
+    if (valid) {
+      const double px = lattice_pos(G->origin[0], h, ix) + ui.x;
+      const double py = lattice_pos(G->origin[1], h, iy) + ui.y;
+      const double pz = lattice_pos(G->origin[2], h, iz) + ui.z;
+      const bool in = px >= Wd->lo[0] && px <= Wd->hi[0] && py >= Wd->lo[1] && py <= Wd->hi[1] &&
+                      pz >= Wd->lo[2] && pz <= Wd->hi[2];
+      const double o = MODE == MODE_FORCE_ONLY ? Wd->off_used : Wd->off;
+      const double d = Wd->n[0] * px + Wd->n[1] * py + Wd->n[2] * pz - o;
+      if (in && d < A.Rc) {
+        if (d <= -A.Rc) {
+          if (MODE != MODE_FORCE_ONLY) atomicOr(A.status, ST_PENETRATION);
+        } else {
+          // cap of the contact ball beyond the wall: height Rc - d, volume
+          // (pi/3)(Rc-d)^2(2Rc+d); its centroid lies 3(Rc+d)^2/(4(2Rc+d)) from p
+          const double H = A.Rc - d, q = 2.0 * A.Rc + d;
+          const double vol = (M_PI / 3.0) * H * H * q;
+          const double ell = 0.75 * (A.Rc + d) * (A.Rc + d) / q;
+          mag = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
+          hit = true;
+        }
+      }
+    }
+    if (hit) {
+      fx = fma(mag, Wd->n[0], fx);
+      fy = fma(mag, Wd->n[1], fy);
+      fz = fma(mag, Wd->n[2], fz);
+    }
+    if (MODE != MODE_FORCE_ONLY) {
+      const uint64_t any = __ballot(hit);
+      double r0 = 0.0, r1 = 0.0, r2 = 0.0;
+      if (any) {
+        const double vm = hit ? G->V * mag : 0.0;
+        r0 = wave_sum(vm * Wd->n[0]);
+        r1 = wave_sum(vm * Wd->n[1]);
+        r2 = wave_sum(vm * Wd->n[2]);
+      }
+      if (lane == 0) {
+        s_wall[wid][3 * w] = r0;
+        s_wall[wid][3 * w + 1] = r1;
+        s_wall[wid][3 * w + 2] = r2;
+      }
+    }
+  }
+
+  // ---- velocity Verlet (Sec. 6.2) and stores ----
+  if (valid) {
+    if (MODE == MODE_FORCE_ONLY) {
+      A.Fout[i] = fx;
+      A.Fout[A.n + i] = fy;
+      A.Fout[2 * A.n + i] = fz;
+    } else {
+      if (!(isfinite(fx) && isfinite(fy) && isfinite(fz))) atomicOr(A.status, ST_NAN);
+      const bool fixed = A.fixed != nullptr && A.fixed[i] != 0;
+      const double rho = G->rho, dt = A.dt, hdt = 0.5 * dt, hdt2 = 0.5 * dt * dt;
+      const double anx = fixed ? 0.0 : fx / rho + A.g[0];
+      const double any = fixed ? 0.0 : fy / rho + A.g[1];
+      const double anz = fixed ? 0.0 : fz / rho + A.g[2];
+      double vx = A.v[i], vy = A.v[A.n + i], vz = A.v[2 * A.n + i];
+      if (MODE == MODE_STEP) {
+        vx = fixed ? 0.0 : fma(hdt, A.a[i] + anx, vx);
+        vy = fixed ? 0.0 : fma(hdt, A.a[A.n + i] + any, vy);
+        vz = fixed ? 0.0 : fma(hdt, A.a[2 * A.n + i] + anz, vz);
+      } else if (fixed) {
+        vx = vy = vz = 0.0;
+      }
+      A.v[i] = vx;
+      A.v[A.n + i] = vy;
+      A.v[2 * A.n + i] = vz;
+      A.a[i] = anx;
+      A.a[A.n + i] = any;
+      A.a[2 * A.n + i] = anz;
+      // positions of the next step: u + dt v + dt^2/2 a
+      double4 un = ui;
+      if (!fixed) {
+        un.x = fma(hdt2, anx, fma(dt, vx, ui.x));
+        un.y = fma(hdt2, any, fma(dt, vy, ui.y));
+        un.z = fma(hdt2, anz, fma(dt, vz, ui.z));
+      }
+      A.unext[i] = un;
+      if (nbroke) A.intact[i] -= nbroke;
+    }
+  }
+
+  if (MODE != MODE_FORCE_ONLY && A.n_walls > 0) {
+    __syncthreads();
+    if (tid < 3 * A.n_walls) {
+      double s = 0.0;
+      for (int q = 0; q < kSlicesPerBlock; ++q) s += s_wall[q][tid];
+      A.wall_partial[blk * 3 * A.n_walls + tid] = s;
+    }
+  }
+}
+
+// reaction forces (fixed-order sum of block partials) and the wall positions
+// of the next step: prescribed velocity or servo on the measured stress
+__global__ __launch_bounds__(256) void k_wall_finalize(WallDev* walls, const double* partial,
+                                                       int32_t nblocks, int32_t n_walls,
+                                                       int64_t* step, int32_t advance, double dt) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  for (int c = 0; c < 3 * n_walls; ++c) {
+    double s = 0.0;
+    for (int b = tid; b < nblocks; b += 256) s += partial[(int64_t)b * 3 * n_walls + c];
+    red[tid] = s;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (tid < o) red[tid] += red[tid + o];
+      __syncthreads();
+    }
+    if (tid == 0) walls[c / 3].force[c % 3] = -red[0];
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t s = *step + advance;  // the step this evaluation belonged to
+    *step = s;
+    for (int w = 0; w < n_walls; ++w) {
+      WallDev& W = walls[w];
+      W.off_used = W.off;
+      if (W.mode == PD_WALL_VELOCITY) {
+        W.off = W.off0 + W.vel * ((double)(s + 1) * dt);
+      } else if (W.mode == PD_WALL_SERVO) {
+        const double sigma = -(W.force[0] * W.n[0] + W.force[1] * W.n[1] + W.force[2] * W.n[2]) / W.area;
+        W.off = W.off + dt * W.gain * (W.target - sigma);
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// energies (diagnostic): kinetic, elastic, contact, gravity potential
+// ---------------------------------------------------------------------------
+
+__global__ __launch_bounds__(kBlock) void k_energy(StepArgs A, double* partial4) {
+  __shared__ double red[4][kBlock];
+  const int tid = threadIdx.x;
+  const int64_t i = (int64_t)blockIdx.x * kBlock + tid;
+  double e[4] = {0.0, 0.0, 0.0, 0.0};
+  if (i < A.n) {
+    const double4 ui = A.ucur[i];
+    const GrainC* G = A.grains + packed_grain(ui.w);
+    const int pi = packed_ijk(ui.w);
+    const double V = G->V, rho = G->rho;
+    const double vx = A.v[i], vy = A.v[A.n + i], vz = A.v[2 * A.n + i];
+    e[0] = 0.5 * rho * V * (vx * vx + vy * vy + vz * vz);
+    e[3] = -rho * V * (A.g[0] * ui.x + A.g[1] * ui.y + A.g[2] * ui.z);
+    const int64_t s = i / kWave;
+    const int lane = (int)(i % kWave);
+    const int64_t off = A.slice_off[s];
+    const int W = (int)((A.slice_off[s + 1] - off) / kWave);
+    double w = 0.0;
+    for (int k = 0; k < W; ++k) {
+      if ((A.maskE[off / kWave + k] >> lane) & 1ull) continue;
+      const int j = A.colE[off + (int64_t)k * kWave + lane];
+      const double4 uj = A.ucur[j];
+      const int pj = packed_ijk(uj.w);
+      const int dx = unpack_x(pj) - unpack_x(pi), dy = unpack_y(pj) - unpack_y(pi),
+                dz = unpack_z(pj) - unpack_z(pi);
+      const double xx = G->h * dx, xy = G->h * dy, xz = G->h * dz;
+      const double yx = xx + (uj.x - ui.x), yy = xy + (uj.y - ui.y), yz = xz + (uj.z - ui.z);
+      const double l0 = sqrt(xx * xx + xy * xy + xz * xz), l = sqrt(yx * yx + yy * yy + yz * yz);
+      const double st = (l - l0) / l0;
+      w += 0.5 * G->cV * st * st * l0;  // micropotential times V_j
+    }
+    e[1] = 0.5 * V * w;
+    if (A.cand_ptr != nullptr) {
+      const int32_t c0 = (int32_t)min((int64_t)A.cand_ptr[i], A.cand_capacity);
+      const int32_t c1 = (int32_t)min((int64_t)A.cand_ptr[i + 1], A.cand_capacity);
+      for (int32_t c = c0; c < c1; ++c) {
+        const int j = A.cand[c];
+        const double4 uj = A.ucur[j];
+        double yx, yy, yz;
+        const double d2 = contact_d2(A.X[j], A.X[i], uj.x, ui.x, A.X[A.n + j], A.X[A.n + i], uj.y,
+                                     ui.y, A.X[2 * A.n + j], A.X[2 * A.n + i], uj.z, ui.z, yx, yy, yz);
+        if (!(d2 < A.Rc2)) continue;
+        const GrainC* Gj = A.grains + packed_grain(uj.w);
+        const double d = sqrt(d2);
+        e[2] += 0.5 * V * 0.5 * A.Kn[G->mat * A.n_mat + Gj->mat] * (A.Rc - d) * (A.Rc - d) * Gj->V;
+      }
+    }
+  }
+  for (int q = 0; q < 4; ++q) red[q][tid] = e[q];
+  __syncthreads();
+  for (int o = kBlock / 2; o > 0; o >>= 1) {
+    if (tid < o)
+      for (int q = 0; q < 4; ++q) red[q][tid] += red[q][tid + o];
+    __syncthreads();
+  }
+  if (tid < 4) partial4[(int64_t)blockIdx.x * 4 + tid] = red[tid][0];
+}
+
+__global__ void k_reduce_energy(const double* partial4, int32_t nblocks, double* out4) {
+  if (threadIdx.x < 4) {
+    double s = 0.0;
+    for (int b = 0; b < nblocks; ++b) s += partial4[(int64_t)b * 4 + threadIdx.x];
+    out4[threadIdx.x] = s;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// contact candidates: hashed uniform cell grid, counting sort, per-node rows
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, uint32_t T) {
+  return (((uint32_t)cx * 73856093u) ^ ((uint32_t)cy * 19349663u) ^ ((uint32_t)cz * 83492791u)) &
+         (T - 1u);
+}
+
+__device__ __forceinline__ int cell_coord(double p, double inv_cell) {
+  double c = floor(p * inv_cell);
+  c = fmin(fmax(c, -1.0e9), 1.0e9);
+  return (int)c;
+}
+
+__global__ void k_bin(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const double4 u = c.u[i];
+  const int cx = cell_coord(c.X[i] + u.x, c.inv_cell);
+  const int cy = cell_coord(c.X[c.n + i] + u.y, c.inv_cell);
+  const int cz = cell_coord(c.X[2 * c.n + i] + u.z, c.inv_cell);
+  c.cellc[3 * i] = cx;
+  c.cellc[3 * i + 1] = cy;
+  c.cellc[3 * i + 2] = cz;
+  const uint32_t hsh = cell_hash(cx, cy, cz, c.T);
+  c.cellh[i] = hsh;
+  atomicAdd(c.bucket_count + hsh, 1);
+}
+
+__global__ void k_scatter(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const uint32_t hsh = c.cellh[i];
+  const int pos = c.bucket_start[hsh] + atomicAdd(c.bucket_fill + hsh, 1);
+  c.sorted[pos] = (int32_t)i;
+}
+
+template <bool FILL>
+__global__ void k_candidates(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const double4 ui = c.u[i];
+  const int gi = packed_grain(ui.w);
+  const int cx = c.cellc[3 * i], cy = c.cellc[3 * i + 1], cz = c.cellc[3 * i + 2];
+  const double Xx = c.X[i], Xy = c.X[c.n + i], Xz = c.X[2 * c.n + i];
+  int cnt = 0;
+  int64_t base = 0;
+  if (FILL) base = c.cand_count[i];  // already scanned into row pointers
+  for (int d = 0; d < kCellDirs; ++d) {
+    const int nx = cx + d % 3 - 1, ny = cy + (d / 3) % 3 - 1, nz = cz + d / 9 - 1;
+    const uint32_t hsh = cell_hash(nx, ny, nz, c.T);
+    for (int e = c.bucket_start[hsh]; e < c.bucket_start[hsh + 1]; ++e) {
+      const int j = c.sorted[e];
+      if (c.cellc[3 * j] != nx || c.cellc[3 * j + 1] != ny || c.cellc[3 * j + 2] != nz) continue;
+      const double4 uj = c.u[j];
+      if (packed_grain(uj.w) == gi) continue;
+      double yx, yy, yz;
+      const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y,
+                                   c.X[2 * c.n + j], Xz, uj.z, ui.z, yx, yy, yz);
+      if (!(d2 < c.cut2)) continue;
+      if (FILL) {
+        const int64_t slot = base + cnt;
+        if (slot < c.capacity) c.cand[slot] = j;
+      }
+      ++cnt;
+    }
+  }
+  if (!FILL) {
+    c.cand_count[i] = cnt;
+    return;
+  }
+  // ascending order inside the row
+  const int64_t end = base + cnt < c.capacity ? base + cnt : c.capacity;
+  for (int64_t a = base + 1; a < end; ++a) {
+    const int32_t x = c.cand[a];
+    int64_t q = a - 1;
+    while (q >= base && c.cand[q] > x) {
+      c.cand[q + 1] = c.cand[q];
+      --q;
+    }
+    c.cand[q + 1] = x;
+  }
+}
+
+__global__ void k_cand_capacity(ContactArgs c) {
+  if (threadIdx.x == 0 && blockIdx.x == 0 && (int64_t)c.cand_count[c.n] > c.capacity)
+    atomicOr(c.status, ST_CAND_OVERFLOW);
+}
+
+// displacement since the last rebuild beyond skin/2 invalidates the list
+__global__ void k_skin(ContactArgs c, int check) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const double4 u = c.u[i];
+  if (check) {
+    const double dx = u.x - c.u_build[i], dy = u.y - c.u_build[c.n + i], dz = u.z - c.u_build[2 * c.n + i];
+    if (dx * dx + dy * dy + dz * dz > c.skin_half2) atomicOr(c.status, ST_SKIN);
+  }
+  c.u_build[i] = u.x;
+  c.u_build[c.n + i] = u.y;
+  c.u_build[2 * c.n + i] = u.z;
+}
+
+__global__ void k_fill_u4(double4* u4, const double* u, const int32_t* ijk, const int64_t* grain_of,
+                          int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t w = (int64_t)(uint32_t)(ijk[i] | (ijk[n + i] << 10) | (ijk[2 * n + i] << 20)) |
+                    (grain_of[i] << 32);
+  u4[i] = make_double4(u[i], u[n + i], u[2 * n + i], __longlong_as_double(w));
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scans (3 passes: block-local, block sums, add)
+// ---------------------------------------------------------------------------
+
+constexpr int kScanThreads = 1024;
+constexpr int kScanItems = 4;
+constexpr int kScanTile = kScanThreads * kScanItems;
+
+template <typename T>
+__device__ T block_inclusive_scan(T x, T* s) {
+  const int tid = threadIdx.x;
+  s[tid] = x;
+  __syncthreads();
+  for (int o = 1; o < kScanThreads; o <<= 1) {
+    const T t = tid >= o ? s[tid - o] : T(0);
+    __syncthreads();
+    s[tid] += t;
+    __syncthreads();
+  }
+  return s[tid];
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_local(const T* in, T* out, int64_t n,
+                                                             T* block_sums) {
+  __shared__ T s[kScanThreads];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  T v[kScanItems];
+  T tot = 0;
+  for (int k = 0; k < kScanItems; ++k) {
+    v[k] = base + k < n ? in[base + k] : T(0);
+    tot += v[k];
+  }
+  const T inc = block_inclusive_scan(tot, s);
+  T run = inc - tot;
+  for (int k = 0; k < kScanItems; ++k) {
+    if (base + k < n) out[base + k] = run;
+    run += v[k];
+  }
+  if (threadIdx.x == kScanThreads - 1) block_sums[blockIdx.x] = inc;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_top(T* block_sums, int64_t nb, T* total) {
+  __shared__ T s[kScanThreads];
+  T carry = 0;
+  for (int64_t c = 0; c < nb; c += kScanThreads) {
+    const int64_t idx = c + threadIdx.x;
+    const T x = idx < nb ? block_sums[idx] : T(0);
+    const T inc = block_inclusive_scan(x, s);
+    if (idx < nb) block_sums[idx] = carry + inc - x;
+    const T chunk = s[kScanThreads - 1];
+    __syncthreads();
+    carry += chunk;
+  }
+  if (threadIdx.x == 0) *total = carry;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kScanThreads) void k_scan_add(T* out, int64_t n, const T* block_sums) {
+  const T add = block_sums[blockIdx.x];
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  for (int k = 0; k < kScanItems; ++k)
+    if (base + k < n) out[base + k] += add;
+}
+
+__global__ void k_fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+template <typename T>
+__global__ void k_set_value(T* p, T v) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = v;
+}
+
+int64_t scan_scratch_elems(int64_t n) { return (n + kScanTile - 1) / kScanTile + 1; }
+
+template <typename T>
+static hipError_t scan_impl(const T* in, T* out, int64_t n, T* scratch, hipStream_t s) {
+  if (n <= 0) {
+    hipLaunchKernelGGL(k_set_value<T>, dim3(1), dim3(64), 0, s, out, T(0));
+    return hipGetLastError();
+  }
+  const int64_t nb = (n + kScanTile - 1) / kScanTile;
+  hipLaunchKernelGGL(k_scan_local<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, in, out, n, scratch);
+  hipLaunchKernelGGL(k_scan_top<T>, dim3(1), dim3(kScanThreads), 0, s, scratch, nb, out + n);
+  hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(kScanThreads), 0, s, out, n,
+                     (const T*)scratch);
+  return hipGetLastError();
+}
+
+hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch, hipStream_t s) {
+  return scan_impl<int64_t>(in, out, n, scratch, s);
+}
+hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s) {
+  return scan_impl<int32_t>(in, out, n, scratch, s);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+
+static inline unsigned grid_for(int64_t n, int threads) {
+  return (unsigned)((n + threads - 1) / threads);
+}
+
+hipError_t launch_map_fill(const BuildArgs& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_map_fill, dim3(grid_for(b.n, 256)), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s) {
+  if (b.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bond_count, dim3(grid_for(b.n, 256)), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s) {
+  if (b.nslices == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_slice_width, dim3(grid_for(b.nslices, 256)), dim3(256), 0, s, b);
+  return hipGetLastError();
+}
+hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s) {
+  if (b.nslices == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_bond_fill, dim3(grid_for(b.nslices, kSlicesPerBlock)), dim3(kBlock), 0, s, b);
+  return hipGetLastError();
+}
+
+int32_t step_grid_blocks(int64_t nslices) { return (int32_t)grid_for(nslices, kSlicesPerBlock); }
+
+hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
+  const int32_t nb = step_grid_blocks(a.nslices);
+  if (nb == 0) return hipSuccess;
+  if (mode == MODE_FIRST)
+    hipLaunchKernelGGL(k_step<MODE_FIRST>, dim3(nb), dim3(kBlock), 0, s, a);
+  else if (mode == MODE_STEP)
+    hipLaunchKernelGGL(k_step<MODE_STEP>, dim3(nb), dim3(kBlock), 0, s, a);
+  else
+    hipLaunchKernelGGL(k_step<MODE_FORCE_ONLY>, dim3(nb), dim3(kBlock), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_finalize(WallDev* walls, const double* partial, int32_t nblocks,
+                                int32_t n_walls, int64_t* step, int32_t advance, double dt,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(256), 0, s, walls, partial, nblocks, n_walls,
+                     step, advance, dt);
+  return hipGetLastError();
+}
+
+hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  const unsigned g = grid_for(c.n, 256);
+  hipError_t e;
+  // clears by kernel (not memset nodes) so the sequence can live in a captured graph
+  if ((e = launch_fill_i32(c.bucket_count, 0, (int64_t)c.T, s)) != hipSuccess) return e;
+  if ((e = launch_fill_i32(c.bucket_fill, 0, (int64_t)c.T, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_skin, dim3(g), dim3(256), 0, s, c, check_skin);
+  hipLaunchKernelGGL(k_bin, dim3(g), dim3(256), 0, s, c);
+  if ((e = scan_i32(c.bucket_count, c.bucket_start, (int64_t)c.T, c.scan_scratch, s)) != hipSuccess)
+    return e;
+  hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_candidates<false>, dim3(g), dim3(256), 0, s, c);
+  if ((e = scan_i32(c.cand_count, c.cand_count, c.n, c.scan_scratch, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cand_capacity, dim3(1), dim3(64), 0, s, c);
+  hipLaunchKernelGGL(k_candidates<true>, dim3(g), dim3(256), 0, s, c);
+  return hipGetLastError();
+}
+
+hipError_t launch_energy(const StepArgs& a, double* partial4, int32_t nblocks, hipStream_t s) {
+  if (nblocks == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_energy, dim3(nblocks), dim3(kBlock), 0, s, a, partial4);
+  return hipGetLastError();
+}
+
+hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double* out4,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(64), 0, s, partial4, nblocks, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_fill_u4(double4* u4, const double* u, const int32_t* ijk, const int64_t* grain_of,
+                          int64_t n, hipStream_t s) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_fill_u4, dim3(grid_for(n, 256)), dim3(256), 0, s, u4, u, ijk, grain_of, n);
+  return hipGetLastError();
+}
+
+}  // namespace pdk

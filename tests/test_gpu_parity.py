@@ -1,0 +1,238 @@
+"""GPU parity: the HIP path through the C ABI against the CPU oracle on the same
+seeded inputs.
+
+Bar (spec tolerances): bond, candidate and broken-bond sets bit-exact
+(broken sets when the oracle's recorded break margin exceeds 1e-9), u, v and F
+within 1e-9 relative (infinity norm over the field), platen force within 1e-6
+relative.
+"""
+import numpy as np
+import pytest
+
+from paper_2506_05362_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+REL = 1e-9
+
+
+def gpu_sim(wl, **kw):
+    from paper_2506_05362_amd import pd
+    return pd.Sim(wl, **kw)
+
+
+def rel_inf(a, b):
+    scale = np.abs(b).max()
+    if scale == 0:
+        return np.abs(a).max()
+    return np.abs(a - b).max() / scale
+
+
+def assert_state_close(sim, ora, rel=REL, what=""):
+    so = ora.state()
+    for name, key in (("displacement", "u"), ("velocity", "v"), ("accel", "a")):
+        g = sim.get(name)
+        r = rel_inf(g, so[key])
+        assert r <= rel, f"{what} {name}: rel err {r:.3e}"
+    Fg = sim.get("force_density")
+    r = rel_inf(Fg, so["F"])
+    assert r <= rel, f"{what} force: rel err {r:.3e}"
+
+
+def assert_bonds_equal(sim, ora, broken=True):
+    rp, col, br = sim.bonds()
+    rpo, colo, bro = ora.bonds()
+    assert np.array_equal(rp, rpo)
+    assert np.array_equal(col, colo)
+    if broken:
+        assert np.array_equal(br, bro)
+
+
+def small_cases():
+    return {
+        "two_spheres_r5": I.two_spheres(radius_cells=5, gap=0.0),
+        "plate_notched": I.notched_plate(nx=40, ny=30, nz=6, h=5e-4, notch_x=(10 * 5e-4, 30 * 5e-4),
+                                         notch_len=15 * 5e-4, steps=1),
+        "aggregate6": I.grain_aggregate(n_grains=6, grid=(3, 2, 1), n_min=800, n_max=3000, seed=2),
+    }
+
+
+@pytest.mark.parametrize("case", list(small_cases()))
+def test_bond_lists_bit_exact(oracle_lib, case):
+    wl = small_cases()[case]
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    assert_bonds_equal(sim, ora)
+    d, it, n0 = ora.damage()
+    assert np.array_equal(sim.get("initial_count"), n0)
+    assert np.array_equal(sim.get("intact_count"), it)
+    assert sim.info()["nnz"] == ora.nnz
+
+
+def test_hollow_cavity_cuts_bit_exact(oracle_lib):
+    from test_oracle_lists import hollow_ball
+    for kind, meshed in ((I.CUT_CAVITY_ENDPOINT, True), (I.CUT_CAVITY_CHORD, False)):
+        wl = hollow_ball(kind, meshed)
+        sim = gpu_sim(wl)
+        ora = oracle_lib.Oracle(wl)
+        assert_bonds_equal(sim, ora)
+
+
+def test_contact_candidates_bit_exact_on_identical_positions(oracle_lib):
+    wl = I.two_spheres(radius_cells=6, gap=0.0, speed=2.0, rebuild_every=10)
+    wl.u0[0, wl.grain_begin[1]:] -= 2.5e-4  # interpenetrating surfaces: many pairs
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    rp, col = sim.candidates()
+    rpo, colo = ora.candidates()
+    assert len(col) > 20
+    assert np.array_equal(rp, rpo) and np.array_equal(col, colo)
+    sim.step(30)  # a rebuild happens at step 30
+    u = sim.get("displacement")
+    ora.set_u(u)
+    rp, col = sim.candidates()
+    rpo, colo = ora.candidates()
+    assert np.array_equal(rp, rpo) and np.array_equal(col, colo)
+
+
+def test_force_at_t0_with_prestrain(oracle_lib):
+    wl = I.two_spheres(radius_cells=6, gap=0.0)
+    rng = np.random.default_rng(5)
+    wl.u0[:] = rng.normal(0, 2e-8, size=wl.u0.shape)
+    wl.u0[0, wl.grain_begin[1]:] -= 3e-6
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    Fo = ora.state()["F"]
+    Fg = sim.get("force_density")
+    assert rel_inf(Fg, Fo) <= 1e-11
+    assert_bonds_equal(sim, ora)
+
+
+@pytest.mark.parametrize("speed,steps", [(1.0, 1000), (50.0, 300)])
+def test_two_spheres_trajectory(oracle_lib, speed, steps):
+    """The two-grain collision (radius 10 h, 8,338 nodes, 839,140 bonds): elastic at
+    1 m/s, fracturing at 50 m/s."""
+    wl = I.two_spheres(speed=speed)
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    for chunk in range(steps // 100):
+        sim.step(100)
+        ora.step(100)
+    assert_state_close(sim, ora, what=f"speed {speed}")
+    margin = ora.min_margin()
+    rp, col, br = sim.bonds()
+    _, _, bro = ora.bonds()
+    if margin > 1e-9:
+        assert np.array_equal(br, bro), f"margin {margin:.2e}"
+    if speed > 10:
+        assert bro.sum() > 0
+    assert np.array_equal(sim.get("damage"), ora.damage()[0]) or margin <= 1e-9
+
+
+def test_notched_plate_with_moving_wall(oracle_lib):
+    """Small double-notched plate hit by the moving wall patch: platen force 1e-6,
+    state 1e-9 after 1000 steps."""
+    h = 5e-4
+    wl = I.notched_plate(nx=40, ny=30, nz=6, h=h, notch_x=(10 * h, 30 * h), notch_len=15 * h,
+                         speed=32.0, steps=1000)
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    for _ in range(10):
+        sim.step(100)
+        ora.step(100)
+        fw = sim.get("wall_force")
+        fo, oo = ora.walls()
+        if np.abs(fo).max() > 0:
+            assert rel_inf(fw, fo) <= 1e-6
+        assert np.allclose(sim.get("wall_offset"), oo, rtol=1e-14, atol=0)
+    assert np.abs(ora.walls()[0]).max() > 0
+    assert_state_close(sim, ora, what="plate")
+
+
+def test_aggregate_between_platens(oracle_lib):
+    wl = I.grain_aggregate(n_grains=6, grid=(3, 2, 1), n_min=800, n_max=3000, seed=2,
+                           platen_speed=5.0, rebuild_every=10)
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    for _ in range(4):
+        sim.step(50)
+        ora.step(50)
+    assert_state_close(sim, ora, what="aggregate")
+    fw = sim.get("wall_force")
+    fo, _ = ora.walls()
+    assert rel_inf(fw, fo) <= 1e-6
+
+
+def test_energy_field_matches_oracle(oracle_lib):
+    wl = I.two_spheres(radius_cells=6, gap=0.0, speed=2.0)
+    wl.u0[0, wl.grain_begin[1]:] -= 1e-6
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    sim.step(20)
+    ora.step(20)
+    e = sim.get("energy")
+    eo = ora.energy()
+    for k, name in enumerate(["kinetic", "elastic", "contact", "gravity"]):
+        assert e[k] == pytest.approx(eo[name], rel=1e-9, abs=1e-30)
+
+
+def test_runs_are_bitwise_deterministic():
+    wl = I.two_spheres(radius_cells=6, speed=30.0, gap=0.0)
+    out = []
+    for _ in range(2):
+        sim = gpu_sim(wl)
+        sim.step(60)
+        out.append((sim.get("displacement"), sim.get("bond_broken")))
+        sim.close()
+    assert np.array_equal(out[0][0], out[1][0])
+    assert np.array_equal(out[0][1], out[1][1])
+
+
+def test_checkpoint_resume_is_bitwise():
+    from paper_2506_05362_amd import pd
+    wl = I.two_spheres(radius_cells=6, speed=30.0, gap=0.0, rebuild_every=7)
+    a = gpu_sim(wl)
+    a.step(25)
+    blob = a.get_state()
+    a.step(40)
+    b = gpu_sim(wl)
+    b.set_state(blob)
+    assert b.info()["step"] == 25
+    b.step(40)
+    assert np.array_equal(a.get("displacement"), b.get("displacement"))
+    assert np.array_equal(a.get("velocity"), b.get("velocity"))
+    assert np.array_equal(a.get("bond_broken"), b.get("bond_broken"))
+    bad = bytearray(blob)
+    bad[100] ^= 0xFF
+    with pytest.raises(pd.PDError) as e:
+        b.set_state(bytes(bad))
+    assert e.value.status == pd.PD_ERR_CORRUPT
+
+
+def test_call_order_and_argument_errors():
+    from paper_2506_05362_amd import pd
+    wl = I.two_spheres(radius_cells=3)
+    s = pd.Sim(wl, build=False)
+    assert s.step_status(1) == pd.PD_ERR_STATE
+    s.build_bonds()
+    with pytest.raises(pd.PDError) as e:
+        s.build_bonds()
+    assert e.value.status == pd.PD_ERR_STATE
+    assert s.step_status(-1) == pd.PD_ERR_INVALID
+    bad = I.two_spheres(radius_cells=3)
+    bad.X[0, 5] += 1e-6  # X no longer on the lattice
+    with pytest.raises(pd.PDError) as e:
+        pd.Sim(bad)
+    assert e.value.status == pd.PD_ERR_INVALID
+
+
+def test_wall_penetration_is_flagged():
+    from paper_2506_05362_amd import pd
+    h = 1e-4
+    wl = I.two_spheres(radius_cells=3)
+    Rc = wl.params.contact_radius
+    zmin = wl.X[2].min()
+    wl.walls = [I.Wall(normal=(0.0, 0.0, 1.0), offset=zmin + 1.5 * Rc)]
+    with pytest.raises(pd.PDError) as e:
+        pd.Sim(wl)
+    assert e.value.status == pd.PD_ERR_UNSTABLE
