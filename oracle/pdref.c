@@ -442,6 +442,16 @@ static void build_candidates(pdref* s) {
 /* force density at the current u                                           */
 /* ------------------------------------------------------------------------- */
 
+/* Bond stretch s = (|xi + eta| - |xi|) / |xi| (Sec. 3.1).  The numerator is
+   evaluated as (|xi+eta|^2 - |xi|^2) / (|xi+eta| + |xi|) with the squared
+   difference formed directly as eta . (2 xi + eta): the same quantity, without
+   the cancellation of two nearly equal rounded lengths (|eta| << |xi|). */
+static double stretch(const double xi[3], const double eta[3], double l0, double l) {
+  double dd = (eta[0] * (2.0 * xi[0] + eta[0]) + eta[1] * (2.0 * xi[1] + eta[1])) +
+              eta[2] * (2.0 * xi[2] + eta[2]);
+  return dd / (l0 * (l + l0));
+}
+
 /* returns nonzero when an instability was seen (NaN force, wall penetration) */
 static int eval_force(pdref* s) {
   const int64_t n = s->n;
@@ -466,7 +476,7 @@ static int eval_force(pdref* s) {
       }
       double l0 = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
       double l = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
-      double st = (l - l0) / l0;
+      double st = stretch(xi, eta, l0, l);
       int over = (s->flags & PDREF_ABS_STRETCH) ? (fabs(st) > s0) : (st > s0);
       if (over) {
         s->broken[e] = 1;
@@ -663,14 +673,15 @@ void pdref_energy_density(const pdref* s, double* W) {
     for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e) {
       if (s->broken[e]) continue;
       const int64_t j = s->col[e];
-      double xi[3], y[3];
+      double xi[3], eta[3], y[3];
       for (int q = 0; q < 3; ++q) {
         xi[q] = s->X[q * n + j] - s->X[q * n + i];
-        y[q] = xi[q] + (s->u[q * n + j] - s->u[q * n + i]);
+        eta[q] = s->u[q * n + j] - s->u[q * n + i];
+        y[q] = xi[q] + eta[q];
       }
       double l0 = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
       double l = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
-      double st = (l - l0) / l0;
+      double st = stretch(xi, eta, l0, l);
       /* micropotential 1/2 c s^2 |xi| per unit volume squared */
       acc += 0.5 * s->gc[g] * st * st * l0 * s->gV[s->grain_of[j]];
     }
