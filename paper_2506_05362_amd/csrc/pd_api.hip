@@ -48,7 +48,8 @@ struct pd_ctx {
   double *v = nullptr, *a = nullptr, *X = nullptr, *F = nullptr;
   uint8_t* fixed = nullptr;
   GrainC* grains = nullptr;
-  double* inv_len = nullptr;
+  StencilC* stencil = nullptr;
+  int32_t n_stencil = 0, node_bits = 31;
   double* Kn = nullptr;
   WallDev* walls = nullptr;
   double* wall_partial = nullptr;
@@ -58,7 +59,7 @@ struct pd_ctx {
   int64_t nslices = 0, padded = 0, nnz = 0;
   int32_t* rowlen = nullptr;
   int64_t* slice_off = nullptr;
-  int32_t* colE = nullptr;
+  uint32_t* colE = nullptr;
   uint64_t* maskE = nullptr;
   int32_t* intact = nullptr;
   // contact
@@ -178,7 +179,9 @@ StepArgs step_args(pd_ctx* c) {
   A.Fout = c->F;
   A.fixed = c->fixed;
   A.grains = c->grains;
-  A.inv_len = c->inv_len;
+  A.stencil = c->stencil;
+  A.n_stencil = c->n_stencil;
+  A.node_bits = c->node_bits;
   A.slice_off = c->slice_off;
   A.rowlen = c->rowlen;
   A.colE = c->colE;
@@ -394,10 +397,13 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     micro_constants(mt.bulk_modulus, mt.fracture_energy, delta, P.flags, &cc, &s0);
     GrainC& gc = c->grains_h[g];
     gc.V = h * h * h;
-    gc.cV = cc * gc.V;
-    gc.thr = h * h * (1.0 + s0) * (1.0 + s0);
-    gc.thr_lo = (P.flags & PD_FLAG_ABS_STRETCH) ? h * h * (1.0 - s0) * (1.0 - s0) : -1.0;
+    gc.cVih = cc * gc.V / h;
+    // break tests on |y|^2 - |xi|^2 against |xi|^2 ((1 +- s0)^2 - 1), |xi|^2 = h^2 |d|^2
+    gc.thr = h * h * s0 * (2.0 + s0);
+    gc.thr_lo = (P.flags & PD_FLAG_ABS_STRETCH) ? -h * h * s0 * (2.0 - s0) : -INFINITY;
     gc.h = h;
+    gc.h2x = 2.0 * h;
+    gc.hh = h * h;
     gc.inv_h = 1.0 / h;
     gc.rho = mt.density;
     for (int q = 0; q < 3; ++q) gc.origin[q] = grains->origin[q * G + g];
@@ -410,8 +416,24 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
       const double keff = 2.0 * ka * kb / (ka + kb);
       kn[(size_t)a * n_mat + b] = 18.0 * keff / (kPi * pow(P.contact_horizon, 5));
     }
-  std::vector<double> inv_len(kMaxD2 + 1, 0.0);
-  for (int d2 = 1; d2 <= kMaxD2; ++d2) inv_len[d2] = 1.0 / sqrt((double)d2);
+  // horizon stencil 0 < |d|^2 <= m^2 in lexicographic order; its index rides in
+  // the top bits of every column word
+  std::vector<StencilC> st;
+  for (int dx = -c->m; dx <= c->m; ++dx)
+    for (int dy = -c->m; dy <= c->m; ++dy)
+      for (int dz = -c->m; dz <= c->m; ++dz) {
+        const int d2 = dx * dx + dy * dy + dz * dz;
+        if (d2 == 0 || d2 > c->m * c->m) continue;
+        st.push_back(StencilC{(double)dx, (double)dy, (double)dz, (double)d2, sqrt((double)d2),
+                              1.0 / sqrt((double)d2)});
+      }
+  c->n_stencil = (int32_t)st.size();
+  int sbits = 0;
+  while ((1 << sbits) < c->n_stencil) ++sbits;
+  c->node_bits = 32 - sbits;
+  if (N > ((int64_t)1 << c->node_bits))
+    return fail(c, PD_ERR_UNSUPPORTED, "%lld nodes exceed the %d-bit node field of a column word at horizon factor %d",
+                (long long)N, c->node_bits, c->m);
   c->walls_h.resize(n_walls);
   for (int32_t w = 0; w < n_walls; ++w) c->walls_h[w] = to_dev(walls[w], 0, P.dt);
 
@@ -422,7 +444,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->a, 3 * N, "a"));
   TRY(alloc_n(c, &c->X, 3 * N, "X"));
   TRY(alloc_n(c, &c->grains, G, "grain constants"));
-  TRY(alloc_n(c, &c->inv_len, kMaxD2 + 1, "inverse lengths"));
+  TRY(alloc_n(c, &c->stencil, c->n_stencil, "stencil"));
   TRY(alloc_n(c, &c->Kn, (int64_t)n_mat * n_mat, "K_n"));
   TRY(alloc_n(c, &c->walls, kMaxWalls, "walls"));
   TRY(alloc_n(c, &c->step_d, 1, "step"));
@@ -431,7 +453,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(c->X, mesh->X, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->grains, c->grains_h.data(), sizeof(GrainC) * G, hipMemcpyHostToDevice, s));
-  HIPCHK(c, hipMemcpyAsync(c->inv_len, inv_len.data(), sizeof(double) * inv_len.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->stencil, st.data(), sizeof(StencilC) * st.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->Kn, kn.data(), sizeof(double) * kn.size(), hipMemcpyHostToDevice, s));
   if (n_walls)
     HIPCHK(c, hipMemcpyAsync(c->walls, c->walls_h.data(), sizeof(WallDev) * n_walls, hipMemcpyHostToDevice, s));
@@ -580,6 +602,7 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   B.cut_begin = cut_begin_d;
   B.stencil = stencil_d;
   B.n_stencil = (int32_t)stencil.size();
+  B.node_bits = c->node_bits;
   B.n = N;
   B.rowlen = c->rowlen;
   B.slice_off = c->slice_off;
@@ -750,7 +773,9 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       return deliver(host.data());
     }
     case PD_BOND_ROWPTR: case PD_BOND_COL: case PD_BOND_BROKEN: {
-      std::vector<int32_t> rl((size_t)N), col((size_t)c->padded);
+      std::vector<int32_t> rl((size_t)N);
+      std::vector<uint32_t> col((size_t)c->padded);
+      const uint32_t node_mask = (1u << c->node_bits) - 1u;
       std::vector<int64_t> so((size_t)c->nslices + 1);
       std::vector<uint64_t> mk((size_t)(c->padded / kWave));
       HIPCHK(c, hipMemcpyAsync(rl.data(), c->rowlen, 4 * N, hipMemcpyDeviceToHost, s));
@@ -766,7 +791,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
         if (f == PD_BOND_ROWPTR) reinterpret_cast<int64_t*>(host.data())[i] = e;
         for (int k = 0; k < rl[(size_t)i]; ++k, ++e) {
           const int64_t slot = so[(size_t)sl] + (int64_t)k * kWave + lane;
-          if (f == PD_BOND_COL) reinterpret_cast<int32_t*>(host.data())[e] = col[(size_t)slot];
+          if (f == PD_BOND_COL) reinterpret_cast<int32_t*>(host.data())[e] = (int32_t)(col[(size_t)slot] & node_mask);
           if (f == PD_BOND_BROKEN)
             host[(size_t)e] = (uint8_t)((mk[(size_t)(so[(size_t)sl] / kWave + k)] >> lane) & 1ull);
         }

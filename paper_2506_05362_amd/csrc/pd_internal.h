@@ -20,18 +20,26 @@ constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
 
-// per-grain constants, one 96-byte record
+// per-grain constants, one 112-byte record
 struct GrainC {
-  double cV;      // c * V (micromodulus times nodal volume of the same grain)
-  double thr;     // h^2 (1 + s0)^2: bond breaks when |y|^2 > thr * |d|^2
-  double thr_lo;  // h^2 (1 - s0)^2 with the |s| reading, else -1
-  double h, inv_h;
+  double cVih;    // c * V / h (micromodulus times nodal volume, over the lattice spacing)
+  double thr;     // h^2 s0 (2 + s0): bond breaks when |y|^2 - |xi|^2 > thr * |d|^2  (s > s0)
+  double thr_lo;  // -h^2 s0 (2 - s0) with the |s| reading (s < -s0), else -inf
+  double h, h2x, hh;  // h, 2h, h^2
+  double inv_h;
   double V;       // h^3
   double rho;
   double origin[3];
   int32_t mat;
   int32_t pad;
 };
+
+// one entry per horizon-stencil offset d (lexicographic order): lattice
+// offset, |d|^2, |d| and 1/|d| in lattice units (scaled by h in the kernels)
+struct StencilC {
+  double dx, dy, dz, d2, len, inv_len;
+};
+constexpr int kMaxStencil = 1024;
 
 struct WallDev {
   double n[3];
@@ -69,10 +77,12 @@ struct StepArgs {
   double* Fout;         // MODE_FORCE_ONLY output (SoA)
   const uint8_t* fixed;
   const GrainC* grains;
-  const double* inv_len;  // 1/sqrt(d2), d2 = 0..kMaxD2
+  const StencilC* stencil;  // [n_stencil]
+  int32_t n_stencil;
+  int32_t node_bits;        // column word = node | stencil_index << node_bits
   const int64_t* slice_off;
   const int32_t* rowlen;
-  const int32_t* colE;
+  const uint32_t* colE;
   uint64_t* maskE;
   int32_t* intact;
   const int32_t* cand_ptr;
@@ -103,10 +113,11 @@ struct BuildArgs {
   const int32_t* cut_begin;  // [G+1]
   const int32_t* stencil;    // [n_stencil] packed (dx+8) | (dy+8)<<8 | (dz+8)<<16, lexicographic
   int32_t n_stencil;
+  int32_t node_bits;
   int64_t n;
   int32_t* rowlen;
   int64_t* slice_off;
-  int32_t* colE;
+  uint32_t* colE;
   uint64_t* maskE;
   int64_t nslices;
 };

@@ -49,6 +49,14 @@ __device__ __forceinline__ double rsqrt_full(double x) {
   return fma(r * e, fma(0.375, e, 0.5), r);
 }
 
+// 1/x to full double precision: hardware estimate refined by r (1 + e + e^2),
+// e = 1 - x r.
+__device__ __forceinline__ double rcp_full(double x) {
+  const double r = __builtin_amdgcn_rcp(x);
+  const double e = fma(-x, r, 1.0);
+  return fma(r, fma(e, e, e), r);
+}
+
 // ---------------------------------------------------------------------------
 // bond family (Sec. 3.1) and bond removal (Sec. 6.3)
 // ---------------------------------------------------------------------------
@@ -170,7 +178,8 @@ __global__ __launch_bounds__(kBlock) void k_bond_fill(BuildArgs b) {
   const bool valid = i < b.n;
   const int64_t off = b.slice_off[s];
   const int W = (int)((b.slice_off[s + 1] - off) / kWave);
-  int32_t* col = b.colE + off + lane;
+  uint32_t* col = b.colE + off + lane;
+  const uint32_t node_mask = (1u << b.node_bits) - 1u;
   int len = 0;
   if (valid) {
     const double w = b.u[i].w;
@@ -179,22 +188,22 @@ __global__ __launch_bounds__(kBlock) void k_bond_fill(BuildArgs b) {
       const int j = lookup(b, g, p, b.stencil[k]);
       if (j < 0) continue;
       if (bond_cut(b, g, p, packed_ijk(b.u[j].w))) continue;
-      col[(int64_t)len * kWave] = j;
+      col[(int64_t)len * kWave] = (uint32_t)j | ((uint32_t)k << b.node_bits);
       ++len;
     }
-    // insertion sort (rows come out nearly sorted from the lexicographic stencil)
+    // insertion sort on the node index (rows come out nearly sorted)
     for (int k = 1; k < len; ++k) {
-      const int32_t x = col[(int64_t)k * kWave];
+      const uint32_t x = col[(int64_t)k * kWave];
       int q = k - 1;
-      while (q >= 0 && col[(int64_t)q * kWave] > x) {
+      while (q >= 0 && (col[(int64_t)q * kWave] & node_mask) > (x & node_mask)) {
         col[(int64_t)(q + 1) * kWave] = col[(int64_t)q * kWave];
         --q;
       }
       col[(int64_t)(q + 1) * kWave] = x;
     }
-    for (int k = len; k < W; ++k) col[(int64_t)k * kWave] = (int32_t)i;
+    for (int k = len; k < W; ++k) col[(int64_t)k * kWave] = (uint32_t)i;
   } else {
-    for (int k = 0; k < W; ++k) col[(int64_t)k * kWave] = 0;
+    for (int k = 0; k < W; ++k) col[(int64_t)k * kWave] = 0u;
   }
   uint64_t* mask = b.maskE + off / kWave;
   for (int k = 0; k < W; ++k) {
@@ -223,12 +232,12 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
-template <int MODE>
+template <int MODE, bool ABS>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
-  __shared__ double s_inv[kMaxD2 + 1];
+  extern __shared__ StencilC s_st[];
   __shared__ double s_wall[kSlicesPerBlock][kMaxWalls * 3];
   const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
-  if (tid <= kMaxD2) s_inv[tid] = A.inv_len[tid];
+  for (int k = tid; k < A.n_stencil; k += kBlock) s_st[k] = A.stencil[k];
   __syncthreads();
 
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -242,8 +251,10 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   const int pi = packed_ijk(ui.w);
   const int gi = valid ? packed_grain(ui.w) : 0;
   const GrainC* G = A.grains + gi;
-  const double h = G->h, inv_h = G->inv_h, cV = G->cV, thr = G->thr, thr_lo = G->thr_lo;
+  const double h = G->h, h2x = G->h2x, hh = G->hh, cVih = G->cVih, thr = G->thr;
+  const double thr_lo = G->thr_lo;
   const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
+  const uint32_t node_mask = (1u << A.node_bits) - 1u;
 
   double fx = 0.0, fy = 0.0, fz = 0.0;
   int nbroke = 0;
@@ -255,28 +266,30 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
     off = A.slice_off[slice];
     W = (int)((A.slice_off[slice + 1] - off) >> 6);
   }
-  const int32_t* cp = A.colE + off + lane;
+  const uint32_t* cp = A.colE + off + lane;
   uint64_t* mp = A.maskE + (off >> 6);
   for (int k = 0; k < W; ++k) {
-    const int j = cp[(int64_t)k * kWave];
+    const uint32_t cw = cp[(int64_t)k * kWave];
     const uint64_t mw = mp[k];
     bool brk = false;
     if (!((mw >> lane) & 1ull)) {
-      const double4 uj = A.ucur[j];
-      const int pj = packed_ijk(uj.w);
-      const int dx = unpack_x(pj) - ix, dy = unpack_y(pj) - iy, dz = unpack_z(pj) - iz;
-      const int d2 = dx * dx + dy * dy + dz * dz;
-      // y = xi + eta with xi = h * (ijk_j - ijk_i) exact inside the fma
-      const double yx = fma(h, (double)dx, uj.x - ui.x);
-      const double yy = fma(h, (double)dy, uj.y - ui.y);
-      const double yz = fma(h, (double)dz, uj.z - ui.z);
-      const double lsq = fma(yx, yx, fma(yy, yy, yz * yz));
-      const double d2f = (double)d2;
-      // s > s0  <=>  |y|^2 > (1+s0)^2 |xi|^2
-      brk = lsq > thr * d2f || lsq < thr_lo * d2f;
+      const double4 uj = A.ucur[cw & node_mask];
+      const StencilC& S = s_st[cw >> A.node_bits];
+      // eta = u_j - u_i; y = xi + eta and 2 xi + eta with xi = h d exact inside the fma
+      const double ex = uj.x - ui.x, ey = uj.y - ui.y, ez = uj.z - ui.z;
+      const double yx = fma(h, S.dx, ex), yy = fma(h, S.dy, ey), yz = fma(h, S.dz, ez);
+      const double tx = fma(h2x, S.dx, ex), ty = fma(h2x, S.dy, ey), tz = fma(h2x, S.dz, ez);
+      // |y|^2 - |xi|^2 = eta . (2 xi + eta): the stretch numerator without cancellation
+      const double d = fma(ex, tx, fma(ey, ty, ez * tz));
+      // s > s0  <=>  |y|^2 - |xi|^2 > |xi|^2 ((1 + s0)^2 - 1)
+      brk = d > thr * S.d2;
+      if (ABS) brk = brk || d < thr_lo * S.d2;
       if (!brk) {
-        // c s V / |y| = c V (1/|xi| - 1/|y|)
-        const double coef = cV * fma(s_inv[d2], inv_h, -rsqrt_full(lsq));
+        // c s V / |y| = c V d / (|xi| |y| (|y| + |xi|))
+        const double lsq = fma(hh, S.d2, d);
+        const double l = lsq * rsqrt_full(lsq);
+        const double q = rcp_full(fma(l, h * S.len, lsq));
+        const double coef = cVih * S.inv_len * d * q;
         fx = fma(coef, yx, fx);
         fy = fma(coef, yy, fy);
         fz = fma(coef, yz, fz);
@@ -474,16 +487,18 @@ __global__ __launch_bounds__(kBlock) void k_energy(StepArgs A, double* partial4)
     double w = 0.0;
     for (int k = 0; k < W; ++k) {
       if ((A.maskE[off / kWave + k] >> lane) & 1ull) continue;
-      const int j = A.colE[off + (int64_t)k * kWave + lane];
+      const int j = (int)(A.colE[off + (int64_t)k * kWave + lane] & ((1u << A.node_bits) - 1u));
       const double4 uj = A.ucur[j];
       const int pj = packed_ijk(uj.w);
       const int dx = unpack_x(pj) - unpack_x(pi), dy = unpack_y(pj) - unpack_y(pi),
                 dz = unpack_z(pj) - unpack_z(pi);
       const double xx = G->h * dx, xy = G->h * dy, xz = G->h * dz;
-      const double yx = xx + (uj.x - ui.x), yy = xy + (uj.y - ui.y), yz = xz + (uj.z - ui.z);
+      const double ex = uj.x - ui.x, ey = uj.y - ui.y, ez = uj.z - ui.z;
+      const double yx = xx + ex, yy = xy + ey, yz = xz + ez;
       const double l0 = sqrt(xx * xx + xy * xy + xz * xz), l = sqrt(yx * yx + yy * yy + yz * yz);
-      const double st = (l - l0) / l0;
-      w += 0.5 * G->cV * st * st * l0;  // micropotential times V_j
+      const double dd = ex * (2.0 * xx + ex) + ey * (2.0 * xy + ey) + ez * (2.0 * xz + ez);
+      const double st = dd / (l0 * (l + l0));
+      w += 0.5 * (G->cVih * G->h) * st * st * l0;  // micropotential times V_j
     }
     e[1] = 0.5 * V * w;
     if (A.cand_ptr != nullptr) {
@@ -772,12 +787,18 @@ int32_t step_grid_blocks(int64_t nslices) { return (int32_t)grid_for(nslices, kS
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
   const int32_t nb = step_grid_blocks(a.nslices);
   if (nb == 0) return hipSuccess;
-  if (mode == MODE_FIRST)
-    hipLaunchKernelGGL(k_step<MODE_FIRST>, dim3(nb), dim3(kBlock), 0, s, a);
-  else if (mode == MODE_STEP)
-    hipLaunchKernelGGL(k_step<MODE_STEP>, dim3(nb), dim3(kBlock), 0, s, a);
-  else
-    hipLaunchKernelGGL(k_step<MODE_FORCE_ONLY>, dim3(nb), dim3(kBlock), 0, s, a);
+  const size_t lds = sizeof(StencilC) * (size_t)a.n_stencil;
+  const bool abs_s = a.abs_stretch != 0;
+  if (mode == MODE_FIRST) {
+    if (abs_s) hipLaunchKernelGGL((k_step<MODE_FIRST, true>), dim3(nb), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_step<MODE_FIRST, false>), dim3(nb), dim3(kBlock), lds, s, a);
+  } else if (mode == MODE_STEP) {
+    if (abs_s) hipLaunchKernelGGL((k_step<MODE_STEP, true>), dim3(nb), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_step<MODE_STEP, false>), dim3(nb), dim3(kBlock), lds, s, a);
+  } else {
+    if (abs_s) hipLaunchKernelGGL((k_step<MODE_FORCE_ONLY, true>), dim3(nb), dim3(kBlock), lds, s, a);
+    else hipLaunchKernelGGL((k_step<MODE_FORCE_ONLY, false>), dim3(nb), dim3(kBlock), lds, s, a);
+  }
   return hipGetLastError();
 }
 

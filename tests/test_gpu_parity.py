@@ -112,7 +112,7 @@ def test_force_at_t0_with_prestrain(oracle_lib):
 def test_two_spheres_trajectory(oracle_lib, speed, steps):
     """The two-grain collision (radius 10 h, 8,338 nodes, 839,140 bonds): elastic at
     1 m/s, fracturing at 50 m/s."""
-    wl = I.two_spheres(speed=speed)
+    wl = I.two_spheres(speed=speed, rebuild_every=20 if speed < 10 else 5)
     sim = gpu_sim(wl)
     ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
     for chunk in range(steps // 100):
