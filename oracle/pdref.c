@@ -601,7 +601,8 @@ int32_t pdref_step(pdref* s, int64_t nsteps) {
     s->step += 1;
     advance_walls(s);
     if (s->step % s->rebuild_every == 0) {
-      if (skin_exceeded(s)) bad = 1;
+      /* the skin guard protects inter-grain pairs; a single grain has none to miss */
+      if (s->n_grains > 1 && skin_exceeded(s)) bad = 1;
       build_candidates(s);
     }
     /* new accelerations at the new positions, then the velocity update */

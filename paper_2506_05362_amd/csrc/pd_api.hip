@@ -69,10 +69,17 @@ struct pd_ctx {
           *bucket_fill = nullptr, *sorted = nullptr, *cand_ptr = nullptr, *cand = nullptr;
   uint32_t* cellh = nullptr;
   double* u_build = nullptr;
+  long long* gbox = nullptr;
+  int32_t *gpair_count = nullptr, *gpair = nullptr;
+  uint8_t* active = nullptr;
   int32_t* scan32 = nullptr;
   int64_t* scan64 = nullptr;
   double* energy_partial = nullptr;
   double* energy_out = nullptr;
+  // measurement hook
+  int timing = 0;
+  std::vector<hipEvent_t> ev_pool;
+  size_t ev_used = 0;
 };
 
 namespace {
@@ -221,6 +228,11 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.cand = c->cand;
   C.u_build = c->u_build;
   C.scan_scratch = c->scan32;
+  C.gbox = c->gbox;
+  C.gpair_count = c->gpair_count;
+  C.gpair = c->gpair;
+  C.active = c->active;
+  C.n_grains = c->n_grains;
   C.status = c->status;
   C.n = c->n;
   C.T = c->T;
@@ -237,11 +249,25 @@ pd_status enqueue_step(pd_ctx* c, int64_t s) {
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
     ContactArgs C = contact_args(c, nxt);
-    HIPCHK(c, launch_contact_rebuild(C, 1, c->stream));
+    // the skin guard protects inter-grain pairs; with one grain there are none to miss
+    HIPCHK(c, launch_contact_rebuild(C, c->n_grains > 1 ? 1 : 0, c->stream));
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (c->timing) {
+    while (c->ev_pool.size() < c->ev_used + 2) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->ev_pool.push_back(e);
+    }
+    e0 = c->ev_pool[c->ev_used];
+    e1 = c->ev_pool[c->ev_used + 1];
+    c->ev_used += 2;
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+  }
   HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+  if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
   HIPCHK(c, launch_wall_finalize(c->walls, c->wall_partial, step_grid_blocks(c->nslices), c->n_walls,
                                  c->step_d, 1, c->dt, c->stream));
   return PD_OK;
@@ -651,6 +677,10 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   TRY(alloc_n(c, &c->cand, c->capacity, "candidates"));
   TRY(alloc_n(c, &c->u_build, 3 * N, "positions at rebuild"));
   TRY(alloc_n(c, &c->scan32, scan_scratch_elems(std::max<int64_t>(T, N)), "scan scratch"));
+  TRY(alloc_n(c, &c->gbox, 6 * (int64_t)G, "grain boxes"));
+  TRY(alloc_n(c, &c->gpair_count, (int64_t)G + 1, "grain pair counts"));
+  TRY(alloc_n(c, &c->gpair, (int64_t)G * G, "grain pairs"));
+  TRY(alloc_n(c, &c->active, N, "active flags"));
   const int32_t nblocks = step_grid_blocks(c->nslices);
   TRY(alloc_n(c, &c->wall_partial, (int64_t)std::max(nblocks, 1) * 3 * std::max(c->n_walls, 1), "wall partials"));
 
@@ -674,6 +704,28 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
     c->step += 1;
   }
   return report_status(c);
+}
+
+pd_status pd_set_timing(pd_ctx* c, int32_t enable) {
+  if (!c) return PD_ERR_INVALID;
+  c->timing = enable != 0;
+  c->ev_used = 0;
+  return PD_OK;
+}
+
+pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
+  if (!c || !launches || !total_ms) return PD_ERR_INVALID;
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  double tot = 0.0;
+  for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
+    float ms = 0.0f;
+    HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
+    tot += ms;
+  }
+  *launches = (int64_t)(c->ev_used / 2);
+  *total_ms = tot;
+  c->ev_used = 0;
+  return PD_OK;
 }
 
 pd_status pd_info(pd_ctx* c, int64_t* out5) {
@@ -967,6 +1019,7 @@ void pd_destroy(pd_ctx* c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
   std::vector<void*> all = c->owned;
   for (void* p : all) dev_free(c, p);
   delete c;

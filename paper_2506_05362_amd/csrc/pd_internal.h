@@ -19,6 +19,7 @@ constexpr int kMaxWalls = 8;
 constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
+constexpr int kUnroll = 4;          // bond entries in flight per lane; slice widths are padded to it
 
 // per-grain constants, one 112-byte record
 struct GrainC {
@@ -135,6 +136,11 @@ struct ContactArgs {
   int32_t* cand;
   double* u_build;        // SoA
   int32_t* scan_scratch;  // >= scan_scratch_elems(max(T, N))
+  long long* gbox;        // [G][6] order-preserving encodings of min xyz, max xyz of p
+  int32_t* gpair_count;   // [G+1] (scanned in place)
+  int32_t* gpair;         // [G*G] other grains whose boxes come within the cutoff
+  uint8_t* active;        // [N] node within the cutoff of another grain's box
+  int32_t n_grains;
   uint32_t* status;
   int64_t n;
   uint32_t T;             // power of two

@@ -165,6 +165,7 @@ __global__ void k_slice_width(BuildArgs b) {
     const int64_t i = s * kWave + l;
     if (i < b.n) w = max(w, b.rowlen[i]);
   }
+  w = (w + kUnroll - 1) / kUnroll * kUnroll;
   b.slice_off[s] = (int64_t)w * kWave;
 }
 
@@ -236,7 +237,8 @@ template <int MODE, bool ABS>
 __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   extern __shared__ StencilC s_st[];
   __shared__ double s_wall[kSlicesPerBlock][kMaxWalls * 3];
-  const int tid = threadIdx.x, lane = tid & 63, wid = tid >> 6;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
   for (int k = tid; k < A.n_stencil; k += kBlock) s_st[k] = A.stencil[k];
   __syncthreads();
 
@@ -255,11 +257,17 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   const double thr_lo = G->thr_lo;
   const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
   const uint32_t node_mask = (1u << A.node_bits) - 1u;
+  const int node_bits = A.node_bits;
 
   double fx = 0.0, fy = 0.0, fz = 0.0;
   int nbroke = 0;
 
   // ---- peridynamic bonds with bond memory ----
+  // Slice width W is a multiple of kUnroll: the column words and broken-flag
+  // words of kUnroll entries are loaded first, then their kUnroll neighbour
+  // gathers, so each lane keeps several memory requests in flight.  Padding
+  // and broken entries are evaluated too (padding points at the node itself)
+  // and discarded by select, keeping the loop free of divergent branches.
   int64_t off = 0;
   int W = 0;
   if (slice_ok) {
@@ -268,38 +276,46 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   }
   const uint32_t* cp = A.colE + off + lane;
   uint64_t* mp = A.maskE + (off >> 6);
-  for (int k = 0; k < W; ++k) {
-    const uint32_t cw = cp[(int64_t)k * kWave];
-    const uint64_t mw = mp[k];
-    bool brk = false;
-    if (!((mw >> lane) & 1ull)) {
-      const double4 uj = A.ucur[cw & node_mask];
-      const StencilC& S = s_st[cw >> A.node_bits];
+  for (int k = 0; k < W; k += kUnroll) {
+    uint32_t cw[kUnroll];
+    uint64_t mw[kUnroll];
+    double4 uj[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      cw[u] = cp[(int64_t)(k + u) * kWave];
+      mw[u] = mp[k + u];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) uj[u] = A.ucur[cw[u] & node_mask];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const bool live = !((mw[u] >> lane) & 1ull);
+      const StencilC& S = s_st[cw[u] >> node_bits];
       // eta = u_j - u_i; y = xi + eta and 2 xi + eta with xi = h d exact inside the fma
-      const double ex = uj.x - ui.x, ey = uj.y - ui.y, ez = uj.z - ui.z;
+      const double ex = uj[u].x - ui.x, ey = uj[u].y - ui.y, ez = uj[u].z - ui.z;
       const double yx = fma(h, S.dx, ex), yy = fma(h, S.dy, ey), yz = fma(h, S.dz, ez);
       const double tx = fma(h2x, S.dx, ex), ty = fma(h2x, S.dy, ey), tz = fma(h2x, S.dz, ez);
       // |y|^2 - |xi|^2 = eta . (2 xi + eta): the stretch numerator without cancellation
       const double d = fma(ex, tx, fma(ey, ty, ez * tz));
       // s > s0  <=>  |y|^2 - |xi|^2 > |xi|^2 ((1 + s0)^2 - 1)
-      brk = d > thr * S.d2;
-      if (ABS) brk = brk || d < thr_lo * S.d2;
-      if (!brk) {
-        // c s V / |y| = c V d / (|xi| |y| (|y| + |xi|))
-        const double lsq = fma(hh, S.d2, d);
-        const double l = lsq * rsqrt_full(lsq);
-        const double q = rcp_full(fma(l, h * S.len, lsq));
-        const double coef = cVih * S.inv_len * d * q;
-        fx = fma(coef, yx, fx);
-        fy = fma(coef, yy, fy);
-        fz = fma(coef, yz, fz);
-      }
-    }
-    if (MODE != MODE_FORCE_ONLY) {
-      const uint64_t nb = __ballot(brk);
-      if (nb) {
-        if (lane == 0) mp[k] = mw | nb;
-        nbroke += brk ? 1 : 0;
+      bool over = d > thr * S.d2;
+      if (ABS) over = over || d < thr_lo * S.d2;
+      const bool brk = live && over;
+      // c s V / |y| = c V d / (|xi| |y| (|y| + |xi|))
+      const double lsq = fma(hh, S.d2, d);
+      const double l = lsq * rsqrt_full(lsq);
+      const double q = rcp_full(fma(l, h * S.len, lsq));
+      double coef = cVih * S.inv_len * d * q;
+      coef = (live && !over) ? coef : 0.0;
+      fx = fma(coef, yx, fx);
+      fy = fma(coef, yy, fy);
+      fz = fma(coef, yz, fz);
+      if (MODE != MODE_FORCE_ONLY) {
+        const uint64_t nb = __ballot(brk);
+        if (nb) {
+          if (lane == 0) mp[k + u] = mw[u] | nb;
+          nbroke += brk ? 1 : 0;
+        }
       }
     }
   }
@@ -550,9 +566,115 @@ __device__ __forceinline__ int cell_coord(double p, double inv_cell) {
   return (int)c;
 }
 
-__global__ void k_bin(ContactArgs c) {
+// Grain-box culling.  A pair (i, j) of different grains closer than the
+// cutoff needs p_i within the cutoff of grain(j)'s box and p_j within the
+// cutoff of grain(i)'s box, so only nodes within the cutoff of another grain's
+// box ("active" nodes) are binned and searched; the result is unchanged.
+
+__device__ __forceinline__ long long ord_key(double x) {
+  const long long b = __double_as_longlong(x);
+  return b ^ ((b >> 63) & 0x7fffffffffffffffll);
+}
+__device__ __forceinline__ double ord_val(long long k) {
+  return __longlong_as_double(k ^ ((k >> 63) & 0x7fffffffffffffffll));
+}
+
+__global__ void k_box_init(ContactArgs c) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 6 * (int64_t)c.n_grains) return;
+  c.gbox[t] = (t % 6) < 3 ? ord_key(INFINITY) : ord_key(-INFINITY);
+}
+
+__device__ __forceinline__ long long wave_min_ll(long long x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const long long y = __shfl_xor(x, o, kWave);
+    x = y < x ? y : x;
+  }
+  return x;
+}
+__device__ __forceinline__ long long wave_max_ll(long long x) {
+  for (int o = 32; o > 0; o >>= 1) {
+    const long long y = __shfl_xor(x, o, kWave);
+    x = y > x ? y : x;
+  }
+  return x;
+}
+
+__global__ __launch_bounds__(256) void k_box(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int lane = threadIdx.x & 63;
+  const bool valid = i < c.n;
+  long long k[6];
+  int g = -1;
+  if (valid) {
+    const double4 u = c.u[i];
+    g = packed_grain(u.w);
+    k[0] = k[3] = ord_key(c.X[i] + u.x);
+    k[1] = k[4] = ord_key(c.X[c.n + i] + u.y);
+    k[2] = k[5] = ord_key(c.X[2 * c.n + i] + u.z);
+  } else {
+    k[0] = k[1] = k[2] = ord_key(INFINITY);
+    k[3] = k[4] = k[5] = ord_key(-INFINITY);
+  }
+  // wavefronts inside one grain reduce first and issue 6 atomics
+  const int g0 = __shfl(g, 0, kWave);
+  const uint64_t same = __ballot(!valid || g == g0 || g < 0);
+  if (same == ~0ull && g0 >= 0) {
+    for (int q = 0; q < 3; ++q) k[q] = wave_min_ll(k[q]);
+    for (int q = 3; q < 6; ++q) k[q] = wave_max_ll(k[q]);
+    if (lane == 0)
+      for (int q = 0; q < 6; ++q)
+        q < 3 ? atomicMin(c.gbox + 6 * g0 + q, k[q]) : atomicMax(c.gbox + 6 * g0 + q, k[q]);
+  } else if (valid) {
+    for (int q = 0; q < 6; ++q)
+      q < 3 ? atomicMin(c.gbox + 6 * g + q, k[q]) : atomicMax(c.gbox + 6 * g + q, k[q]);
+  }
+}
+
+// grain boxes closer than the cutoff (one thread per grain, plain loop over the others)
+template <bool FILL>
+__global__ void k_box_pairs(ContactArgs c, double cut) {
+  const int a = blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= c.n_grains) return;
+  double alo[3], ahi[3];
+  for (int q = 0; q < 3; ++q) {
+    alo[q] = ord_val(c.gbox[6 * a + q]) - cut;
+    ahi[q] = ord_val(c.gbox[6 * a + 3 + q]) + cut;
+  }
+  int cnt = 0;
+  const int base = FILL ? c.gpair_count[a] : 0;
+  for (int b = 0; b < c.n_grains; ++b) {
+    if (b == a) continue;
+    bool ov = true;
+    for (int q = 0; q < 3; ++q)
+      ov = ov && ord_val(c.gbox[6 * b + q]) <= ahi[q] && ord_val(c.gbox[6 * b + 3 + q]) >= alo[q];
+    if (!ov) continue;
+    if (FILL) c.gpair[base + cnt] = b;
+    ++cnt;
+  }
+  if (!FILL) c.gpair_count[a] = cnt;
+}
+
+__global__ void k_active(ContactArgs c, double cut) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.n) return;
+  const double4 u = c.u[i];
+  const int g = packed_grain(u.w);
+  const double p[3] = {c.X[i] + u.x, c.X[c.n + i] + u.y, c.X[2 * c.n + i] + u.z};
+  uint8_t act = 0;
+  for (int e = c.gpair_count[g]; e < c.gpair_count[g + 1] && !act; ++e) {
+    const int b = c.gpair[e];
+    bool in = true;
+    for (int q = 0; q < 3; ++q)
+      in = in && p[q] >= ord_val(c.gbox[6 * b + q]) - cut && p[q] <= ord_val(c.gbox[6 * b + 3 + q]) + cut;
+    act = in ? 1 : 0;
+  }
+  c.active[i] = act;
+}
+
+__global__ void k_bin(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n || !c.active[i]) return;
   const double4 u = c.u[i];
   const int cx = cell_coord(c.X[i] + u.x, c.inv_cell);
   const int cy = cell_coord(c.X[c.n + i] + u.y, c.inv_cell);
@@ -567,7 +689,7 @@ __global__ void k_bin(ContactArgs c) {
 
 __global__ void k_scatter(ContactArgs c) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n) return;
+  if (i >= c.n || !c.active[i]) return;
   const uint32_t hsh = c.cellh[i];
   const int pos = c.bucket_start[hsh] + atomicAdd(c.bucket_fill + hsh, 1);
   c.sorted[pos] = (int32_t)i;
@@ -577,6 +699,10 @@ template <bool FILL>
 __global__ void k_candidates(ContactArgs c) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.n) return;
+  if (!c.active[i]) {
+    if (!FILL) c.cand_count[i] = 0;
+    return;
+  }
   const double4 ui = c.u[i];
   const int gi = packed_grain(ui.w);
   const int cx = c.cellc[3 * i], cy = c.cellc[3 * i + 1], cz = c.cellc[3 * i + 2];
@@ -813,11 +939,19 @@ hipError_t launch_wall_finalize(WallDev* walls, const double* partial, int32_t n
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const unsigned g = grid_for(c.n, 256);
+  const double cut = sqrt(c.cut2) * (1.0 + 1e-9) + 1e-300;  // boxes inflated by the cutoff
   hipError_t e;
   // clears by kernel (not memset nodes) so the sequence can live in a captured graph
   if ((e = launch_fill_i32(c.bucket_count, 0, (int64_t)c.T, s)) != hipSuccess) return e;
   if ((e = launch_fill_i32(c.bucket_fill, 0, (int64_t)c.T, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_skin, dim3(g), dim3(256), 0, s, c, check_skin);
+  hipLaunchKernelGGL(k_box_init, dim3(grid_for(6 * (int64_t)c.n_grains, 256)), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_box, dim3(g), dim3(256), 0, s, c);
+  const unsigned gg = grid_for(c.n_grains, 64);
+  hipLaunchKernelGGL(k_box_pairs<false>, dim3(gg), dim3(64), 0, s, c, cut);
+  if ((e = scan_i32(c.gpair_count, c.gpair_count, c.n_grains, c.scan_scratch, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_box_pairs<true>, dim3(gg), dim3(64), 0, s, c, cut);
+  hipLaunchKernelGGL(k_active, dim3(g), dim3(256), 0, s, c, cut);
   hipLaunchKernelGGL(k_bin, dim3(g), dim3(256), 0, s, c);
   if ((e = scan_i32(c.bucket_count, c.bucket_start, (int64_t)c.T, c.scan_scratch, s)) != hipSuccess)
     return e;

@@ -72,8 +72,8 @@ ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
 FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 EXPORTS = ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get", "pd_set_wall",
-           "pd_get_state", "pd_set_state", "pd_info", "pd_destroy", "pd_last_error",
-           "pd_status_string"]
+           "pd_get_state", "pd_set_state", "pd_info", "pd_set_timing", "pd_timing", "pd_destroy",
+           "pd_last_error", "pd_status_string"]
 
 
 def load_library(path: str = _LIB_PATH) -> C.CDLL:
@@ -94,13 +94,16 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_get_state.argtypes = [P, P, C.POINTER(C.c_int64)]
     L.pd_set_state.argtypes = [P, P, C.c_int64]
     L.pd_info.argtypes = [P, P]
+    L.pd_set_timing.argtypes = [P, C.c_int32]
+    L.pd_timing.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.pd_destroy.argtypes = [P]
     L.pd_last_error.argtypes = [P]
     L.pd_last_error.restype = C.c_char_p
     L.pd_status_string.argtypes = [C.c_int32]
     L.pd_status_string.restype = C.c_char_p
     for name in ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get",
-                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info"]:
+                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_set_timing",
+                 "pd_timing"]:
         getattr(L, name).restype = C.c_int32
     return L
 
@@ -274,6 +277,15 @@ class Sim:
         self._check(lib().pd_info(self.h, _ptr(o)))
         return dict(n_nodes=int(o[0]), nnz=int(o[1]), padded=int(o[2]), candidates=int(o[3]),
                     step=int(o[4]))
+
+    def set_timing(self, enable: bool):
+        self._check(lib().pd_set_timing(self.h, 1 if enable else 0))
+
+    def timing(self):
+        """(launches, total_ms) of the fused step kernel since timing was enabled."""
+        n, ms = C.c_int64(), C.c_double()
+        self._check(lib().pd_timing(self.h, C.byref(n), C.byref(ms)))
+        return n.value, ms.value
 
     def bonds(self):
         return self.get("bond_rowptr"), self.get("bond_col"), self.get("bond_broken")
