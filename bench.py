@@ -28,9 +28,9 @@ KERNEL_SRC = os.path.join(ROOT, "paper_2506_05362_amd", "csrc", "pd_kernels.hip"
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_notched_plate.json")
 
 # algorithmic bytes of the fused step kernel (per launch):
-#   per directed bond : 4 B column word + 1 bit broken flag
+#   per directed bond : 4 B column word (it also carries the bond-broken state)
 #   per node          : read u, v, a (72 B) + write u, v, a (72 B) + 4 B lattice/grain word
-BYTES_PER_BOND = 4.0 + 1.0 / 8.0
+BYTES_PER_BOND = 4.0
 BYTES_PER_NODE = 148.0
 
 
@@ -70,13 +70,14 @@ def cpu_baseline(wl, nnz_gpu: int, budget_s: float):
 
 
 def copy_probe():
-    """Plain device copies of known size, for scaling hardware byte counters."""
+    """Plain device kernels of known size, for scaling hardware byte counters:
+    a fill (writes 1 GiB) and a scale (reads 1 GiB, writes 1 GiB)."""
     import torch
     n = 1 << 27  # 1 GiB of float64
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
     for _ in range(3):
-        y.copy_(x)
+        torch.mul(x, 2.0, out=y)
     torch.cuda.synchronize()
     print(json.dumps({"copy_probe_bytes": 8 * n}), flush=True)
 

@@ -49,7 +49,8 @@ struct pd_ctx {
   uint8_t* fixed = nullptr;
   GrainC* grains = nullptr;
   StencilC* stencil = nullptr;
-  int32_t n_stencil = 0, node_bits = 31;
+  int32_t n_stencil = 0, n_classes = 1, node_bits = 31;
+  uint32_t sentinel_hi = 0;
   double* Kn = nullptr;
   WallDev* walls = nullptr;
   double* wall_partial = nullptr;
@@ -60,7 +61,7 @@ struct pd_ctx {
   int32_t* rowlen = nullptr;
   int64_t* slice_off = nullptr;
   uint32_t* colE = nullptr;
-  uint64_t* maskE = nullptr;
+  uint32_t* colOrig = nullptr;
   int32_t* intact = nullptr;
   // contact
   uint32_t T = 0;
@@ -188,11 +189,12 @@ StepArgs step_args(pd_ctx* c) {
   A.grains = c->grains;
   A.stencil = c->stencil;
   A.n_stencil = c->n_stencil;
+  A.n_classes = c->n_classes;
   A.node_bits = c->node_bits;
   A.slice_off = c->slice_off;
   A.rowlen = c->rowlen;
   A.colE = c->colE;
-  A.maskE = c->maskE;
+  A.sentinel_hi = c->sentinel_hi;
   A.intact = c->intact;
   A.cand_ptr = c->cand_ptr;
   A.cand = c->cand;
@@ -414,8 +416,9 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
       }
   }
 
-  // per-grain constants
+  // per-grain constants; grains sharing (h, material) share a stencil table
   c->grains_h.resize(G);
+  std::vector<std::pair<double, int32_t>> classes;
   for (int32_t g = 0; g < G; ++g) {
     const pd_material& mt = materials[grains->material[g]];
     const double h = grains->h[g], delta = P.horizon_factor * h;
@@ -426,14 +429,15 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     gc.cVih = cc * gc.V / h;
     // break tests on |y|^2 - |xi|^2 against |xi|^2 ((1 +- s0)^2 - 1), |xi|^2 = h^2 |d|^2
     gc.thr = h * h * s0 * (2.0 + s0);
-    gc.thr_lo = (P.flags & PD_FLAG_ABS_STRETCH) ? -h * h * s0 * (2.0 - s0) : -INFINITY;
+    gc.abs_ratio = (2.0 - s0) / (2.0 + s0);
     gc.h = h;
-    gc.h2x = 2.0 * h;
-    gc.hh = h * h;
-    gc.inv_h = 1.0 / h;
     gc.rho = mt.density;
     for (int q = 0; q < 3; ++q) gc.origin[q] = grains->origin[q * G + g];
     gc.mat = grains->material[g];
+    const std::pair<double, int32_t> key(h, gc.mat);
+    auto it = std::find(classes.begin(), classes.end(), key);
+    gc.cls = (int32_t)(it - classes.begin());
+    if (it == classes.end()) classes.push_back(key);
   }
   std::vector<double> kn((size_t)n_mat * n_mat);
   for (int32_t a = 0; a < n_mat; ++a)
@@ -444,19 +448,41 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     }
   // horizon stencil 0 < |d|^2 <= m^2 in lexicographic order; its index rides in
   // the top bits of every column word
-  std::vector<StencilC> st;
+  std::vector<int> sd;
   for (int dx = -c->m; dx <= c->m; ++dx)
     for (int dy = -c->m; dy <= c->m; ++dy)
       for (int dz = -c->m; dz <= c->m; ++dz) {
         const int d2 = dx * dx + dy * dy + dz * dz;
         if (d2 == 0 || d2 > c->m * c->m) continue;
-        st.push_back(StencilC{(double)dx, (double)dy, (double)dz, (double)d2, sqrt((double)d2),
-                              1.0 / sqrt((double)d2)});
+        sd.push_back(dx);
+        sd.push_back(dy);
+        sd.push_back(dz);
       }
-  c->n_stencil = (int32_t)st.size();
+  c->n_stencil = (int32_t)(sd.size() / 3);
+  c->n_classes = (int32_t)classes.size();
+  if ((int64_t)c->n_classes * (c->n_stencil + 1) * (int64_t)sizeof(StencilC) > kMaxLdsTables)
+    return fail(c, PD_ERR_UNSUPPORTED, "%d distinct (h, material) classes exceed the stencil-table space",
+                c->n_classes);
+  std::vector<StencilC> st;
+  for (int32_t cl = 0; cl < c->n_classes; ++cl) {
+    const double h = classes[(size_t)cl].first;
+    const pd_material& mt = materials[classes[(size_t)cl].second];
+    double cc, s0;
+    micro_constants(mt.bulk_modulus, mt.fracture_energy, P.horizon_factor * h, P.flags, &cc, &s0);
+    const double cV = cc * h * h * h;
+    for (int32_t k = 0; k < c->n_stencil; ++k) {
+      const double d2 = (double)(sd[3 * k] * sd[3 * k] + sd[3 * k + 1] * sd[3 * k + 1] + sd[3 * k + 2] * sd[3 * k + 2]);
+      const double l0 = h * sqrt(d2), l0sq = h * h * d2;
+      st.push_back(StencilC{h * sd[3 * k], h * sd[3 * k + 1], h * sd[3 * k + 2], l0sq * s0 * (2.0 + s0),
+                            1.0 / l0sq, cV / l0, l0, l0sq});
+    }
+    // zero-force class: xi = 0, x = 0, c V / |xi| = 0 (broken bonds, padding)
+    st.push_back(StencilC{0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 1.0});
+  }
   int sbits = 0;
-  while ((1 << sbits) < c->n_stencil) ++sbits;
+  while ((1 << sbits) < c->n_stencil + 1) ++sbits;
   c->node_bits = 32 - sbits;
+  c->sentinel_hi = (uint32_t)c->n_stencil << c->node_bits;
   if (N > ((int64_t)1 << c->node_bits))
     return fail(c, PD_ERR_UNSUPPORTED, "%lld nodes exceed the %d-bit node field of a column word at horizon factor %d",
                 (long long)N, c->node_bits, c->m);
@@ -470,7 +496,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->a, 3 * N, "a"));
   TRY(alloc_n(c, &c->X, 3 * N, "X"));
   TRY(alloc_n(c, &c->grains, G, "grain constants"));
-  TRY(alloc_n(c, &c->stencil, c->n_stencil, "stencil"));
+  TRY(alloc_n(c, &c->stencil, (int64_t)st.size(), "stencil tables"));
   TRY(alloc_n(c, &c->Kn, (int64_t)n_mat * n_mat, "K_n"));
   TRY(alloc_n(c, &c->walls, kMaxWalls, "walls"));
   TRY(alloc_n(c, &c->step_d, 1, "step"));
@@ -629,6 +655,7 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   B.stencil = stencil_d;
   B.n_stencil = (int32_t)stencil.size();
   B.node_bits = c->node_bits;
+  B.sentinel_hi = c->sentinel_hi;
   B.n = N;
   B.rowlen = c->rowlen;
   B.slice_off = c->slice_off;
@@ -640,9 +667,9 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   HIPCHK(c, hipMemcpyAsync(&c->padded, c->slice_off + c->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
   TRY(alloc_n(c, &c->colE, c->padded, "bond columns"));
-  TRY(alloc_n(c, &c->maskE, c->padded / kWave, "broken masks"));
+  TRY(alloc_n(c, &c->colOrig, c->padded, "bond columns as built"));
   B.colE = c->colE;
-  B.maskE = c->maskE;
+  B.colOrig = c->colOrig;
   HIPCHK(c, launch_bond_fill(B, s));
   HIPCHK(c, hipMemcpyAsync(c->intact, c->rowlen, sizeof(int32_t) * N, hipMemcpyDeviceToDevice, s));
   {
@@ -829,23 +856,21 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       std::vector<uint32_t> col((size_t)c->padded);
       const uint32_t node_mask = (1u << c->node_bits) - 1u;
       std::vector<int64_t> so((size_t)c->nslices + 1);
-      std::vector<uint64_t> mk((size_t)(c->padded / kWave));
       HIPCHK(c, hipMemcpyAsync(rl.data(), c->rowlen, 4 * N, hipMemcpyDeviceToHost, s));
       HIPCHK(c, hipMemcpyAsync(so.data(), c->slice_off, 8 * (c->nslices + 1), hipMemcpyDeviceToHost, s));
-      if (f != PD_BOND_ROWPTR) {
+      if (f == PD_BOND_COL)
+        HIPCHK(c, hipMemcpyAsync(col.data(), c->colOrig, 4 * c->padded, hipMemcpyDeviceToHost, s));
+      if (f == PD_BOND_BROKEN)
         HIPCHK(c, hipMemcpyAsync(col.data(), c->colE, 4 * c->padded, hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipMemcpyAsync(mk.data(), c->maskE, 8 * (c->padded / kWave), hipMemcpyDeviceToHost, s));
-      }
       HIPCHK(c, hipStreamSynchronize(s));
       int64_t e = 0;
       for (int64_t i = 0; i < N; ++i) {
         const int64_t sl = i / kWave, lane = i % kWave;
         if (f == PD_BOND_ROWPTR) reinterpret_cast<int64_t*>(host.data())[i] = e;
         for (int k = 0; k < rl[(size_t)i]; ++k, ++e) {
-          const int64_t slot = so[(size_t)sl] + (int64_t)k * kWave + lane;
-          if (f == PD_BOND_COL) reinterpret_cast<int32_t*>(host.data())[e] = (int32_t)(col[(size_t)slot] & node_mask);
-          if (f == PD_BOND_BROKEN)
-            host[(size_t)e] = (uint8_t)((mk[(size_t)(so[(size_t)sl] / kWave + k)] >> lane) & 1ull);
+          const uint32_t w = col[(size_t)(so[(size_t)sl] + (int64_t)k * kWave + lane)];
+          if (f == PD_BOND_COL) reinterpret_cast<int32_t*>(host.data())[e] = (int32_t)(w & node_mask);
+          if (f == PD_BOND_BROKEN) host[(size_t)e] = (uint8_t)((w & ~node_mask) == c->sentinel_hi);
         }
       }
       if (f == PD_BOND_ROWPTR) reinterpret_cast<int64_t*>(host.data())[N] = e;
@@ -917,13 +942,13 @@ pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
 }
 
 // checkpoint layout: header[8] (magic, n, padded, n_walls, step, cur, nnz, crc-less size),
-// then u4[cur], u4[cur^1], v, a, maskE, intact, u_build, walls, crc32
+// then u4[cur], u4[cur^1], v, a, live column words, intact, u_build, walls, crc32
 pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   if (!c || !bytes) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   const int64_t N = c->n;
-  const int64_t words = c->padded / kWave;
-  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 8 * words + 4 * N + 24 * N +
+  const int64_t words = c->padded;
+  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
                        (int64_t)sizeof(WallDev) * c->n_walls;
   const int64_t total = body + 4;
   if (!blob) {
@@ -945,7 +970,7 @@ pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   TRY(grab(c->u4[c->cur ^ 1], 32 * N));
   TRY(grab(c->v, 24 * N));
   TRY(grab(c->a, 24 * N));
-  TRY(grab(c->maskE, 8 * words));
+  TRY(grab(c->colE, 4 * words));
   TRY(grab(c->intact, 4 * N));
   TRY(grab(c->u_build, 24 * N));
   TRY(grab(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));
@@ -963,8 +988,8 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   if (bytes < 68) return fail(c, PD_ERR_CORRUPT, "checkpoint too short");
   int64_t hdr[8];
   memcpy(hdr, p, sizeof hdr);
-  const int64_t N = c->n, words = c->padded / kWave;
-  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 8 * words + 4 * N + 24 * N +
+  const int64_t N = c->n, words = c->padded;
+  const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
                        (int64_t)sizeof(WallDev) * c->n_walls;
   if (hdr[0] != (int64_t)kMagic || hdr[1] != N || hdr[2] != c->padded || hdr[3] != c->n_walls ||
       hdr[6] != c->nnz || hdr[7] != body || bytes != body + 4)
@@ -984,7 +1009,7 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   TRY(put(c->u4[1], 32 * N));
   TRY(put(c->v, 24 * N));
   TRY(put(c->a, 24 * N));
-  TRY(put(c->maskE, 8 * words));
+  TRY(put(c->colE, 4 * words));
   TRY(put(c->intact, 4 * N));
   TRY(put(c->u_build, 24 * N));
   TRY(put(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));

@@ -19,27 +19,38 @@ constexpr int kMaxWalls = 8;
 constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
-constexpr int kUnroll = 4;          // bond entries in flight per lane; slice widths are padded to it
+#ifndef PD_BOND_UNROLL
+#define PD_BOND_UNROLL 4
+#endif
+constexpr int kUnroll = PD_BOND_UNROLL;  // bond entries in flight per lane; slice widths are padded to it
 
-// per-grain constants, one 112-byte record
+// per-grain constants
 struct GrainC {
   double cVih;    // c * V / h (micromodulus times nodal volume, over the lattice spacing)
   double thr;     // h^2 s0 (2 + s0): bond breaks when |y|^2 - |xi|^2 > thr * |d|^2  (s > s0)
-  double thr_lo;  // -h^2 s0 (2 - s0) with the |s| reading (s < -s0), else -inf
-  double h, h2x, hh;  // h, 2h, h^2
-  double inv_h;
+  double abs_ratio;  // (2 - s0) / (2 + s0): with the |s| reading a bond also breaks when
+                     // |y|^2 - |xi|^2 < -abs_ratio * thr * |d|^2  (s < -s0)
+  double h;
   double V;       // h^3
   double rho;
   double origin[3];
   int32_t mat;
-  int32_t pad;
+  int32_t cls;    // index of the (h, material) stencil table
 };
 
-// one entry per horizon-stencil offset d (lexicographic order): lattice
-// offset, |d|^2, |d| and 1/|d| in lattice units (scaled by h in the kernels)
+// One row per horizon-stencil offset d (lexicographic order) and per
+// (h, material) class, with every constant of the bond law folded in:
+// xi = h d, the break threshold on |y|^2 - |xi|^2, 1/|xi|^2, c V / |xi|,
+// |xi| and |xi|^2.  The last row of each class is the zero-force class used by
+// broken bonds and padding.
 struct StencilC {
-  double dx, dy, dz, d2, len, inv_len;
+  double hx, hy, hz;  // xi
+  double thr_d;       // |xi|^2 ((1 + s0)^2 - 1)
+  double inv_l0sq;    // 1 / |xi|^2
+  double civ;         // c V / |xi|
+  double l0, l0sq;    // |xi|, |xi|^2
 };
+constexpr int kMaxLdsTables = 48 * 1024;  // bytes of stencil tables a workgroup may stage
 constexpr int kMaxStencil = 1024;
 
 struct WallDev {
@@ -78,13 +89,14 @@ struct StepArgs {
   double* Fout;         // MODE_FORCE_ONLY output (SoA)
   const uint8_t* fixed;
   const GrainC* grains;
-  const StencilC* stencil;  // [n_stencil]
+  const StencilC* stencil;  // [n_classes][n_stencil + 1]
   int32_t n_stencil;
-  int32_t node_bits;        // column word = node | stencil_index << node_bits
+  int32_t n_classes;
+  int32_t node_bits;        // column word = node | stencil_class << node_bits
+  uint32_t sentinel_hi;     // zero-force class << node_bits (broken bonds and padding)
   const int64_t* slice_off;
   const int32_t* rowlen;
-  const uint32_t* colE;
-  uint64_t* maskE;
+  uint32_t* colE;           // live column words; a broken bond becomes node_i | sentinel_hi
   int32_t* intact;
   const int32_t* cand_ptr;
   const int32_t* cand;
@@ -115,11 +127,12 @@ struct BuildArgs {
   const int32_t* stencil;    // [n_stencil] packed (dx+8) | (dy+8)<<8 | (dz+8)<<16, lexicographic
   int32_t n_stencil;
   int32_t node_bits;
+  uint32_t sentinel_hi;
   int64_t n;
   int32_t* rowlen;
   int64_t* slice_off;
   uint32_t* colE;
-  uint64_t* maskE;
+  uint32_t* colOrig;         // column words as built (kept for output)
   int64_t nslices;
 };
 

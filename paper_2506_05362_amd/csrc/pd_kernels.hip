@@ -9,9 +9,11 @@
 //   bonds  : sliced-ELL (SELL-64) CSR.  Slice s = nodes [64 s, 64 s + 64) (one
 //            wavefront); entry k of lane l sits at colE[slice_off[s] + 64 k + l],
 //            so the column loads of a wavefront are one coalesced 256-byte read.
-//            The broken flags of entry k of a slice are one 64-bit word
-//            maskE[slice_off[s]/64 + k] (bit l = lane l); padding entries are
-//            permanently set so they are skipped like broken bonds.
+//            A column word is node_j | class << node_bits, class = index of the
+//            lattice offset in the horizon stencil.  Bond memory lives in the
+//            word itself: a bond that breaks is rewritten to node_i with the
+//            zero-force class, which is also what padding entries hold, so the
+//            step kernel needs no separate broken-flag reads.
 //
 // Each lane owns one node and evaluates its row in order (gather formulation,
 // Sec. 3.1 eq. (peri-damage) with nodal quadrature, Sec. 6.1): no atomics, so
@@ -180,6 +182,7 @@ __global__ __launch_bounds__(kBlock) void k_bond_fill(BuildArgs b) {
   const int64_t off = b.slice_off[s];
   const int W = (int)((b.slice_off[s + 1] - off) / kWave);
   uint32_t* col = b.colE + off + lane;
+  uint32_t* orig = b.colOrig + off + lane;
   const uint32_t node_mask = (1u << b.node_bits) - 1u;
   int len = 0;
   if (valid) {
@@ -202,15 +205,11 @@ __global__ __launch_bounds__(kBlock) void k_bond_fill(BuildArgs b) {
       }
       col[(int64_t)(q + 1) * kWave] = x;
     }
-    for (int k = len; k < W; ++k) col[(int64_t)k * kWave] = (uint32_t)i;
+    for (int k = len; k < W; ++k) col[(int64_t)k * kWave] = (uint32_t)i | b.sentinel_hi;
   } else {
-    for (int k = 0; k < W; ++k) col[(int64_t)k * kWave] = 0u;
+    for (int k = 0; k < W; ++k) col[(int64_t)k * kWave] = b.sentinel_hi;
   }
-  uint64_t* mask = b.maskE + off / kWave;
-  for (int k = 0; k < W; ++k) {
-    const uint64_t pad = __ballot(!valid || k >= len);
-    if (lane == 0) mask[k] = pad;
-  }
+  for (int k = 0; k < W; ++k) orig[(int64_t)k * kWave] = col[(int64_t)k * kWave];
 }
 
 // ---------------------------------------------------------------------------
@@ -233,13 +232,35 @@ __device__ __forceinline__ double wave_sum(double x) {
   return x;
 }
 
+#ifndef PD_STEP_WAVES_PER_EU
+#define PD_STEP_WAVES_PER_EU 1
+#endif
+
+// 1 - (1 + x)^(-1/2) = x * sum_k (-1)^k a_{k+1} x^k with a_k = C(2k, k) / 4^k.
+// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange.
+constexpr double kPolyRange = 0.02;
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) {
+  double p = -46189.0 / 262144.0;
+  p = fma(p, x, 12155.0 / 65536.0);
+  p = fma(p, x, -6435.0 / 32768.0);
+  p = fma(p, x, 429.0 / 2048.0);
+  p = fma(p, x, -231.0 / 1024.0);
+  p = fma(p, x, 63.0 / 256.0);
+  p = fma(p, x, -35.0 / 128.0);
+  p = fma(p, x, 5.0 / 16.0);
+  p = fma(p, x, -3.0 / 8.0);
+  return fma(p, x, 0.5);
+}
+
 template <int MODE, bool ABS>
-__global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
+__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PD_STEP_WAVES_PER_EU)))
+void k_step(StepArgs A) {
   extern __shared__ StencilC s_st[];
   __shared__ double s_wall[kSlicesPerBlock][kMaxWalls * 3];
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  for (int k = tid; k < A.n_stencil; k += kBlock) s_st[k] = A.stencil[k];
+  const int rows = A.n_classes * (A.n_stencil + 1);
+  for (int k = tid; k < rows; k += kBlock) s_st[k] = A.stencil[k];
   __syncthreads();
 
   const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
@@ -253,8 +274,8 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   const int pi = packed_ijk(ui.w);
   const int gi = valid ? packed_grain(ui.w) : 0;
   const GrainC* G = A.grains + gi;
-  const double h = G->h, h2x = G->h2x, hh = G->hh, cVih = G->cVih, thr = G->thr;
-  const double thr_lo = G->thr_lo;
+  const double h = G->h;
+  const double abs_ratio = G->abs_ratio;
   const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
   const uint32_t node_mask = (1u << A.node_bits) - 1u;
   const int node_bits = A.node_bits;
@@ -263,59 +284,69 @@ __global__ __launch_bounds__(kBlock) void k_step(StepArgs A) {
   int nbroke = 0;
 
   // ---- peridynamic bonds with bond memory ----
-  // Slice width W is a multiple of kUnroll: the column words and broken-flag
-  // words of kUnroll entries are loaded first, then their kUnroll neighbour
-  // gathers, so each lane keeps several memory requests in flight.  Padding
-  // and broken entries are evaluated too (padding points at the node itself)
-  // and discarded by select, keeping the loop free of divergent branches.
+  // Slice width W is a multiple of kUnroll: the column words of kUnroll entries
+  // are loaded one iteration ahead, then their kUnroll neighbour gathers, so
+  // each lane keeps several memory requests in flight.  Broken bonds and
+  // padding carry the zero-force class and point at the node itself, so every
+  // entry is evaluated the same way.
+  //
+  // Bond law (Sec. 3.1): the force on i is c s V_j y/|y|, y = xi + eta, and
+  //   c V s / |y| = (c V / |xi|) g,   g = 1 - |xi|/|y| = 1 - (1 + x)^(-1/2),
+  //   x = (|y|^2 - |xi|^2) / |xi|^2,   |y|^2 - |xi|^2 = eta . (2 xi + eta).
+  // g comes from its power series when |x| <= kPolyRange (no square root or
+  // division), else from g = (|y|^2 - |xi|^2) / (|y| (|y| + |xi|)); neither
+  // form subtracts nearly equal numbers.
   int64_t off = 0;
   int W = 0;
   if (slice_ok) {
     off = A.slice_off[slice];
     W = (int)((A.slice_off[slice + 1] - off) >> 6);
   }
-  const uint32_t* cp = A.colE + off + lane;
-  uint64_t* mp = A.maskE + (off >> 6);
+  uint32_t* cp = A.colE + off + lane;
+  const char* ubase = reinterpret_cast<const char*>(A.ucur);
+  const char* tbase = reinterpret_cast<const char*>(s_st) +
+                      (uint32_t)G->cls * (uint32_t)(A.n_stencil + 1) * (uint32_t)sizeof(StencilC);
+  const uint32_t mine = (uint32_t)(valid ? i : 0) | A.sentinel_hi;
+  uint32_t cn[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) cn[u] = W > 0 ? cp[u * kWave] : mine;
   for (int k = 0; k < W; k += kUnroll) {
     uint32_t cw[kUnroll];
-    uint64_t mw[kUnroll];
     double4 uj[kUnroll];
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      cw[u] = cp[(int64_t)(k + u) * kWave];
-      mw[u] = mp[k + u];
+    for (int u = 0; u < kUnroll; ++u) cw[u] = cn[u];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      uj[u] = *reinterpret_cast<const double4*>(ubase + ((cw[u] & node_mask) << 5));
+    if (k + kUnroll < W) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) cn[u] = cp[(k + kUnroll + u) * kWave];
     }
 #pragma unroll
-    for (int u = 0; u < kUnroll; ++u) uj[u] = A.ucur[cw[u] & node_mask];
-#pragma unroll
     for (int u = 0; u < kUnroll; ++u) {
-      const bool live = !((mw[u] >> lane) & 1ull);
-      const StencilC& S = s_st[cw[u] >> node_bits];
-      // eta = u_j - u_i; y = xi + eta and 2 xi + eta with xi = h d exact inside the fma
+      const StencilC& S =
+          *reinterpret_cast<const StencilC*>(tbase + (cw[u] >> node_bits) * (uint32_t)sizeof(StencilC));
       const double ex = uj[u].x - ui.x, ey = uj[u].y - ui.y, ez = uj[u].z - ui.z;
-      const double yx = fma(h, S.dx, ex), yy = fma(h, S.dy, ey), yz = fma(h, S.dz, ez);
-      const double tx = fma(h2x, S.dx, ex), ty = fma(h2x, S.dy, ey), tz = fma(h2x, S.dz, ez);
-      // |y|^2 - |xi|^2 = eta . (2 xi + eta): the stretch numerator without cancellation
-      const double d = fma(ex, tx, fma(ey, ty, ez * tz));
+      const double yx = S.hx + ex, yy = S.hy + ey, yz = S.hz + ez;  // y = xi + eta
+      // |y|^2 - |xi|^2 = eta . (2 xi + eta)
+      const double d = fma(ex, yx + S.hx, fma(ey, yy + S.hy, ez * (yz + S.hz)));
       // s > s0  <=>  |y|^2 - |xi|^2 > |xi|^2 ((1 + s0)^2 - 1)
-      bool over = d > thr * S.d2;
-      if (ABS) over = over || d < thr_lo * S.d2;
-      const bool brk = live && over;
-      // c s V / |y| = c V d / (|xi| |y| (|y| + |xi|))
-      const double lsq = fma(hh, S.d2, d);
-      const double l = lsq * rsqrt_full(lsq);
-      const double q = rcp_full(fma(l, h * S.len, lsq));
-      double coef = cVih * S.inv_len * d * q;
-      coef = (live && !over) ? coef : 0.0;
+      bool over = d > S.thr_d;
+      if (ABS) over = over || d < -abs_ratio * S.thr_d;
+      const double x = d * S.inv_l0sq;
+      double g = x * one_minus_rsqrt1p_over_x(x);
+      if (!(fabs(x) <= kPolyRange)) {
+        const double lsq = S.l0sq + d;
+        const double l = lsq * rsqrt_full(lsq);
+        g = d * rcp_full(fma(l, S.l0, lsq));
+      }
+      const double coef = over ? 0.0 : S.civ * g;
       fx = fma(coef, yx, fx);
       fy = fma(coef, yy, fy);
       fz = fma(coef, yz, fz);
-      if (MODE != MODE_FORCE_ONLY) {
-        const uint64_t nb = __ballot(brk);
-        if (nb) {
-          if (lane == 0) mp[k + u] = mw[u] | nb;
-          nbroke += brk ? 1 : 0;
-        }
+      if (MODE != MODE_FORCE_ONLY && over) {
+        cp[(k + u) * kWave] = mine;  // the bond stays broken from now on
+        ++nbroke;
       }
     }
   }
@@ -502,8 +533,9 @@ __global__ __launch_bounds__(kBlock) void k_energy(StepArgs A, double* partial4)
     const int W = (int)((A.slice_off[s + 1] - off) / kWave);
     double w = 0.0;
     for (int k = 0; k < W; ++k) {
-      if ((A.maskE[off / kWave + k] >> lane) & 1ull) continue;
-      const int j = (int)(A.colE[off + (int64_t)k * kWave + lane] & ((1u << A.node_bits) - 1u));
+      const uint32_t cw = A.colE[off + (int64_t)k * kWave + lane];
+      if ((cw & ~((1u << A.node_bits) - 1u)) == A.sentinel_hi) continue;  // broken or padding
+      const int j = (int)(cw & ((1u << A.node_bits) - 1u));
       const double4 uj = A.ucur[j];
       const int pj = packed_ijk(uj.w);
       const int dx = unpack_x(pj) - unpack_x(pi), dy = unpack_y(pj) - unpack_y(pi),
@@ -913,7 +945,7 @@ int32_t step_grid_blocks(int64_t nslices) { return (int32_t)grid_for(nslices, kS
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
   const int32_t nb = step_grid_blocks(a.nslices);
   if (nb == 0) return hipSuccess;
-  const size_t lds = sizeof(StencilC) * (size_t)a.n_stencil;
+  const size_t lds = sizeof(StencilC) * (size_t)(a.n_stencil + 1) * (size_t)a.n_classes;
   const bool abs_s = a.abs_stretch != 0;
   if (mode == MODE_FIRST) {
     if (abs_s) hipLaunchKernelGGL((k_step<MODE_FIRST, true>), dim3(nb), dim3(kBlock), lds, s, a);
