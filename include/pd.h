@@ -86,7 +86,9 @@ typedef struct {
 } pd_mesh;
 
 enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 */
-       PD_FLAG_ABS_STRETCH = 2    /* break on |s| > s0 instead of s > s0 */ };
+       PD_FLAG_ABS_STRETCH = 2,   /* break on |s| > s0 instead of s > s0 */
+       PD_FLAG_NO_GRAPH = 4       /* launch every step's kernels directly instead of replaying
+                                     a captured HIP graph of rebuild_every steps */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with
@@ -151,7 +153,9 @@ typedef enum {
 } pd_field;
 
 /* Create a context: validates and copies the problem to the device.
-   materials[n_mat]; walls[n_walls] (may be NULL when 0); stream = hipStream_t or NULL.
+   materials[n_mat]; walls[n_walls] (may be NULL when 0); stream = a hipStream_t
+   that is not the legacy null stream (graph capture needs a real stream), or
+   NULL for a stream the library creates and owns.
    alloc/free may be NULL (then hipMalloc/hipFree are used). */
 pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
                   const pd_material* materials, int32_t n_mat, const pd_params* params,
@@ -165,7 +169,9 @@ pd_status pd_build_bonds(pd_ctx* ctx, const pd_cut* cuts, int32_t n_cuts);
 
 /* Advance n_steps velocity-Verlet steps.  Enqueues on the context stream and
    waits for the device status word at the end; PD_ERR_UNSTABLE reports a flag
-   raised during these steps (the state is the last completed step). */
+   raised during these steps (the state is the last completed step).  Chunks of
+   rebuild_every steps (doubled when odd) that start on a multiple of that
+   length replay one captured HIP graph; the rest launch kernels directly. */
 pd_status pd_step(pd_ctx* ctx, int64_t n_steps);
 
 /* Bytes a field occupies (for sizing dst). */
@@ -184,10 +190,11 @@ pd_status pd_get_state(pd_ctx* ctx, void* blob, int64_t* bytes);
 /* Restore a checkpoint taken from a context built from the same inputs. */
 pd_status pd_set_state(pd_ctx* ctx, const void* blob, int64_t bytes);
 
-/* Measurement hook: with enable != 0, pd_step brackets every launch of the
-   fused step kernel with a pair of HIP events on the context stream.
-   pd_timing waits for the stream, returns the number of bracketed launches and
-   their summed duration in milliseconds, and clears the record. */
+/* Measurement hook: with enable != 0, pd_step launches every step directly
+   (no graph replay) and brackets each launch of the fused step kernel with a
+   pair of HIP events on the context stream.  pd_timing waits for the stream,
+   returns the number of bracketed launches and their summed duration in
+   milliseconds, and clears the record. */
 pd_status pd_set_timing(pd_ctx* ctx, int32_t enable);
 pd_status pd_timing(pd_ctx* ctx, int64_t* launches, double* total_ms);
 

@@ -30,6 +30,7 @@ struct pd_ctx {
   int32_t m = 3, flags = 0, rebuild_every = 1, cap_per_node = 16;
   double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0};
   hipStream_t stream = nullptr;
+  int own_stream = 0;
   pd_alloc_fn alloc = nullptr;
   pd_free_fn free_fn = nullptr;
   void* user = nullptr;
@@ -54,6 +55,8 @@ struct pd_ctx {
   double* Kn = nullptr;
   WallDev* walls = nullptr;
   double* wall_partial = nullptr;
+  int64_t* box_chunks = nullptr;
+  int32_t n_box_chunks = 0;
   int64_t* step_d = nullptr;
   uint32_t* status = nullptr;
   // bonds
@@ -81,6 +84,11 @@ struct pd_ctx {
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  // captured step loop of graph_len steps
+  int use_graph = 1;
+  int64_t graph_len = 0;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t graph_exec = nullptr;
 };
 
 namespace {
@@ -203,6 +211,8 @@ StepArgs step_args(pd_ctx* c) {
   A.Kn = c->Kn;
   A.walls = c->walls;
   A.wall_partial = c->wall_partial;
+  A.step = c->step_d;
+  A.advance = 1;
   A.status = c->status;
   A.n = c->n;
   A.nslices = c->nslices;
@@ -234,6 +244,8 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.gpair_count = c->gpair_count;
   C.gpair = c->gpair;
   C.active = c->active;
+  C.box_chunks = c->box_chunks;
+  C.n_box_chunks = c->n_box_chunks;
   C.n_grains = c->n_grains;
   C.status = c->status;
   C.n = c->n;
@@ -246,8 +258,9 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   return C;
 }
 
-// one step on the device: rebuild on cadence, force+Verlet, walls
-pd_status enqueue_step(pd_ctx* c, int64_t s) {
+// one step on the device: rebuild on cadence, force+Verlet, walls.
+// ev0/ev1 (optional) bracket the step kernel.
+pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
     ContactArgs C = contact_args(c, nxt);
@@ -256,6 +269,35 @@ pd_status enqueue_step(pd_ctx* c, int64_t s) {
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
+  if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
+  HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+  if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
+  HIPCHK(c, launch_wall_finalize(A, c->stream));
+  return PD_OK;
+}
+
+// capture graph_len steps starting at a multiple of graph_len (buffer parity 0)
+pd_status capture_graph(pd_ctx* c) {
+  if (c->graph_exec) return PD_OK;
+  const int cur0 = c->cur;
+  HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+  pd_status st = PD_OK;
+  for (int64_t p = 1; p <= c->graph_len && st == PD_OK; ++p)
+    st = enqueue_step_ev(c, p, nullptr, nullptr);  // p stands for any step congruent to it
+  hipGraph_t g = nullptr;
+  const hipError_t ec = hipStreamEndCapture(c->stream, &g);
+  c->cur = cur0;
+  if (st != PD_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (ec != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorName(ec));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  return PD_OK;
+}
+
+pd_status enqueue_step(pd_ctx* c, int64_t s) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (c->timing) {
     while (c->ev_pool.size() < c->ev_used + 2) {
@@ -266,13 +308,8 @@ pd_status enqueue_step(pd_ctx* c, int64_t s) {
     e0 = c->ev_pool[c->ev_used];
     e1 = c->ev_pool[c->ev_used + 1];
     c->ev_used += 2;
-    HIPCHK(c, hipEventRecord(e0, c->stream));
   }
-  HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
-  if (c->timing) HIPCHK(c, hipEventRecord(e1, c->stream));
-  HIPCHK(c, launch_wall_finalize(c->walls, c->wall_partial, step_grid_blocks(c->nslices), c->n_walls,
-                                 c->step_d, 1, c->dt, c->stream));
-  return PD_OK;
+  return enqueue_step_ev(c, s, e0, e1);
 }
 
 pd_status read_status(pd_ctx* c, uint32_t* st) {
@@ -351,6 +388,10 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->free_fn = free_fn;
   c->user = alloc_user;
   c->stream = static_cast<hipStream_t>(stream);
+  if (!c->stream) {
+    if (hipStreamCreate(&c->stream) != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamCreate failed");
+    c->own_stream = 1;
+  }
 
   const int64_t N = mesh->n_nodes;
   const int32_t G = grains->n_grains;
@@ -383,7 +424,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     return fail(c, PD_ERR_INVALID, "contact radius/horizon must be > 0 and skin >= 0");
   if (!(P.dt > 0)) return fail(c, PD_ERR_INVALID, "dt must be > 0");
   if (P.rebuild_every < 1) return fail(c, PD_ERR_INVALID, "rebuild_every must be >= 1");
-  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH))
+  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
 
@@ -398,6 +439,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->skin = P.skin;
   c->dt = P.dt;
   c->rebuild_every = P.rebuild_every;
+  c->use_graph = (P.flags & PD_FLAG_NO_GRAPH) ? 0 : 1;
+  c->graph_len = (P.rebuild_every % 2 == 0) ? P.rebuild_every : 2 * (int64_t)P.rebuild_every;
   c->cap_per_node = P.candidate_capacity_per_node > 0 ? P.candidate_capacity_per_node : 16;
   for (int q = 0; q < 3; ++q) c->g[q] = P.gravity[q];
   c->grain_begin.assign(grains->node_begin, grains->node_begin + G + 1);
@@ -708,6 +751,20 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   TRY(alloc_n(c, &c->gpair_count, (int64_t)G + 1, "grain pair counts"));
   TRY(alloc_n(c, &c->gpair, (int64_t)G * G, "grain pairs"));
   TRY(alloc_n(c, &c->active, N, "active flags"));
+  {
+    // grain-box reduction work: chunks of at most 16384 nodes of one grain
+    std::vector<int64_t> ch;
+    for (int32_t g = 0; g < G; ++g)
+      for (int64_t b = c->grain_begin[g]; b < c->grain_begin[g + 1]; b += 16384) {
+        ch.push_back(g);
+        ch.push_back(b);
+        ch.push_back(std::min<int64_t>(b + 16384, c->grain_begin[g + 1]));
+      }
+    c->n_box_chunks = (int32_t)(ch.size() / 3);
+    TRY(alloc_n(c, &c->box_chunks, (int64_t)ch.size(), "box chunks"));
+    HIPCHK(c, hipMemcpyAsync(c->box_chunks, ch.data(), sizeof(int64_t) * ch.size(), hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
   const int32_t nblocks = step_grid_blocks(c->nslices);
   TRY(alloc_n(c, &c->wall_partial, (int64_t)std::max(nblocks, 1) * 3 * std::max(c->n_walls, 1), "wall partials"));
 
@@ -715,8 +772,9 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   ContactArgs C = contact_args(c, c->cur);
   HIPCHK(c, launch_contact_rebuild(C, 0, s));
   StepArgs A = step_args(c);
+  A.advance = 0;
   HIPCHK(c, launch_step(A, MODE_FIRST, s));
-  HIPCHK(c, launch_wall_finalize(c->walls, c->wall_partial, nblocks, c->n_walls, c->step_d, 0, c->dt, s));
+  HIPCHK(c, launch_wall_finalize(A, s));
   c->built = 1;
   c->step = 0;
   return report_status(c);
@@ -726,9 +784,20 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
   if (!c) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   if (n_steps < 0) return fail(c, PD_ERR_INVALID, "n_steps < 0");
-  for (int64_t k = 0; k < n_steps; ++k) {
-    TRY(enqueue_step(c, c->step + 1));
-    c->step += 1;
+  int64_t left = n_steps;
+  while (left > 0) {
+    // timing brackets each step kernel with events, so it launches directly
+    const bool aligned = c->use_graph && !c->timing && c->step % c->graph_len == 0 && left >= c->graph_len;
+    if (aligned) {
+      TRY(capture_graph(c));
+      HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+      c->step += c->graph_len;
+      left -= c->graph_len;
+    } else {
+      TRY(enqueue_step(c, c->step + 1));
+      c->step += 1;
+      left -= 1;
+    }
   }
   return report_status(c);
 }
@@ -744,12 +813,14 @@ pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
   if (!c || !launches || !total_ms) return PD_ERR_INVALID;
   HIPCHK(c, hipStreamSynchronize(c->stream));
   double tot = 0.0;
+  int64_t n = 0;
   for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
     float ms = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
     tot += ms;
+    ++n;
   }
-  *launches = (int64_t)(c->ev_used / 2);
+  *launches = n;
   *total_ms = tot;
   c->ev_used = 0;
   return PD_OK;
@@ -1004,9 +1075,9 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
     o += n;
     return PD_OK;
   };
-  c->cur = 0;
-  TRY(put(c->u4[0], 32 * N));
-  TRY(put(c->u4[1], 32 * N));
+  c->cur = (int)(hdr[4] & 1);  // u4[step % 2] holds u_step, the invariant captured graphs rely on
+  TRY(put(c->u4[c->cur], 32 * N));
+  TRY(put(c->u4[c->cur ^ 1], 32 * N));
   TRY(put(c->v, 24 * N));
   TRY(put(c->a, 24 * N));
   TRY(put(c->colE, 4 * words));
@@ -1020,9 +1091,9 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   {
     double4* tmp;
     TRY(alloc_n(c, &tmp, N, "rebuild staging"));
-    ContactArgs C = contact_args(c, 0);
+    ContactArgs C = contact_args(c, c->cur);
     std::vector<double4> ub((size_t)N);
-    HIPCHK(c, hipMemcpyAsync(ub.data(), c->u4[0], 32 * N, hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipMemcpyAsync(ub.data(), c->u4[c->cur], 32 * N, hipMemcpyDeviceToHost, s));
     std::vector<double> bld((size_t)(3 * N));
     HIPCHK(c, hipMemcpyAsync(bld.data(), c->u_build, 24 * N, hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1042,11 +1113,13 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
 
 void pd_destroy(pd_ctx* c) {
   if (!c) return;
-  if (c->stream) (void)hipStreamSynchronize(c->stream);
-  else (void)hipDeviceSynchronize();
+  (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph) (void)hipGraphDestroy(c->graph);
   std::vector<void*> all = c->owned;
   for (void* p : all) dev_free(c, p);
+  if (c->own_stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
 

@@ -105,6 +105,8 @@ struct StepArgs {
   const double* Kn;     // [n_mat * n_mat]
   WallDev* walls;
   double* wall_partial;  // [nblocks][n_walls][3]
+  int64_t* step;         // device step counter
+  int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;
   int64_t n;
   int64_t nslices;
@@ -153,6 +155,8 @@ struct ContactArgs {
   int32_t* gpair_count;   // [G+1] (scanned in place)
   int32_t* gpair;         // [G*G] other grains whose boxes come within the cutoff
   uint8_t* active;        // [N] node within the cutoff of another grain's box
+  const int64_t* box_chunks;  // [n_box_chunks][3]: grain, first node, end node (one grain each)
+  int32_t n_box_chunks;
   int32_t n_grains;
   uint32_t* status;
   int64_t n;
@@ -169,9 +173,9 @@ hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s);
 hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s);
 hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s);
-hipError_t launch_wall_finalize(WallDev* walls, const double* partial, int32_t nblocks,
-                                int32_t n_walls, int64_t* step, int32_t advance, double dt,
-                                hipStream_t s);
+// wall reactions, next wall offsets and the step counter after a step launch
+hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s);
+
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s);
 hipError_t launch_energy(const StepArgs& a, double* partial4, int32_t nblocks, hipStream_t s);
 hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double* out4,

@@ -466,6 +466,8 @@ void k_step(StepArgs A) {
   }
 
   if (MODE != MODE_FORCE_ONLY && A.n_walls > 0) {
+    // per-workgroup wall partials; k_wall_finalize sums them in a fixed order
+    // (a kernel boundary is the cheap way to make them visible across XCDs)
     __syncthreads();
     if (tid < 3 * A.n_walls) {
       double s = 0.0;
@@ -476,35 +478,46 @@ void k_step(StepArgs A) {
 }
 
 // reaction forces (fixed-order sum of block partials) and the wall positions
-// of the next step: prescribed velocity or servo on the measured stress
-__global__ __launch_bounds__(256) void k_wall_finalize(WallDev* walls, const double* partial,
-                                                       int32_t nblocks, int32_t n_walls,
-                                                       int64_t* step, int32_t advance, double dt) {
-  __shared__ double red[256];
-  const int tid = threadIdx.x;
-  for (int c = 0; c < 3 * n_walls; ++c) {
-    double s = 0.0;
-    for (int b = tid; b < nblocks; b += 256) s += partial[(int64_t)b * 3 * n_walls + c];
-    red[tid] = s;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (tid < o) red[tid] += red[tid + o];
-      __syncthreads();
-    }
-    if (tid == 0) walls[c / 3].force[c % 3] = -red[0];
-    __syncthreads();
+// of the next step: prescribed velocity or servo on the measured stress.
+// One workgroup of 1024 threads; every thread loads its share of all
+// components first (one memory round trip), then a fixed-order LDS tree.
+__global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblocks) {
+  __shared__ double red[kMaxWalls * 3][1024 / kWave];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nc = 3 * A.n_walls;
+  double acc[kMaxWalls * 3];
+#pragma unroll
+  for (int c = 0; c < kMaxWalls * 3; ++c) acc[c] = 0.0;
+  for (int b = tid; b < nblocks; b += 1024) {
+    const double* p = A.wall_partial + (int64_t)b * nc;
+#pragma unroll
+    for (int c = 0; c < kMaxWalls * 3; ++c)
+      if (c < nc) acc[c] += p[c];
   }
+#pragma unroll
+  for (int c = 0; c < kMaxWalls * 3; ++c) {
+    if (c < nc) {
+      const double t = wave_sum(acc[c]);
+      if (lane == 0) red[c][wv] = t;
+    }
+  }
+  __syncthreads();
   if (tid == 0) {
-    const int64_t s = *step + advance;  // the step this evaluation belonged to
-    *step = s;
-    for (int w = 0; w < n_walls; ++w) {
-      WallDev& W = walls[w];
+    const int64_t s = *A.step + A.advance;  // the step this evaluation belonged to
+    *A.step = s;
+    for (int w = 0; w < A.n_walls; ++w) {
+      WallDev& W = A.walls[w];
+      for (int q = 0; q < 3; ++q) {
+        double t = 0.0;
+        for (int k = 0; k < 1024 / kWave; ++k) t += red[3 * w + q][k];
+        W.force[q] = -t;
+      }
       W.off_used = W.off;
       if (W.mode == PD_WALL_VELOCITY) {
-        W.off = W.off0 + W.vel * ((double)(s + 1) * dt);
+        W.off = W.off0 + W.vel * ((double)(s + 1) * A.dt);
       } else if (W.mode == PD_WALL_SERVO) {
         const double sigma = -(W.force[0] * W.n[0] + W.force[1] * W.n[1] + W.force[2] * W.n[2]) / W.area;
-        W.off = W.off + dt * W.gain * (W.target - sigma);
+        W.off = W.off + A.dt * W.gain * (W.target - sigma);
       }
     }
   }
@@ -632,35 +645,35 @@ __device__ __forceinline__ long long wave_max_ll(long long x) {
   return x;
 }
 
+// one workgroup per chunk of a single grain: LDS reduction, then 6 atomics
 __global__ __launch_bounds__(256) void k_box(ContactArgs c) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  const bool valid = i < c.n;
-  long long k[6];
-  int g = -1;
-  if (valid) {
+  __shared__ long long red[6][256];
+  const int tid = threadIdx.x;
+  const int64_t* ch = c.box_chunks + 3 * (int64_t)blockIdx.x;
+  const int g = (int)ch[0];
+  long long k[6] = {ord_key(INFINITY), ord_key(INFINITY), ord_key(INFINITY),
+                    ord_key(-INFINITY), ord_key(-INFINITY), ord_key(-INFINITY)};
+  for (int64_t i = ch[1] + tid; i < ch[2]; i += 256) {
     const double4 u = c.u[i];
-    g = packed_grain(u.w);
-    k[0] = k[3] = ord_key(c.X[i] + u.x);
-    k[1] = k[4] = ord_key(c.X[c.n + i] + u.y);
-    k[2] = k[5] = ord_key(c.X[2 * c.n + i] + u.z);
-  } else {
-    k[0] = k[1] = k[2] = ord_key(INFINITY);
-    k[3] = k[4] = k[5] = ord_key(-INFINITY);
+    const long long x = ord_key(c.X[i] + u.x), y = ord_key(c.X[c.n + i] + u.y),
+                    z = ord_key(c.X[2 * c.n + i] + u.z);
+    k[0] = min(k[0], x);
+    k[1] = min(k[1], y);
+    k[2] = min(k[2], z);
+    k[3] = max(k[3], x);
+    k[4] = max(k[4], y);
+    k[5] = max(k[5], z);
   }
-  // wavefronts inside one grain reduce first and issue 6 atomics
-  const int g0 = __shfl(g, 0, kWave);
-  const uint64_t same = __ballot(!valid || g == g0 || g < 0);
-  if (same == ~0ull && g0 >= 0) {
-    for (int q = 0; q < 3; ++q) k[q] = wave_min_ll(k[q]);
-    for (int q = 3; q < 6; ++q) k[q] = wave_max_ll(k[q]);
-    if (lane == 0)
+  for (int q = 0; q < 6; ++q) red[q][tid] = k[q];
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o)
       for (int q = 0; q < 6; ++q)
-        q < 3 ? atomicMin(c.gbox + 6 * g0 + q, k[q]) : atomicMax(c.gbox + 6 * g0 + q, k[q]);
-  } else if (valid) {
-    for (int q = 0; q < 6; ++q)
-      q < 3 ? atomicMin(c.gbox + 6 * g + q, k[q]) : atomicMax(c.gbox + 6 * g + q, k[q]);
+        red[q][tid] = q < 3 ? min(red[q][tid], red[q][tid + o]) : max(red[q][tid], red[q][tid + o]);
+    __syncthreads();
   }
+  if (tid < 3) atomicMin(c.gbox + 6 * g + tid, red[tid][0]);
+  else if (tid < 6) atomicMax(c.gbox + 6 * g + tid, red[tid][0]);
 }
 
 // grain boxes closer than the cutoff (one thread per grain, plain loop over the others)
@@ -942,6 +955,11 @@ hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s) {
 
 int32_t step_grid_blocks(int64_t nslices) { return (int32_t)grid_for(nslices, kSlicesPerBlock); }
 
+hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(1024), 0, s, a, step_grid_blocks(a.nslices));
+  return hipGetLastError();
+}
+
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
   const int32_t nb = step_grid_blocks(a.nslices);
   if (nb == 0) return hipSuccess;
@@ -960,14 +978,6 @@ hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_wall_finalize(WallDev* walls, const double* partial, int32_t nblocks,
-                                int32_t n_walls, int64_t* step, int32_t advance, double dt,
-                                hipStream_t s) {
-  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(256), 0, s, walls, partial, nblocks, n_walls,
-                     step, advance, dt);
-  return hipGetLastError();
-}
-
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const unsigned g = grid_for(c.n, 256);
@@ -978,7 +988,7 @@ hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStrea
   if ((e = launch_fill_i32(c.bucket_fill, 0, (int64_t)c.T, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_skin, dim3(g), dim3(256), 0, s, c, check_skin);
   hipLaunchKernelGGL(k_box_init, dim3(grid_for(6 * (int64_t)c.n_grains, 256)), dim3(256), 0, s, c);
-  hipLaunchKernelGGL(k_box, dim3(g), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_box, dim3((unsigned)c.n_box_chunks), dim3(256), 0, s, c);
   const unsigned gg = grid_for(c.n_grains, 64);
   hipLaunchKernelGGL(k_box_pairs<false>, dim3(gg), dim3(64), 0, s, c, cut);
   if ((e = scan_i32(c.gpair_count, c.gpair_count, c.n_grains, c.scan_scratch, s)) != hipSuccess) return e;

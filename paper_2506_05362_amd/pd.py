@@ -19,7 +19,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpd_mi35
 
 PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_OOM, PD_ERR_HIP, PD_ERR_UNSTABLE = 0, -1, -2, -3, -4, -5
 PD_ERR_UNSUPPORTED, PD_ERR_CORRUPT = -6, -7
-FLAG_TABLE_LITERAL, FLAG_ABS_STRETCH = 1, 2
+FLAG_TABLE_LITERAL, FLAG_ABS_STRETCH, FLAG_NO_GRAPH = 1, 2, 4
 
 FIELDS = dict(displacement=0, velocity=1, accel=2, force_density=3, damage=4, intact_count=5,
               initial_count=6, bond_rowptr=7, bond_col=8, bond_broken=9, contact_rowptr=10,
@@ -155,16 +155,19 @@ def make_cut(c: "_inp.Cut") -> pd_cut:
 
 
 class TorchPlumbing:
-    """Device memory from PyTorch's caching allocator and PyTorch's current HIP stream."""
+    """Device memory from PyTorch's caching allocator and a PyTorch HIP stream.
 
-    def __init__(self, device: int = 0):
+    By default each context gets its own stream (default priority): the legacy
+    null stream cannot be captured into the library's HIP graphs."""
+
+    def __init__(self, device: int = 0, stream=None):
         import torch
         if not torch.cuda.is_available():
             raise RuntimeError("no GPU visible to PyTorch")
         self.torch = torch
         self.device = device
         torch.cuda.set_device(device)
-        self.stream = torch.cuda.current_stream(device)
+        self.stream = stream if stream is not None else torch.cuda.Stream(device)
         self.stream_ptr = self.stream.cuda_stream
 
         def _alloc(nbytes, user):

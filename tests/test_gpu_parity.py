@@ -236,3 +236,22 @@ def test_wall_penetration_is_flagged():
     with pytest.raises(pd.PDError) as e:
         pd.Sim(wl)
     assert e.value.status == pd.PD_ERR_UNSTABLE
+
+
+def test_graph_replay_matches_direct_launches():
+    """The captured step loop (rebuild_every steps per graph) gives bitwise the
+    same state as launching every step directly, across misaligned chunks."""
+    from paper_2506_05362_amd import pd
+    wl = I.two_spheres(radius_cells=6, speed=30.0, gap=0.0, rebuild_every=5)
+    a = gpu_sim(wl)
+    b = gpu_sim(wl, flags=pd.FLAG_NO_GRAPH)
+    for n in (3, 27, 40, 1, 9):
+        a.step(n)
+        b.step(n)
+    assert a.info()["step"] == b.info()["step"] == 80
+    for f in ("displacement", "velocity", "accel", "bond_broken", "intact_count"):
+        assert np.array_equal(a.get(f), b.get(f)), f
+    a.set_timing(True)
+    a.step(20)
+    n, ms = a.timing()
+    assert n == 20 and ms > 0
