@@ -17,6 +17,7 @@ HIPFLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
 
 LIBS = {
     "libpd_mi355x.so": ["pd_kernels.hip", "pd_api.hip"],
+    "libpd_mlp.so": ["mlp.hip"],
 }
 
 

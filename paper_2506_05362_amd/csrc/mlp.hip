@@ -1,0 +1,448 @@
+// Surrogate network on gfx950: BF16 matrix-core GEMMs with FP32 accumulation,
+// fused bias / GELU / GELU' epilogues, MSE loss and FP32 Adam.  C ABI in
+// include/pd_mlp.h.
+//
+// Every layer product is one kernel k_gemm: a 256-thread workgroup computes a
+// 64 x 64 tile of C = A B with v_mfma_f32_16x16x16_bf16 (each wavefront owns a
+// 32 x 32 quarter as 2 x 2 matrix-core blocks); A and B are read from FP32
+// arrays through arbitrary strides (so the transposed operands of the
+// backward pass need no copies), rounded to BF16 and staged in LDS 16 columns
+// of K at a time.
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pd_mlp.h"
+
+namespace {
+
+typedef short v4s __attribute__((ext_vector_type(4)));
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+constexpr int kTile = 64;
+constexpr int kK = 16;
+
+// FP32 -> BF16, round to nearest even (NaN kept quiet)
+__device__ __forceinline__ short to_bf16(float x) {
+  uint32_t u = __float_as_uint(x);
+  if ((u & 0x7fffffffu) > 0x7f800000u) return (short)((u >> 16) | 0x40u);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (short)(u >> 16);
+}
+
+__device__ __forceinline__ float gelu(float z) { return 0.5f * z * (1.0f + erff(z * 0.70710678118654752f)); }
+__device__ __forceinline__ float gelu_grad(float z) {
+  return 0.5f * (1.0f + erff(z * 0.70710678118654752f)) + z * 0.39894228040143268f * expf(-0.5f * z * z);
+}
+
+struct Gemm {
+  const float* A;
+  int64_t sam, sak;  // A(m, k) = A[m * sam + k * sak]
+  const float* B;
+  int64_t sbk, sbn;  // B(k, n) = B[k * sbk + n * sbn]
+  int64_t M, N, K;
+  float* C;
+  int64_t ldc;         // C(m, n) = C[m * ldc + n]
+  const float* bias;   // [N]
+  float* Zout;         // pre-activation store (ldc), may be null
+  const float* Zin;    // pre-activation for GELU' (ldc)
+};
+
+enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
+
+template <int EPI>
+__global__ __launch_bounds__(256) void k_gemm(Gemm g) {
+  __shared__ short As[kTile][kK];  // As[m][k]
+  __shared__ short Bs[kTile][kK];  // Bs[n][k] (B transposed)
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
+  const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
+  v4f acc[2][2];
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
+  const int lr = tid >> 2, lk = (tid & 3) * 4;  // staging: row / column of the tile, 4 k each
+  for (int64_t k0 = 0; k0 < g.K; k0 += kK) {
+    {
+      const int64_t m = m0 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t k = k0 + lk + e;
+        As[lr][lk + e] = to_bf16((m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.0f);
+      }
+      const int64_t n = n0 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t k = k0 + lk + e;
+        Bs[lr][lk + e] = to_bf16((n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : 0.0f);
+      }
+    }
+    __syncthreads();
+    // operand layout of the 16x16x16 BF16 matrix core: lane l holds A[l%16][4(l/16)..+3]
+    // and B[4(l/16)..+3][l%16]; the result C[4(l/16)+e][l%16] lands in element e
+    v4s a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4s*>(&As[wm + i * 16 + (lane & 15)][4 * (lane >> 4)]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const v4s*>(&Bs[wn + j * 16 + (lane & 15)][4 * (lane >> 4)]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t m = m0 + wm + i * 16 + 4 * (lane >> 4) + e;
+        const int64_t n = n0 + wn + j * 16 + (lane & 15);
+        if (m >= g.M || n >= g.N) continue;
+        const float v = acc[i][j][e];
+        const int64_t o = m * g.ldc + n;
+        if (EPI == EPI_STORE) {
+          g.C[o] = v;
+        } else if (EPI == EPI_BIAS) {
+          g.C[o] = v + g.bias[n];
+        } else if (EPI == EPI_BIAS_GELU) {
+          const float z = v + g.bias[n];
+          if (g.Zout) g.Zout[o] = z;
+          g.C[o] = gelu(z);
+        } else {
+          g.C[o] = v * gelu_grad(g.Zin[o]);
+        }
+      }
+}
+
+// residual, loss partial sums and dY = 2 (Y_hat - Y) / (B * d)
+__global__ __launch_bounds__(256) void k_loss(const float* yh, const float* y, float* dy, int64_t n,
+                                               float scale, double* partial) {
+  __shared__ double red[256];
+  const int tid = threadIdx.x;
+  double s = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + tid; i < n; i += (int64_t)gridDim.x * 256) {
+    const float r = yh[i] - y[i];
+    dy[i] = scale * r;
+    s += (double)r * (double)r;
+  }
+  red[tid] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (tid < o) red[tid] += red[tid + o];
+    __syncthreads();
+  }
+  if (tid == 0) partial[blockIdx.x] = red[0];
+}
+
+// db[n] = sum_m dZ[m][n]
+__global__ void k_colsum(const float* dz, int64_t M, int64_t N, float* db) {
+  const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (n >= N) return;
+  float s = 0.0f;
+  for (int64_t m = 0; m < M; ++m) s += dz[m * N + n];
+  db[n] = s;
+}
+
+__global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
+                       float b2, float eps, float c1, float c2) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = b1 * m[i] + (1.0f - b1) * gi;
+  const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+}  // namespace
+
+struct pdm_net {
+  std::vector<int32_t> dims;
+  int64_t max_batch = 0, n_params = 0;
+  hipStream_t stream = nullptr;
+  int own_stream = 0;
+  std::string err;
+  float *params = nullptr, *grad = nullptr, *m = nullptr, *v = nullptr;
+  std::vector<float*> Z, Aout, dZ;  // per layer, [max_batch][dims[l+1]]
+  float* yhat = nullptr;            // [max_batch][d_out]
+  double* partial = nullptr;
+  int nloss_blocks = 0;
+  std::vector<int64_t> woff, boff;  // offsets of W_l, b_l in the parameter vector
+  float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  int64_t t = 0;
+  std::vector<void*> owned;
+};
+
+namespace {
+
+pd_status fail(pdm_net* n, pd_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  if (n) n->err = buf;
+  return st;
+}
+
+#define HIPCHK(net, call)                                                                    \
+  do {                                                                                       \
+    hipError_t e_ = (call);                                                                  \
+    if (e_ != hipSuccess)                                                                    \
+      return fail((net), PD_ERR_HIP, "%s failed: %s", #call, hipGetErrorName(e_));           \
+  } while (0)
+
+template <typename T>
+pd_status alloc(pdm_net* n, T** p, int64_t count) {
+  void* q = nullptr;
+  if (hipMalloc(&q, sizeof(T) * (size_t)(count > 0 ? count : 1)) != hipSuccess)
+    return fail(n, PD_ERR_OOM, "device allocation of %lld elements failed", (long long)count);
+  n->owned.push_back(q);
+  *p = static_cast<T*>(q);
+  return PD_OK;
+}
+
+#define TRY(e)                        \
+  do {                                \
+    pd_status s_ = (e);               \
+    if (s_ != PD_OK) return s_;       \
+  } while (0)
+
+template <int EPI>
+hipError_t gemm(const Gemm& g, hipStream_t s) {
+  if (g.M <= 0 || g.N <= 0) return hipSuccess;
+  dim3 grid((unsigned)((g.N + kTile - 1) / kTile), (unsigned)((g.M + kTile - 1) / kTile));
+  hipLaunchKernelGGL(k_gemm<EPI>, grid, dim3(256), 0, s, g);
+  return hipGetLastError();
+}
+
+int n_layers(const pdm_net* n) { return (int)n->dims.size() - 1; }
+
+// forward of `batch` rows (<= max_batch) from x into y (device pointers)
+pd_status forward_chunk(pdm_net* n, const float* x, int64_t batch, float* y, bool keep_z) {
+  const int L = n_layers(n);
+  const float* A = x;
+  for (int l = 0; l < L; ++l) {
+    const int64_t din = n->dims[l], dout = n->dims[l + 1];
+    Gemm g{};
+    g.A = A;
+    g.sam = din;
+    g.sak = 1;
+    g.B = n->params + n->woff[l];
+    g.sbk = dout;
+    g.sbn = 1;
+    g.M = batch;
+    g.N = dout;
+    g.K = din;
+    g.bias = n->params + n->boff[l];
+    g.ldc = dout;
+    if (l < L - 1) {
+      g.C = n->Aout[l];
+      g.Zout = keep_z ? n->Z[l] : nullptr;
+      HIPCHK(n, gemm<EPI_BIAS_GELU>(g, n->stream));
+      A = n->Aout[l];
+    } else {
+      g.C = y;
+      HIPCHK(n, gemm<EPI_BIAS>(g, n->stream));
+    }
+  }
+  return PD_OK;
+}
+
+// loss and gradient into n->grad for one batch
+pd_status loss_and_grad(pdm_net* n, const float* x, const float* y, int64_t batch, float* loss) {
+  const int L = n_layers(n);
+  const int64_t dout = n->dims[L];
+  TRY(forward_chunk(n, x, batch, n->yhat, true));
+  const int64_t cnt = batch * dout;
+  hipLaunchKernelGGL(k_loss, dim3(n->nloss_blocks), dim3(256), 0, n->stream, n->yhat, y, n->dZ[L - 1],
+                     cnt, 2.0f / (float)cnt, n->partial);
+  HIPCHK(n, hipGetLastError());
+  for (int l = L - 1; l >= 0; --l) {
+    const int64_t din = n->dims[l], dl = n->dims[l + 1];
+    const float* Ain = l == 0 ? x : n->Aout[l - 1];
+    // dW_l = A_in^T dZ_l
+    Gemm gw{};
+    gw.A = Ain;
+    gw.sam = 1;
+    gw.sak = din;
+    gw.B = n->dZ[l];
+    gw.sbk = dl;
+    gw.sbn = 1;
+    gw.M = din;
+    gw.N = dl;
+    gw.K = batch;
+    gw.C = n->grad + n->woff[l];
+    gw.ldc = dl;
+    HIPCHK(n, gemm<EPI_STORE>(gw, n->stream));
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((dl + 255) / 256)), dim3(256), 0, n->stream, n->dZ[l],
+                       batch, dl, n->grad + n->boff[l]);
+    HIPCHK(n, hipGetLastError());
+    if (l > 0) {
+      // dZ_{l-1} = (dZ_l W_l^T) * GELU'(Z_{l-1})
+      Gemm gx{};
+      gx.A = n->dZ[l];
+      gx.sam = dl;
+      gx.sak = 1;
+      gx.B = n->params + n->woff[l];
+      gx.sbk = 1;
+      gx.sbn = dl;
+      gx.M = batch;
+      gx.N = din;
+      gx.K = dl;
+      gx.C = n->dZ[l - 1];
+      gx.ldc = din;
+      gx.Zin = n->Z[l - 1];
+      HIPCHK(n, gemm<EPI_GELU_GRAD>(gx, n->stream));
+    }
+  }
+  if (loss) {
+    std::vector<double> part((size_t)n->nloss_blocks);
+    HIPCHK(n, hipMemcpyAsync(part.data(), n->partial, sizeof(double) * part.size(), hipMemcpyDeviceToHost,
+                             n->stream));
+    HIPCHK(n, hipStreamSynchronize(n->stream));
+    double s = 0.0;
+    for (double p : part) s += p;
+    *loss = (float)(s / (double)cnt);
+  }
+  return PD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t max_batch, void* stream) {
+  if (!out) return PD_ERR_INVALID;
+  *out = nullptr;
+  pdm_net* n = new (std::nothrow) pdm_net();
+  if (!n) return PD_ERR_OOM;
+  *out = n;
+  if (!dims || n_dims < 2) return fail(n, PD_ERR_INVALID, "need at least two layer widths");
+  for (int k = 0; k < n_dims; ++k)
+    if (dims[k] < 1 || dims[k] > 1024) return fail(n, PD_ERR_INVALID, "layer width %d out of [1, 1024]", dims[k]);
+  if (max_batch < 1 || max_batch > (1 << 24)) return fail(n, PD_ERR_INVALID, "max_batch out of range");
+  n->dims.assign(dims, dims + n_dims);
+  n->max_batch = max_batch;
+  n->stream = static_cast<hipStream_t>(stream);
+  if (!n->stream) {
+    if (hipStreamCreate(&n->stream) != hipSuccess) return fail(n, PD_ERR_HIP, "hipStreamCreate failed");
+    n->own_stream = 1;
+  }
+  const int L = n_dims - 1;
+  int64_t o = 0;
+  for (int l = 0; l < L; ++l) {
+    n->woff.push_back(o);
+    o += (int64_t)dims[l] * dims[l + 1];
+    n->boff.push_back(o);
+    o += dims[l + 1];
+  }
+  n->n_params = o;
+  TRY(alloc(n, &n->params, o));
+  TRY(alloc(n, &n->grad, o));
+  TRY(alloc(n, &n->m, o));
+  TRY(alloc(n, &n->v, o));
+  n->Z.resize(L);
+  n->Aout.resize(L);
+  n->dZ.resize(L);
+  for (int l = 0; l < L; ++l) {
+    TRY(alloc(n, &n->Z[l], max_batch * dims[l + 1]));
+    TRY(alloc(n, &n->Aout[l], max_batch * dims[l + 1]));
+    TRY(alloc(n, &n->dZ[l], max_batch * dims[l + 1]));
+  }
+  TRY(alloc(n, &n->yhat, max_batch * dims[L]));
+  n->nloss_blocks = 256;
+  TRY(alloc(n, &n->partial, n->nloss_blocks));
+  HIPCHK(n, hipMemsetAsync(n->params, 0, sizeof(float) * o, n->stream));
+  HIPCHK(n, hipMemsetAsync(n->m, 0, sizeof(float) * o, n->stream));
+  HIPCHK(n, hipMemsetAsync(n->v, 0, sizeof(float) * o, n->stream));
+  HIPCHK(n, hipStreamSynchronize(n->stream));
+  return PD_OK;
+}
+
+int64_t pdm_param_count(const pdm_net* n) { return n ? n->n_params : 0; }
+
+pd_status pdm_set_params(pdm_net* n, const float* p, int64_t cnt) {
+  if (!n || !p) return PD_ERR_INVALID;
+  if (cnt != n->n_params) return fail(n, PD_ERR_INVALID, "expected %lld parameters", (long long)n->n_params);
+  HIPCHK(n, hipMemcpyAsync(n->params, p, sizeof(float) * cnt, hipMemcpyHostToDevice, n->stream));
+  HIPCHK(n, hipMemsetAsync(n->m, 0, sizeof(float) * cnt, n->stream));
+  HIPCHK(n, hipMemsetAsync(n->v, 0, sizeof(float) * cnt, n->stream));
+  HIPCHK(n, hipStreamSynchronize(n->stream));
+  n->t = 0;
+  return PD_OK;
+}
+
+pd_status pdm_get_params(pdm_net* n, float* p, int64_t cnt) {
+  if (!n || !p) return PD_ERR_INVALID;
+  if (cnt < n->n_params) return fail(n, PD_ERR_INVALID, "expected room for %lld parameters", (long long)n->n_params);
+  HIPCHK(n, hipMemcpyAsync(p, n->params, sizeof(float) * n->n_params, hipMemcpyDeviceToHost, n->stream));
+  HIPCHK(n, hipStreamSynchronize(n->stream));
+  return PD_OK;
+}
+
+pd_status pdm_set_adam(pdm_net* n, float b1, float b2, float eps) {
+  if (!n) return PD_ERR_INVALID;
+  if (!(b1 >= 0 && b1 < 1 && b2 >= 0 && b2 < 1 && eps > 0)) return fail(n, PD_ERR_INVALID, "bad Adam parameters");
+  n->beta1 = b1;
+  n->beta2 = b2;
+  n->eps = eps;
+  return PD_OK;
+}
+
+pd_status pdm_forward(pdm_net* n, const float* x, int64_t batch, float* y) {
+  if (!n || (!x && batch > 0) || (!y && batch > 0) || batch < 0) return PD_ERR_INVALID;
+  const int64_t din = n->dims.front(), dout = n->dims.back();
+  for (int64_t b0 = 0; b0 < batch; b0 += n->max_batch) {
+    const int64_t cb = batch - b0 < n->max_batch ? batch - b0 : n->max_batch;
+    TRY(forward_chunk(n, x + b0 * din, cb, y + b0 * dout, false));
+  }
+  HIPCHK(n, hipStreamSynchronize(n->stream));
+  return PD_OK;
+}
+
+pd_status pdm_gradients(pdm_net* n, const float* x, const float* y, int64_t batch, float* loss, float* grad) {
+  if (!n || !x || !y || !grad) return PD_ERR_INVALID;
+  if (batch < 1 || batch > n->max_batch) return fail(n, PD_ERR_INVALID, "batch must be in [1, max_batch]");
+  TRY(loss_and_grad(n, x, y, batch, loss));
+  HIPCHK(n, hipMemcpyAsync(grad, n->grad, sizeof(float) * n->n_params, hipMemcpyDeviceToHost, n->stream));
+  HIPCHK(n, hipStreamSynchronize(n->stream));
+  return PD_OK;
+}
+
+pd_status pdm_train_step(pdm_net* n, const float* x, const float* y, int64_t batch, float lr, float* loss) {
+  if (!n || !x || !y) return PD_ERR_INVALID;
+  if (batch < 1 || batch > n->max_batch) return fail(n, PD_ERR_INVALID, "batch must be in [1, max_batch]");
+  if (!(lr > 0)) return fail(n, PD_ERR_INVALID, "learning rate must be > 0");
+  TRY(loss_and_grad(n, x, y, batch, loss));
+  n->t += 1;
+  const float c1 = 1.0f - powf(n->beta1, (float)n->t), c2 = 1.0f - powf(n->beta2, (float)n->t);
+  hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->n_params + 255) / 256)), dim3(256), 0, n->stream, n->params,
+                     n->grad, n->m, n->v, n->n_params, lr, n->beta1, n->beta2, n->eps, c1, c2);
+  HIPCHK(n, hipGetLastError());
+  if (!loss) HIPCHK(n, hipStreamSynchronize(n->stream));
+  return PD_OK;
+}
+
+void pdm_destroy(pdm_net* n) {
+  if (!n) return;
+  (void)hipStreamSynchronize(n->stream);
+  for (void* p : n->owned) (void)hipFree(p);
+  if (n->own_stream) (void)hipStreamDestroy(n->stream);
+  delete n;
+}
+
+const char* pdm_last_error(const pdm_net* n) { return n ? n->err.c_str() : "null network"; }
+
+}  // extern "C"
