@@ -21,6 +21,13 @@
  *      (pi/3)(Rc-d)^2(2Rc+d), the one consistent with the printed centroid;
  *      several walls are summed.
  *   R6 velocity Verlet in position form; fixed nodes keep u and have v = a = 0.
+ *   R15 normal damping (Sec. 3.4) is linear in the normal relative velocity,
+ *      -beta_d (w . e) e with w the velocity of the node relative to its partner
+ *      (the sign that dissipates): the text calls the law linear and likens it
+ *      to a viscoelastic spring, while the printed formula normalises w.  The
+ *      velocity is the mid-step value v_n + dt/2 a_n, the one known when the
+ *      force at u_{n+1} is evaluated (v_0 in the first evaluation).  Against a
+ *      wall the partner moves with the wall's rate along its normal.
  */
 #include "pdref.h"
 
@@ -37,7 +44,9 @@ typedef struct {
   double n[3], offset0, offset, velocity, lo[3], hi[3];
   int mode;
   double target, gain, area;
-  double force[3]; /* reaction on the wall, -sum_i V_i F_wall,i */
+  double rate;       /* d(offset)/dt over the step that led to the current offset */
+  double force[3];   /* reaction on the wall, -sum_i V_i F_wall,i */
+  double impulse[3]; /* sum over completed steps of force * dt */
 } wall_t;
 
 typedef struct {
@@ -59,6 +68,8 @@ struct pdref {
   double* mat;
   int m;
   double Rc, eps, skin, dt, g[3];
+  double beta;   /* normal damping coefficient beta_d, Sec. 3.4 */
+  double* vh;    /* velocity that the damping law sees: v + dt/2 a (v at the build) */
   int rebuild_every;
   int32_t n_walls;
   wall_t* walls;
@@ -132,6 +143,7 @@ pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double
   s->u = dup_d(u0, 3 * n);
   s->v = dup_d(v0, 3 * n);
   s->a = dup_d(NULL, 3 * n);
+  s->vh = dup_d(NULL, 3 * n);
   s->F = dup_d(NULL, 3 * n);
   s->u_at_build = dup_d(NULL, 3 * n);
   s->ijk = (int32_t*)malloc(sizeof(int32_t) * (size_t)(3 * n + 1));
@@ -156,6 +168,7 @@ pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double
   s->g[0] = params[6];
   s->g[1] = params[7];
   s->g[2] = params[8];
+  s->beta = params[9];
   s->flags = flags;
   s->grain_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
   for (int32_t g = 0; g < n_grains; ++g)
@@ -187,6 +200,7 @@ pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double
     W->target = r[12];
     W->gain = r[13];
     W->area = r[14];
+    W->rate = W->mode == 1 ? W->velocity : 0.0;
   }
   s->n_cuts = n_cuts;
   s->cuts = (cut_t*)calloc((size_t)(n_cuts > 0 ? n_cuts : 1), sizeof(cut_t));
@@ -204,7 +218,7 @@ pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double
 
 void pdref_destroy(pdref* s) {
   if (!s) return;
-  free(s->X); free(s->u); free(s->v); free(s->a); free(s->F); free(s->u_at_build);
+  free(s->X); free(s->u); free(s->v); free(s->a); free(s->vh); free(s->F); free(s->u_at_build);
   free(s->ijk); free(s->fixed); free(s->grain_begin); free(s->gmat); free(s->gh);
   free(s->mat); free(s->grain_of); free(s->gc); free(s->gs0); free(s->gV); free(s->grho);
   free(s->gK); free(s->walls); free(s->cuts); free(s->row_ptr); free(s->col); free(s->broken);
@@ -498,6 +512,13 @@ static int eval_force(pdref* s) {
       const int32_t gj = s->grain_of[j];
       double Kn = pdref_contact_stiffness(s->gK[g], s->gK[gj], s->eps);
       double coef = -Kn * (Rc - d) * s->gV[gj] / d;
+      if (s->beta > 0.0) {
+        /* normal damping, Sec. 3.4 (linear reading): -beta (w . e) e V_j with w the
+           velocity of i relative to j and e = y/d pointing from i to j */
+        double w = 0.0;
+        for (int q = 0; q < 3; ++q) w += (s->vh[q * n + i] - s->vh[q * n + j]) * y[q];
+        coef -= s->beta * s->gV[gj] * w / d2;
+      }
       for (int q = 0; q < 3; ++q) Fi[q] += coef * y[q];
     }
     for (int q = 0; q < 3; ++q) {
@@ -529,6 +550,12 @@ static int eval_force(pdref* s) {
       pdref_wall_cap(Rc, d, &vol, &ell);
       /* -K_n (R_c - |c_l - p|) |S_l| e_l with e_l = -n (towards the wall) */
       double mag = Kn * (Rc - ell) * vol;
+      if (s->beta > 0.0) {
+        /* damping against the wall (Sec. 4.1 with V_y -> |S_l|): the relative
+           normal velocity is v . n minus the wall's own rate along n */
+        double vn = (W->n[0] * s->vh[i] + W->n[1] * s->vh[n + i]) + W->n[2] * s->vh[2 * n + i];
+        mag -= s->beta * (vn - W->rate) * vol;
+      }
       for (int q = 0; q < 3; ++q) {
         double f = mag * W->n[q];
         s->F[q * n + i] += f;
@@ -554,10 +581,12 @@ static void advance_walls(pdref* s) {
     wall_t* W = &s->walls[w];
     if (W->mode == 1) {
       W->offset = W->offset0 + W->velocity * t;
+      W->rate = W->velocity;
     } else if (W->mode == 2) {
       /* servo: stress from the previous step's reaction; move into the domain when low */
       double sigma = -((W->force[0] * W->n[0] + W->force[1] * W->n[1]) + W->force[2] * W->n[2]) / W->area;
-      W->offset += s->dt * W->gain * (W->target - sigma);
+      W->rate = W->gain * (W->target - sigma);
+      W->offset += s->dt * W->rate;
     }
   }
 }
@@ -577,6 +606,9 @@ int32_t pdref_build(pdref* s) {
   build_bonds(s);
   build_candidates(s);
   s->step = 0;
+  /* the first evaluation sees the initial velocity (zero on fixed nodes) */
+  for (int64_t i = 0; i < s->n; ++i)
+    for (int q = 0; q < 3; ++q) s->vh[q * s->n + i] = s->fixed[i] ? 0.0 : s->v[q * s->n + i];
   int bad = eval_force(s);
   set_accel(s, s->a);
   for (int64_t i = 0; i < s->n; ++i)
@@ -605,8 +637,12 @@ int32_t pdref_step(pdref* s, int64_t nsteps) {
       if (s->n_grains > 1 && skin_exceeded(s)) bad = 1;
       build_candidates(s);
     }
-    /* new accelerations at the new positions, then the velocity update */
+    /* new accelerations at the new positions, then the velocity update; the
+       damping law sees the mid-step velocity v_n + dt/2 a_n */
+    for (int64_t k3 = 0; k3 < 3 * n; ++k3) s->vh[k3] = s->v[k3] + 0.5 * dt * s->a[k3];
     bad |= eval_force(s);
+    for (int32_t w = 0; w < s->n_walls; ++w)
+      for (int q = 0; q < 3; ++q) s->walls[w].impulse[q] += s->walls[w].force[q] * dt;
     set_accel(s, anew);
     for (int64_t i = 0; i < n; ++i)
       for (int q = 0; q < 3; ++q) {
@@ -657,6 +693,11 @@ void pdref_get_walls(const pdref* s, double* force, double* offset) {
       if (force) force[3 * w + q] = s->walls[w].force[q];
     if (offset) offset[w] = s->walls[w].offset;
   }
+}
+
+void pdref_get_wall_impulse(const pdref* s, double* impulse) {
+  for (int32_t w = 0; w < s->n_walls; ++w)
+    for (int q = 0; q < 3; ++q) impulse[3 * w + q] = s->walls[w].impulse[q];
 }
 
 int64_t pdref_n_candidates(const pdref* s) { return s->cand_ptr ? s->cand_ptr[s->n] : 0; }

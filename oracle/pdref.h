@@ -41,8 +41,8 @@ extern "C" {
 /* packed cut record (16 int64):
  *   kind grain a b c d lox loy loz hix hiy hiz cx cy cz radius2     (half-lattice units) */
 #define PDREF_CUT_INTS 16
-/* params (9 doubles): m R_c eps skin rebuild_every dt gx gy gz */
-#define PDREF_PARAM_DOUBLES 9
+/* params (10 doubles): m R_c eps skin rebuild_every dt gx gy gz beta_d */
+#define PDREF_PARAM_DOUBLES 10
 
 typedef struct pdref pdref;
 
@@ -72,6 +72,8 @@ void pdref_get_bonds(const pdref* s, int64_t* row_ptr, int32_t* col, uint8_t* br
 void pdref_get_state(const pdref* s, double* u, double* v, double* a, double* F);
 void pdref_get_damage(const pdref* s, double* damage, int32_t* intact, int32_t* n0);
 void pdref_get_walls(const pdref* s, double* force /* [n_walls][3] */, double* offset);
+/* time integral of each wall's reaction: sum over completed steps of P_w dt */
+void pdref_get_wall_impulse(const pdref* s, double* impulse /* [n_walls][3] */);
 int64_t pdref_n_candidates(const pdref* s);
 void pdref_get_candidates(const pdref* s, int64_t* row_ptr, int32_t* col);
 /* energies: kinetic, elastic (bonds), contact, gravity potential */

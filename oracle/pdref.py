@@ -59,6 +59,7 @@ def lib():
         L.pdref_get_state.argtypes = [P, P, P, P, P]
         L.pdref_get_damage.argtypes = [P, P, P, P]
         L.pdref_get_walls.argtypes = [P, P, P]
+        L.pdref_get_wall_impulse.argtypes = [P, P]
         L.pdref_n_candidates.argtypes = [P]
         L.pdref_n_candidates.restype = C.c_int64
         L.pdref_get_candidates.argtypes = [P, P, P]
@@ -133,7 +134,8 @@ class Oracle:
             mat=np.array([[m.bulk_modulus, m.density, m.fracture_energy] for m in wl.materials],
                          dtype=np.float64),
             par=np.array([p.horizon_factor, p.contact_radius, p.contact_horizon, p.skin,
-                          p.rebuild_every, p.dt, *p.gravity], dtype=np.float64),
+                          p.rebuild_every, p.dt, *p.gravity, p.contact_damping],
+                         dtype=np.float64),
             walls=pack_walls(wl.walls), cuts=pack_cuts(wl.cuts))
         k = self._keep
         L.pdref_set_threads(threads)
@@ -191,6 +193,12 @@ class Oracle:
         o = np.zeros(max(nw, 1))
         lib().pdref_get_walls(self.h, _p(f), _p(o))
         return f[:nw], o[:nw]
+
+    def wall_impulse(self):
+        nw = len(self.wl.walls)
+        f = np.zeros((max(nw, 1), 3))
+        lib().pdref_get_wall_impulse(self.h, _p(f))
+        return f[:nw]
 
     def candidates(self):
         nc = int(lib().pdref_n_candidates(self.h))

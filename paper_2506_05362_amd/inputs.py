@@ -73,6 +73,7 @@ class Params:
     rebuild_every: int  # candidate rebuild cadence [steps]
     dt: float
     gravity: tuple = (0.0, 0.0, 0.0)
+    contact_damping: float = 0.0  # beta_d of the normal damping law [N s/m^7]; 0 = none
 
 
 @dataclasses.dataclass
@@ -403,6 +404,108 @@ def grain_aggregate(n_grains: int = 100, seed: int = 0, h: float = 1e-4, n_min: 
 
 
 # ----------------------------------------------------------------------------
+# representative volume: a dense tessellated aggregate in a confining box
+# ----------------------------------------------------------------------------
+
+def _hard_core_seeds(rng: np.random.Generator, n: int, L: float, dmin: float) -> np.ndarray:
+    """Random sequential addition of n points in [0, L]^3 at least dmin apart."""
+    pts = np.empty((0, 3))
+    tries = 0
+    while pts.shape[0] < n:
+        c = rng.uniform(0.0, L, size=3)
+        if pts.shape[0] == 0 or np.min(np.sum((pts - c) ** 2, axis=1)) >= dmin * dmin:
+            pts = np.vstack([pts, c])
+        tries += 1
+        if tries > 200 * n:
+            raise RuntimeError("seed placement did not converge; lower dmin")
+    return pts
+
+
+def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1850.0,
+                  h: float = 7e-5, dt: float = 7e-9, confinement: float = 10e6,
+                  platen_speed: float = 10.0, axial_strain: float = 0.05,
+                  servo_gain: float = 5e-7, gap_factor: float = 1.01, material: Material = SAND,
+                  rebuild_every: int = 20, min_grain_nodes: int = 20) -> Workload:
+    """A dense aggregate of polyhedral grains filling a box, confined by six walls.
+
+    The grains are the cells of a Voronoi tessellation of hard-core random
+    seeds, meshed on one cubic lattice with node centres at (i + 1/2) h.  A node
+    is kept when its distance to every bisector plane of its cell is at least
+    half the gap g = gap_factor * R_c, so nodes of different grains start at
+    least g apart (just out of contact) and the aggregate needs no settling.
+    The bottom wall (normal +z) is fixed, the top wall moves down at
+    platen_speed, and the four lateral walls are servo-controlled to the
+    confining stress.  Every wall starts gap_factor * R_c from the nearest node.
+    steps covers axial_strain of the initial wall spacing.
+    """
+    rng = np.random.default_rng(seed)
+    from scipy.spatial import cKDTree
+    params = default_params(h, dt, rebuild_every=rebuild_every)
+    Rc = params.contact_radius
+    g = gap_factor * Rc
+    n_side = int(math.ceil((n_grains * nodes_per_grain) ** (1.0 / 3.0)))
+    L = n_side * h
+    spacing = L / n_grains ** (1.0 / 3.0)
+    seeds = _hard_core_seeds(rng, n_grains, L, 0.75 * spacing)
+    # order grains along a coarse space-filling sweep so neighbours stay close in memory
+    cell = np.floor(seeds / (L / 4.0)).clip(0, 3).astype(np.int64)
+    seeds = seeds[np.lexsort((seeds[:, 0], cell[:, 0], cell[:, 1], cell[:, 2]))]
+    r = np.arange(n_side)
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    lat = np.stack([I.ravel(), J.ravel(), K.ravel()])
+    x = (lat.T + 0.5) * h
+    kq = min(16, n_grains)
+    dist, idx = cKDTree(seeds).query(x, k=kq)
+    own = idx[:, 0]
+    si = seeds[own]
+    margin = np.full(x.shape[0], np.inf)
+    for q in range(1, kq):
+        sj = seeds[idx[:, q]]
+        dsep = np.linalg.norm(sj - si, axis=1)
+        margin = np.minimum(margin, (dist[:, q] ** 2 - dist[:, 0] ** 2) / (2.0 * dsep))
+    keep = margin >= 0.5 * g
+    # exhaustive check: drop any node of a pair of grains closer than g
+    pos = x[keep]
+    gid = own[keep]
+    lat_k = lat[:, keep]
+    pairs = cKDTree(pos).query_pairs(g * (1.0 - 1e-12), output_type="ndarray")
+    if pairs.size:
+        bad = pairs[gid[pairs[:, 0]] != gid[pairs[:, 1]]][:, 1]
+        ok = np.ones(pos.shape[0], dtype=bool)
+        ok[bad] = False
+        pos, gid, lat_k = pos[ok], gid[ok], lat_k[:, ok]
+    blocks = []
+    for gr in range(n_grains):
+        m = gid == gr
+        if int(m.sum()) < min_grain_nodes:
+            continue
+        ijk, origin = _grain_block(lat_k[:, m], np.full(3, 0.5 * h), h)
+        blocks.append((ijk, origin, h, 0))
+    wl = _assemble("rve_aggregate", blocks, [material], params, [], [], 1,
+                   info={"seed": seed, "n_grains": len(blocks), "box": L})
+    lo = wl.X.min(axis=1) - g
+    hi = wl.X.max(axis=1) + g
+    span = hi - lo
+    area = [span[1] * span[2], span[0] * span[2], span[0] * span[1]]
+    wl.walls = [
+        Wall(normal=(0.0, 0.0, 1.0), offset=lo[2], mode=WALL_FIXED, area=area[2]),
+        Wall(normal=(0.0, 0.0, -1.0), offset=-hi[2], mode=WALL_VELOCITY, velocity=platen_speed,
+             area=area[2]),
+    ]
+    for ax in (0, 1):
+        for sgn in (1.0, -1.0):
+            nrm = [0.0, 0.0, 0.0]
+            nrm[ax] = sgn
+            wl.walls.append(Wall(normal=tuple(nrm), offset=lo[ax] if sgn > 0 else -hi[ax],
+                                 mode=WALL_SERVO, target_stress=confinement,
+                                 servo_gain=servo_gain, area=area[ax]))
+    wl.steps = int(math.ceil(axial_strain * span[2] / (platen_speed * dt)))
+    wl.info.update({"span0": span.tolist(), "confinement": confinement,
+                    "platen_speed": platen_speed, "gap": g})
+    return wl
+
+
+# ----------------------------------------------------------------------------
 # named workloads with the sizes of the paper-scale experiments
 # ----------------------------------------------------------------------------
 
@@ -416,4 +519,6 @@ def workload(name: str, **kw) -> Workload:
         return notched_plate(**kw)
     if name == "grain_aggregate":
         return grain_aggregate(**kw)
+    if name == "rve_aggregate":
+        return rve_aggregate(**kw)
     raise KeyError(name)

@@ -312,3 +312,110 @@ def test_moving_wall_offset(oracle_lib):
     o = oracle_lib.Oracle(wl)
     o.step(7)
     assert o.walls()[1][0] == pytest.approx(-1.0 + 3.0 * 7e-8, rel=1e-15)
+
+
+def test_wall_impulse_and_servo_law(oracle_lib):
+    """A fixed node pressed by a fixed wall feels the same reaction every step, so
+    the impulse after n steps is n dt P.  A servo wall with nothing to push moves
+    at gain * target (into the domain for a compressive target); a servo wall whose
+    target is the stress it already carries stays where it is."""
+    h, dt, n = 1e-4, 1e-8, 9
+    off = np.zeros((3, 1), dtype=np.int64)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, dt)
+    Rc = params.contact_radius
+    d = 0.4 * Rc
+    press = I.Wall(normal=(0.0, 0.0, 1.0), offset=-d, mode=I.WALL_FIXED, area=3e-8)
+    free = I.Wall(normal=(1.0, 0.0, 0.0), offset=-5 * Rc, mode=I.WALL_SERVO, target_stress=2e6,
+                  servo_gain=4e-7, area=1e-8)
+    wl = I.assemble("node", [(ijk, origin, h, 0)], [I.SAND], params, [press, free], [], n,
+                    fixed=np.ones(1, dtype=np.uint8))
+    o = oracle_lib.Oracle(wl)
+    P0, _ = o.walls()
+    sigma = -P0[0, 2] / press.area  # -(P . n) / area, n = +z
+    assert sigma > 0
+    o.step(n)
+    P, offs = o.walls()
+    assert np.array_equal(P, P0)
+    imp = o.wall_impulse()
+    assert imp[0, 2] == pytest.approx(n * dt * P0[0, 2], rel=1e-14)
+    assert np.all(imp[1] == 0.0)
+    assert offs[1] == pytest.approx(-5 * Rc + n * dt * 4e-7 * 2e6, rel=1e-13)
+    # equilibrium: a servo wall at the pressing wall's place with that stress as target
+    hold = I.Wall(normal=(0.0, 0.0, 1.0), offset=-d, mode=I.WALL_SERVO, target_stress=sigma,
+                  servo_gain=4e-7, area=3e-8)
+    wl.walls = [hold]
+    o = oracle_lib.Oracle(wl)
+    o.step(n)
+    assert o.walls()[1][0] == -d
+
+
+def _two_nodes(h, dt, gap, speed, beta):
+    off = np.zeros((3, 1), dtype=np.int64)
+    blocks = []
+    for x0 in (0.0, gap):
+        ijk, origin = I.grain_block(off, np.array([x0, 0.0, 0.0]), h)
+        blocks.append((ijk, origin, h, 0))
+    params = I.default_params(h, dt)
+    params.contact_damping = beta
+    v0 = np.zeros((3, 2))
+    v0[0, 0], v0[0, 1] = 0.5 * speed, -0.5 * speed
+    return I.assemble("pair", blocks, [I.SAND], params, [], [], 1, v0=v0), params
+
+
+def _restitution(oracle_lib, h, dt, zeta):
+    """Head-on collision of two one-node grains; returns outgoing / incoming speed."""
+    V = h ** 3
+    Kn = 18 * I.SAND.bulk_modulus / (math.pi * (3 * h) ** 5)
+    w0 = math.sqrt(2.0 * Kn * V / I.SAND.density)  # relative coordinate, reduced mass rho V / 2
+    beta = zeta * I.SAND.density * w0 / V
+    Rc = 0.95 * h
+    wl, _ = _two_nodes(h, dt, Rc * 1.0001, 2.0, beta)
+    o = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    T = math.pi / w0
+    for _ in range(int(3 * T / dt) // 10):
+        o.step(10)
+        s = o.state()
+        gap = (wl.X[0, 1] + s["u"][0, 1]) - (wl.X[0, 0] + s["u"][0, 0])
+        if gap > Rc and s["v"][0, 1] > s["v"][0, 0]:
+            return (s["v"][0, 1] - s["v"][0, 0]) / 2.0
+    raise AssertionError("no separation")
+
+
+def test_contact_damping_restitution_matches_spring_dashpot(oracle_lib):
+    """Two one-node grains form a linear spring (K_n V^2) and dashpot (beta_d V^2):
+    the coefficient of restitution of a head-on collision is
+    exp(-pi zeta / sqrt(1 - zeta^2)); without damping it is 1."""
+    h = 1e-4
+    assert _restitution(oracle_lib, h, 1e-9, 0.0) == pytest.approx(1.0, abs=2e-5)
+    zeta = 0.2
+    exact = math.exp(-math.pi * zeta / math.sqrt(1.0 - zeta * zeta))
+    # contact starts and ends between steps: an O(omega dt) error, omega dt = 5e-3 here
+    for dt in (1e-9, 5e-10):
+        assert abs(_restitution(oracle_lib, h, dt, zeta) - exact) < 3e-3 * exact
+
+
+def test_wall_damping_uses_the_wall_rate(oracle_lib):
+    """A node moving with a velocity wall feels no damping; one approaching a fixed
+    wall is pushed back harder, by an amount linear in beta_d."""
+    h, dt = 1e-4, 1e-9
+    off = np.zeros((3, 1), dtype=np.int64)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, dt)
+    d = 0.5 * params.contact_radius
+    v0 = np.zeros((3, 1))
+
+    def force(beta, mode, vz, rate=0.0):
+        params.contact_damping = beta
+        v0[2, 0] = vz
+        wall = I.Wall(normal=(0.0, 0.0, 1.0), offset=-d, mode=mode, velocity=rate)
+        wl = I.assemble("node", [(ijk, origin, h, 0)], [I.SAND], params, [wall], [], 1, v0=v0)
+        return oracle_lib.Oracle(wl).state()["F"][:, 0]
+
+    F0 = force(0.0, I.WALL_VELOCITY, 3.0, 3.0)
+    assert np.array_equal(force(1e21, I.WALL_VELOCITY, 3.0, 3.0), F0)
+    Ff = force(0.0, I.WALL_FIXED, -2.0)
+    F1 = force(1e21, I.WALL_FIXED, -2.0)
+    F2 = force(2e21, I.WALL_FIXED, -2.0)
+    assert F1[2] > Ff[2]
+    assert (F2[2] - Ff[2]) == pytest.approx(2.0 * (F1[2] - Ff[2]), rel=1e-12)
