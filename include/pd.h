@@ -98,9 +98,17 @@ typedef struct {
   double contact_horizon;  /* eps in K_n = 18 k / (pi eps^5) [m] */
   double skin;             /* Verlet skin [m]: candidates are other-grain nodes within R_c + skin */
   int32_t rebuild_every;   /* candidate rebuild cadence in steps (>= 1) */
-  int32_t candidate_capacity_per_node; /* capacity of the candidate list, per node (0 = 16) */
+  int32_t candidate_capacity_per_node; /* candidate list capacity: N times this in total and
+                                          twice this for any one node (0 = 16); exceeding
+                                          either raises PD_ERR_UNSTABLE */
   double dt;               /* time step [s] */
   double gravity[3];       /* body force per unit mass [m/s^2] */
+  double contact_damping;  /* beta_d of the normal damping law (Sec. 3.4) [N s/m^7], >= 0;
+                              0 disables it.  Between nodes of different grains within R_c
+                              the force density on i is -beta_d (w . e) e V_j, w = velocity of
+                              i relative to j, e the unit vector from i to j; against a wall
+                              -beta_d (v . n - wall rate) |S| n.  Velocities are the mid-step
+                              values v_n + dt/2 a_n (v_0 in the first evaluation). */
 } pd_params;
 
 enum { PD_WALL_FIXED = 0, PD_WALL_VELOCITY = 1, PD_WALL_SERVO = 2 };
@@ -149,7 +157,9 @@ typedef enum {
   PD_WALL_FORCE = 12,     /* [n_walls][3] f64 reaction P_w = -sum_i V_i F_wall,i (last evaluation) */
   PD_WALL_OFFSET = 13,    /* [n_walls] f64 wall offset used by the last evaluation */
   PD_ENERGY = 14,         /* [4] f64 kinetic, elastic (bonds), contact, gravity potential [J] */
-  PD_STEP = 15            /* [1] i64 completed steps */
+  PD_STEP = 15,           /* [1] i64 completed steps */
+  PD_WALL_IMPULSE = 16    /* [n_walls][3] f64 sum over completed steps of P_w dt: the
+                             reaction averaged over steps a..b is (I_b - I_a) / ((b - a) dt) */
 } pd_field;
 
 /* Create a context: validates and copies the problem to the device.

@@ -44,8 +44,10 @@ int64_t pdm_param_count(const pdm_net* net);
 /* Load parameters (host FP32 vector of pdm_param_count entries); resets Adam. */
 pd_status pdm_set_params(pdm_net* net, const float* params, int64_t n);
 pd_status pdm_get_params(pdm_net* net, float* params, int64_t n);
-/* Adam hyper-parameters (defaults 0.9, 0.999, 1e-8). */
-pd_status pdm_set_adam(pdm_net* net, float beta1, float beta2, float eps);
+/* Adam hyper-parameters (defaults 0.9, 0.999, 1e-8, 0): the update is
+   p -= lr (m_hat / (sqrt(v_hat) + eps) + weight_decay p), decay decoupled from
+   the gradient moments. */
+pd_status pdm_set_adam(pdm_net* net, float beta1, float beta2, float eps, float weight_decay);
 /* Inference: y[batch][dims[n-1]] = net(x[batch][dims[0]]); any batch size
    (processed in chunks of max_batch). */
 pd_status pdm_forward(pdm_net* net, const float* x, int64_t batch, float* y);

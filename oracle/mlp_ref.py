@@ -90,10 +90,11 @@ def gradients(params, dims, X, Y):
     return np.concatenate([np.concatenate([gW.ravel(), gb]) for gW, gb in grads])
 
 
-def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8):
-    """One Adam update (t counts from 1); returns new params, m, v."""
+def adam_step(params, grad, m, v, t, lr, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+    """One Adam update (t counts from 1) with decoupled weight decay; returns new
+    params, m, v."""
     m = beta1 * m + (1.0 - beta1) * grad
     v = beta2 * v + (1.0 - beta2) * grad * grad
     mhat = m / (1.0 - beta1 ** t)
     vhat = v / (1.0 - beta2 ** t)
-    return params - lr * mhat / (np.sqrt(vhat) + eps), m, v
+    return params - lr * (mhat / (np.sqrt(vhat) + eps) + weight_decay * params), m, v

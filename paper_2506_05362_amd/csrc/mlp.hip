@@ -153,8 +153,9 @@ __global__ void k_colsum(const float* dz, int64_t M, int64_t N, float* db) {
   db[n] = s;
 }
 
+// Adam with decoupled weight decay: p -= lr (m_hat / (sqrt(v_hat) + eps) + wd p)
 __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, float lr, float b1,
-                       float b2, float eps, float c1, float c2) {
+                       float b2, float eps, float wd, float c1, float c2) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const float gi = g[i];
@@ -162,7 +163,8 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
   m[i] = mi;
   v[i] = vi;
-  p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  const float pi = p[i];
+  p[i] = pi - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * pi);
 }
 
 }  // namespace
@@ -179,7 +181,7 @@ struct pdm_net {
   double* partial = nullptr;
   int nloss_blocks = 0;
   std::vector<int64_t> woff, boff;  // offsets of W_l, b_l in the parameter vector
-  float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f;
+  float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f, weight_decay = 0.0f;
   int64_t t = 0;
   std::vector<void*> owned;
 };
@@ -392,9 +394,11 @@ pd_status pdm_get_params(pdm_net* n, float* p, int64_t cnt) {
   return PD_OK;
 }
 
-pd_status pdm_set_adam(pdm_net* n, float b1, float b2, float eps) {
+pd_status pdm_set_adam(pdm_net* n, float b1, float b2, float eps, float weight_decay) {
   if (!n) return PD_ERR_INVALID;
-  if (!(b1 >= 0 && b1 < 1 && b2 >= 0 && b2 < 1 && eps > 0)) return fail(n, PD_ERR_INVALID, "bad Adam parameters");
+  if (!(b1 >= 0 && b1 < 1 && b2 >= 0 && b2 < 1 && eps > 0 && weight_decay >= 0))
+    return fail(n, PD_ERR_INVALID, "bad Adam parameters");
+  n->weight_decay = weight_decay;
   n->beta1 = b1;
   n->beta2 = b2;
   n->eps = eps;
@@ -429,7 +433,7 @@ pd_status pdm_train_step(pdm_net* n, const float* x, const float* y, int64_t bat
   n->t += 1;
   const float c1 = 1.0f - powf(n->beta1, (float)n->t), c2 = 1.0f - powf(n->beta2, (float)n->t);
   hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->n_params + 255) / 256)), dim3(256), 0, n->stream, n->params,
-                     n->grad, n->m, n->v, n->n_params, lr, n->beta1, n->beta2, n->eps, c1, c2);
+                     n->grad, n->m, n->v, n->n_params, lr, n->beta1, n->beta2, n->eps, n->weight_decay, c1, c2);
   HIPCHK(n, hipGetLastError());
   if (!loss) HIPCHK(n, hipStreamSynchronize(n->stream));
   return PD_OK;

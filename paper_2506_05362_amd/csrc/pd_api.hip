@@ -28,7 +28,7 @@ struct pd_ctx {
   int64_t n = 0;
   int32_t n_grains = 0, n_mat = 0, n_walls = 0;
   int32_t m = 3, flags = 0, rebuild_every = 1, cap_per_node = 16;
-  double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0};
+  double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0}, beta = 0;
   hipStream_t stream = nullptr;
   int own_stream = 0;
   pd_alloc_fn alloc = nullptr;
@@ -46,6 +46,7 @@ struct pd_ctx {
   std::vector<void*> owned;
   // device state
   double4* u4[2] = {nullptr, nullptr};
+  double4* vh[2] = {nullptr, nullptr};  // mid-step velocities, indexed like u4 (beta > 0)
   double *v = nullptr, *a = nullptr, *X = nullptr, *F = nullptr;
   uint8_t* fixed = nullptr;
   GrainC* grains = nullptr;
@@ -69,8 +70,12 @@ struct pd_ctx {
   // contact
   uint32_t T = 0;
   int64_t capacity = 0;
-  int32_t *cellc = nullptr, *bucket_count = nullptr, *bucket_start = nullptr,
-          *bucket_fill = nullptr, *sorted = nullptr, *cand_ptr = nullptr, *cand = nullptr;
+  long long* cellkey = nullptr;
+  int4* srec = nullptr;
+  int32_t* cand_scratch = nullptr;
+  int32_t scratch_w = 32;
+  int32_t *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr,
+          *cand_ptr = nullptr, *cand = nullptr;
   uint32_t* cellh = nullptr;
   double* u_build = nullptr;
   long long* gbox = nullptr;
@@ -174,6 +179,7 @@ WallDev to_dev(const pd_wall& w, int64_t next_step, double dt) {
   d.gain = w.servo_gain;
   d.area = w.area;
   d.mode = w.mode;
+  d.rate = d.rate_used = w.mode == PD_WALL_VELOCITY ? w.velocity : 0.0;
   return d;
 }
 
@@ -193,6 +199,9 @@ StepArgs step_args(pd_ctx* c) {
   A.v = c->v;
   A.a = c->a;
   A.Fout = c->F;
+  A.vh_cur = c->vh[c->cur];
+  A.vh_next = c->vh[c->cur ^ 1];
+  A.beta = c->beta;
   A.fixed = c->fixed;
   A.grains = c->grains;
   A.stencil = c->stencil;
@@ -230,12 +239,14 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   ContactArgs C{};
   C.u = c->u4[buf];
   C.X = c->X;
-  C.cellc = c->cellc;
+  C.cellkey = c->cellkey;
+  C.srec = c->srec;
+  C.cand_scratch = c->cand_scratch;
+  C.scratch_w = c->scratch_w;
   C.cellh = c->cellh;
   C.bucket_count = c->bucket_count;
   C.bucket_start = c->bucket_start;
   C.bucket_fill = c->bucket_fill;
-  C.sorted = c->sorted;
   C.cand_count = c->cand_ptr;
   C.cand = c->cand;
   C.u_build = c->u_build;
@@ -424,6 +435,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     return fail(c, PD_ERR_INVALID, "contact radius/horizon must be > 0 and skin >= 0");
   if (!(P.dt > 0)) return fail(c, PD_ERR_INVALID, "dt must be > 0");
   if (P.rebuild_every < 1) return fail(c, PD_ERR_INVALID, "rebuild_every must be >= 1");
+  if (!(P.contact_damping >= 0) || !isfinite(P.contact_damping))
+    return fail(c, PD_ERR_INVALID, "contact_damping must be finite and >= 0");
   if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
@@ -438,6 +451,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->eps = P.contact_horizon;
   c->skin = P.skin;
   c->dt = P.dt;
+  c->beta = P.contact_damping;
   c->rebuild_every = P.rebuild_every;
   c->use_graph = (P.flags & PD_FLAG_NO_GRAPH) ? 0 : 1;
   c->graph_len = (P.rebuild_every % 2 == 0) ? P.rebuild_every : 2 * (int64_t)P.rebuild_every;
@@ -560,6 +574,19 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   else
     HIPCHK(c, hipMemsetAsync(c->v, 0, sizeof(double) * 3 * N, s));
   HIPCHK(c, hipMemsetAsync(c->a, 0, sizeof(double) * 3 * N, s));
+  if (c->beta > 0) {
+    // the first evaluation's damping sees v_0 (zero on fixed nodes)
+    TRY(alloc_n(c, &c->vh[0], N, "mid-step velocity"));
+    TRY(alloc_n(c, &c->vh[1], N, "mid-step velocity'"));
+    std::vector<double4> vh0((size_t)N, make_double4(0.0, 0.0, 0.0, 0.0));
+    if (mesh->v0)
+      for (int64_t i = 0; i < N; ++i)
+        if (!(mesh->fixed && mesh->fixed[i]))
+          vh0[(size_t)i] = make_double4(mesh->v0[i], mesh->v0[N + i], mesh->v0[2 * N + i], 0.0);
+    HIPCHK(c, hipMemcpyAsync(c->vh[0], vh0.data(), sizeof(double4) * N, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipMemcpyAsync(c->vh[1], vh0.data(), sizeof(double4) * N, hipMemcpyHostToDevice, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+  }
   // packed u buffers: (u0, ijk | grain << 32)
   {
     double* u0d;
@@ -737,12 +764,14 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   while ((int64_t)T < 2 * N) T <<= 1;
   c->T = T;
   c->capacity = std::max<int64_t>((int64_t)c->cap_per_node * N, 1 << 16);
-  TRY(alloc_n(c, &c->cellc, 3 * N, "cell coordinates"));
+  c->scratch_w = 2 * c->cap_per_node;
+  TRY(alloc_n(c, &c->cellkey, N, "cell keys"));
+  TRY(alloc_n(c, &c->srec, N, "binned records"));
+  TRY(alloc_n(c, &c->cand_scratch, (int64_t)c->scratch_w * N, "candidate scratch rows"));
   TRY(alloc_n(c, &c->cellh, N, "cell hashes"));
   TRY(alloc_n(c, &c->bucket_count, T, "bucket counts"));
   TRY(alloc_n(c, &c->bucket_start, (int64_t)T + 1, "bucket starts"));
   TRY(alloc_n(c, &c->bucket_fill, T, "bucket fill"));
-  TRY(alloc_n(c, &c->sorted, N, "binned nodes"));
   TRY(alloc_n(c, &c->cand_ptr, N + 1, "candidate rows"));
   TRY(alloc_n(c, &c->cand, c->capacity, "candidates"));
   TRY(alloc_n(c, &c->u_build, 3 * N, "positions at rebuild"));
@@ -861,6 +890,7 @@ pd_status pd_field_bytes(pd_ctx* c, pd_field f, int64_t* bytes) {
     }
     case PD_WALL_FORCE: *bytes = 24 * c->n_walls; return PD_OK;
     case PD_WALL_OFFSET: *bytes = 8 * c->n_walls; return PD_OK;
+    case PD_WALL_IMPULSE: *bytes = 24 * c->n_walls; return PD_OK;
     case PD_ENERGY: *bytes = 32; return PD_OK;
     case PD_STEP: *bytes = 8; return PD_OK;
   }
@@ -962,7 +992,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       }
       return deliver(host.data());
     }
-    case PD_WALL_FORCE: case PD_WALL_OFFSET: {
+    case PD_WALL_FORCE: case PD_WALL_OFFSET: case PD_WALL_IMPULSE: {
       std::vector<WallDev> w((size_t)std::max(c->n_walls, 1));
       if (c->n_walls) {
         HIPCHK(c, hipMemcpyAsync(w.data(), c->walls, sizeof(WallDev) * c->n_walls, hipMemcpyDeviceToHost, s));
@@ -972,6 +1002,8 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       for (int32_t k = 0; k < c->n_walls; ++k) {
         if (f == PD_WALL_FORCE)
           for (int q = 0; q < 3; ++q) o[3 * k + q] = w[(size_t)k].force[q];
+        else if (f == PD_WALL_IMPULSE)
+          for (int q = 0; q < 3; ++q) o[3 * k + q] = w[(size_t)k].impulse[q];
         else
           o[k] = c->built ? w[(size_t)k].off_used : w[(size_t)k].off;
       }
@@ -1005,7 +1037,10 @@ pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
   HIPCHK(c, hipStreamSynchronize(c->stream));
   WallDev d = to_dev(*wall, c->built ? c->step + 1 : 0, c->dt);
   d.off_used = old.off_used;
-  for (int q = 0; q < 3; ++q) d.force[q] = old.force[q];
+  for (int q = 0; q < 3; ++q) {
+    d.force[q] = old.force[q];
+    d.impulse[q] = old.impulse[q];
+  }
   HIPCHK(c, hipMemcpyAsync(c->walls + w, &d, sizeof(WallDev), hipMemcpyHostToDevice, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->walls_h[(size_t)w] = d;
@@ -1013,14 +1048,16 @@ pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
 }
 
 // checkpoint layout: header[8] (magic, n, padded, n_walls, step, cur, nnz, crc-less size),
-// then u4[cur], u4[cur^1], v, a, live column words, intact, u_build, walls, crc32
+// then u4[cur], u4[cur^1], v, a, live column words, intact, u_build, walls,
+// [vh[cur], vh[cur^1] when damping is on], crc32
 pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   if (!c || !bytes) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   const int64_t N = c->n;
   const int64_t words = c->padded;
+  const int64_t nvh = c->beta > 0 ? 2 * 32 * N : 0;
   const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
-                       (int64_t)sizeof(WallDev) * c->n_walls;
+                       (int64_t)sizeof(WallDev) * c->n_walls + nvh;
   const int64_t total = body + 4;
   if (!blob) {
     *bytes = total;
@@ -1045,6 +1082,10 @@ pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   TRY(grab(c->intact, 4 * N));
   TRY(grab(c->u_build, 24 * N));
   TRY(grab(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));
+  if (nvh) {
+    TRY(grab(c->vh[c->cur], 32 * N));
+    TRY(grab(c->vh[c->cur ^ 1], 32 * N));
+  }
   HIPCHK(c, hipStreamSynchronize(s));
   const uint32_t crc = crc32_update(0, p, (size_t)body);
   memcpy(p + body, &crc, 4);
@@ -1060,8 +1101,9 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   int64_t hdr[8];
   memcpy(hdr, p, sizeof hdr);
   const int64_t N = c->n, words = c->padded;
+  const int64_t nvh = c->beta > 0 ? 2 * 32 * N : 0;
   const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
-                       (int64_t)sizeof(WallDev) * c->n_walls;
+                       (int64_t)sizeof(WallDev) * c->n_walls + nvh;
   if (hdr[0] != (int64_t)kMagic || hdr[1] != N || hdr[2] != c->padded || hdr[3] != c->n_walls ||
       hdr[6] != c->nnz || hdr[7] != body || bytes != body + 4)
     return fail(c, PD_ERR_CORRUPT, "checkpoint does not match this context");
@@ -1084,6 +1126,10 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   TRY(put(c->intact, 4 * N));
   TRY(put(c->u_build, 24 * N));
   TRY(put(c->walls, (int64_t)sizeof(WallDev) * c->n_walls));
+  if (nvh) {
+    TRY(put(c->vh[c->cur], 32 * N));
+    TRY(put(c->vh[c->cur ^ 1], 32 * N));
+  }
   c->step = hdr[4];
   HIPCHK(c, hipMemcpyAsync(c->step_d, &c->step, 8, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipStreamSynchronize(s));

@@ -61,7 +61,10 @@ struct WallDev {
   double vel;
   double lo[3], hi[3];
   double target, gain, area;
+  double rate;      // d(offset)/dt over the step into the next evaluation
+  double rate_used; // the same for the last evaluation
   double force[3];  // reaction of the last evaluation
+  double impulse[3];  // sum over completed steps of force * dt
   int32_t mode;
   int32_t pad;
 };
@@ -87,6 +90,8 @@ struct StepArgs {
   double* v;            // SoA
   double* a;            // SoA
   double* Fout;         // MODE_FORCE_ONLY output (SoA)
+  const double4* vh_cur;  // mid-step velocity seen by the damping law (beta > 0 only)
+  double4* vh_next;       // ... written for the next evaluation
   const uint8_t* fixed;
   const GrainC* grains;
   const StencilC* stencil;  // [n_classes][n_stencil + 1]
@@ -104,7 +109,7 @@ struct StepArgs {
   const double* X;      // SoA, contact path only
   const double* Kn;     // [n_mat * n_mat]
   WallDev* walls;
-  double* wall_partial;  // [nblocks][n_walls][3]
+  double* wall_partial;  // [n_walls][3][nblocks] (component-major)
   int64_t* step;         // device step counter
   int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;
@@ -115,6 +120,7 @@ struct StepArgs {
   double Rc, Rc2;
   double dt;
   double g[3];
+  double beta;           // normal damping coefficient, 0 = off
   int32_t abs_stretch;
 };
 
@@ -141,12 +147,14 @@ struct BuildArgs {
 struct ContactArgs {
   const double4* u;
   const double* X;
-  int32_t* cellc;        // [3N]
+  long long* cellkey;    // [N] packed cell coordinates of each binned node
   uint32_t* cellh;       // [N]
   int32_t* bucket_count;  // [T]
   int32_t* bucket_start;  // [T+1]
   int32_t* bucket_fill;   // [T]
-  int32_t* sorted;        // [N]
+  int4* srec;             // [N] bucket-sorted (node, grain, cell key lo, hi)
+  int32_t* cand_scratch;  // [N][scratch_w] unsorted candidates of each node
+  int32_t scratch_w;
   int32_t* cand_count;    // [N+1] (scanned in place to cand_ptr)
   int32_t* cand;
   double* u_build;        // SoA

@@ -351,6 +351,11 @@ void k_step(StepArgs A) {
     }
   }
 
+  // mid-step velocity of this node for the normal damping law (Sec. 3.4)
+  const bool damp = A.beta > 0.0;
+  double4 vhi = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (damp && valid) vhi = A.vh_cur[i];
+
   // ---- repulsive contact with candidates of other grains (Sec. 3.2) ----
   if (valid && A.cand_ptr != nullptr) {
     // rows past the capacity were not stored (the rebuild flagged it)
@@ -368,7 +373,13 @@ void k_step(StepArgs A) {
         if (d2 < A.Rc2 && d2 > 0.0) {
           const GrainC* Gj = A.grains + packed_grain(uj.w);
           const double d = sqrt(d2);
-          const double coef = -A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V / d;
+          double coef = -A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V / d;
+          if (damp) {
+            // -beta (w . e) e V_j, w = velocity of i relative to j, e = y / d
+            const double4 vhj = A.vh_cur[j];
+            const double w = (vhi.x - vhj.x) * yx + (vhi.y - vhj.y) * yy + (vhi.z - vhj.z) * yz;
+            coef -= A.beta * Gj->V * w / d2;
+          }
           fx = fma(coef, yx, fx);
           fy = fma(coef, yy, fy);
           fz = fma(coef, yz, fz);
@@ -400,6 +411,12 @@ void k_step(StepArgs A) {
           const double vol = (M_PI / 3.0) * H * H * q;
           const double ell = 0.75 * (A.Rc + d) * (A.Rc + d) / q;
           mag = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
+          if (damp) {
+            // damping against the wall: relative normal velocity v . n - wall rate
+            const double rate = MODE == MODE_FORCE_ONLY ? Wd->rate_used : Wd->rate;
+            const double vn = Wd->n[0] * vhi.x + Wd->n[1] * vhi.y + Wd->n[2] * vhi.z;
+            mag -= A.beta * (vn - rate) * vol;
+          }
           hit = true;
         }
       }
@@ -461,6 +478,11 @@ void k_step(StepArgs A) {
         un.z = fma(hdt2, anz, fma(dt, vz, ui.z));
       }
       A.unext[i] = un;
+      if (damp) {
+        // the next evaluation's damping sees v_{n+1} + dt/2 a_{n+1}
+        A.vh_next[i] = fixed ? make_double4(0.0, 0.0, 0.0, 0.0)
+                             : make_double4(fma(hdt, anx, vx), fma(hdt, any, vy), fma(hdt, anz, vz), 0.0);
+      }
       if (nbroke) A.intact[i] -= nbroke;
     }
   }
@@ -472,15 +494,15 @@ void k_step(StepArgs A) {
     if (tid < 3 * A.n_walls) {
       double s = 0.0;
       for (int q = 0; q < kSlicesPerBlock; ++q) s += s_wall[q][tid];
-      A.wall_partial[blk * 3 * A.n_walls + tid] = s;
+      A.wall_partial[(int64_t)tid * gridDim.x + blk] = s;  // component-major
     }
   }
 }
 
 // reaction forces (fixed-order sum of block partials) and the wall positions
 // of the next step: prescribed velocity or servo on the measured stress.
-// One workgroup of 1024 threads; every thread loads its share of all
-// components first (one memory round trip), then a fixed-order LDS tree.
+// One workgroup of 1024 threads; thread t sums blocks t, t + 1024, ... of
+// every component, then a fixed-order reduction over lanes and waves.
 __global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblocks) {
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -488,11 +510,25 @@ __global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblo
   double acc[kMaxWalls * 3];
 #pragma unroll
   for (int c = 0; c < kMaxWalls * 3; ++c) acc[c] = 0.0;
-  for (int b = tid; b < nblocks; b += 1024) {
-    const double* p = A.wall_partial + (int64_t)b * nc;
+  // component-major partials: lanes read consecutive blocks (coalesced); the
+  // loads of 8 components x 4 blocks are issued together, then summed in block order
 #pragma unroll
-    for (int c = 0; c < kMaxWalls * 3; ++c)
-      if (c < nc) acc[c] += p[c];
+  for (int c0 = 0; c0 < kMaxWalls * 3; c0 += 8) {
+    if (c0 >= nc) break;
+    for (int b0 = tid; b0 < nblocks; b0 += 4 * 1024) {
+      double v[8][4];
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int c = c0 + cc, b = b0 + 1024 * k;
+          v[cc][k] = (c < nc && b < nblocks) ? A.wall_partial[(int64_t)c * nblocks + b] : 0.0;
+        }
+#pragma unroll
+      for (int cc = 0; cc < 8; ++cc)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) acc[c0 + cc] += v[cc][k];
+    }
   }
 #pragma unroll
   for (int c = 0; c < kMaxWalls * 3; ++c) {
@@ -502,24 +538,36 @@ __global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblo
     }
   }
   __syncthreads();
-  if (tid == 0) {
-    const int64_t s = *A.step + A.advance;  // the step this evaluation belonged to
-    *A.step = s;
-    for (int w = 0; w < A.n_walls; ++w) {
-      WallDev& W = A.walls[w];
-      for (int q = 0; q < 3; ++q) {
-        double t = 0.0;
-        for (int k = 0; k < 1024 / kWave; ++k) t += red[3 * w + q][k];
-        W.force[q] = -t;
-      }
-      W.off_used = W.off;
-      if (W.mode == PD_WALL_VELOCITY) {
-        W.off = W.off0 + W.vel * ((double)(s + 1) * A.dt);
-      } else if (W.mode == PD_WALL_SERVO) {
-        const double sigma = -(W.force[0] * W.n[0] + W.force[1] * W.n[1] + W.force[2] * W.n[2]) / W.area;
-        W.off = W.off + A.dt * W.gain * (W.target - sigma);
-      }
+  // one thread per component sums the 16 wave partials (fixed order)
+  __shared__ double tot[kMaxWalls * 3];
+  __shared__ int64_t s_step;
+  if (tid < nc) {
+    double t = 0.0;
+    for (int k = 0; k < 1024 / kWave; ++k) t += red[tid][k];
+    tot[tid] = t;
+  }
+  if (tid == 0) s_step = *A.step + A.advance;  // the step this evaluation belonged to
+  __syncthreads();
+  const int64_t s = s_step;
+  if (tid == 0) *A.step = s;
+  // one thread per wall: its loads are independent of the other walls'
+  if (tid < A.n_walls) {
+    WallDev W = A.walls[tid];
+    for (int q = 0; q < 3; ++q) {
+      W.force[q] = -tot[3 * tid + q];
+      if (A.advance) W.impulse[q] += W.force[q] * A.dt;
     }
+    W.off_used = W.off;
+    W.rate_used = W.rate;
+    if (W.mode == PD_WALL_VELOCITY) {
+      W.off = W.off0 + W.vel * ((double)(s + 1) * A.dt);
+      W.rate = W.vel;
+    } else if (W.mode == PD_WALL_SERVO) {
+      const double sigma = -(W.force[0] * W.n[0] + W.force[1] * W.n[1] + W.force[2] * W.n[2]) / W.area;
+      W.rate = W.gain * (W.target - sigma);
+      W.off = W.off + A.dt * W.rate;
+    }
+    A.walls[tid] = W;
   }
 }
 
@@ -605,10 +653,20 @@ __device__ __forceinline__ uint32_t cell_hash(int cx, int cy, int cz, uint32_t T
          (T - 1u);
 }
 
+// cell coordinates are clamped to |c| < 2^20 - 1 so that a cell and its
+// neighbours pack into one 63-bit key (21 bits per axis); nodes beyond the clamp
+// share boundary cells and are still separated by the exact distance test
+constexpr int kCellClamp = (1 << 20) - 2;
+
 __device__ __forceinline__ int cell_coord(double p, double inv_cell) {
   double c = floor(p * inv_cell);
-  c = fmin(fmax(c, -1.0e9), 1.0e9);
+  c = fmin(fmax(c, -(double)kCellClamp), (double)kCellClamp);
   return (int)c;
+}
+
+__device__ __forceinline__ long long cell_key(int cx, int cy, int cz) {
+  return ((long long)(cx + (1 << 20)) << 42) | ((long long)(cy + (1 << 20)) << 21) |
+         (long long)(cz + (1 << 20));
 }
 
 // Grain-box culling.  A pair (i, j) of different grains closer than the
@@ -676,11 +734,11 @@ __global__ __launch_bounds__(256) void k_box(ContactArgs c) {
   else if (tid < 6) atomicMax(c.gbox + 6 * g + tid, red[tid][0]);
 }
 
-// grain boxes closer than the cutoff (one thread per grain, plain loop over the others)
+// grain boxes closer than the cutoff: one wavefront per grain, the others
+// tested 64 at a time; ballot prefix counts keep each list in ascending order
 template <bool FILL>
-__global__ void k_box_pairs(ContactArgs c, double cut) {
-  const int a = blockIdx.x * blockDim.x + threadIdx.x;
-  if (a >= c.n_grains) return;
+__global__ __launch_bounds__(kWave) void k_box_pairs(ContactArgs c, double cut) {
+  const int a = blockIdx.x, lane = threadIdx.x;
   double alo[3], ahi[3];
   for (int q = 0; q < 3; ++q) {
     alo[q] = ord_val(c.gbox[6 * a + q]) - cut;
@@ -688,16 +746,17 @@ __global__ void k_box_pairs(ContactArgs c, double cut) {
   }
   int cnt = 0;
   const int base = FILL ? c.gpair_count[a] : 0;
-  for (int b = 0; b < c.n_grains; ++b) {
-    if (b == a) continue;
-    bool ov = true;
-    for (int q = 0; q < 3; ++q)
-      ov = ov && ord_val(c.gbox[6 * b + q]) <= ahi[q] && ord_val(c.gbox[6 * b + 3 + q]) >= alo[q];
-    if (!ov) continue;
-    if (FILL) c.gpair[base + cnt] = b;
-    ++cnt;
+  for (int b0 = 0; b0 < c.n_grains; b0 += kWave) {
+    const int b = b0 + lane;
+    bool ov = b < c.n_grains && b != a;
+    if (ov)
+      for (int q = 0; q < 3; ++q)
+        ov = ov && ord_val(c.gbox[6 * b + q]) <= ahi[q] && ord_val(c.gbox[6 * b + 3 + q]) >= alo[q];
+    const uint64_t m = __ballot(ov);
+    if (FILL && ov) c.gpair[base + cnt + __popcll(m & ((1ull << lane) - 1ull))] = b;
+    cnt += __popcll(m);
   }
-  if (!FILL) c.gpair_count[a] = cnt;
+  if (!FILL && lane == 0) c.gpair_count[a] = cnt;
 }
 
 __global__ void k_active(ContactArgs c, double cut) {
@@ -724,9 +783,7 @@ __global__ void k_bin(ContactArgs c) {
   const int cx = cell_coord(c.X[i] + u.x, c.inv_cell);
   const int cy = cell_coord(c.X[c.n + i] + u.y, c.inv_cell);
   const int cz = cell_coord(c.X[2 * c.n + i] + u.z, c.inv_cell);
-  c.cellc[3 * i] = cx;
-  c.cellc[3 * i + 1] = cy;
-  c.cellc[3 * i + 2] = cz;
+  c.cellkey[i] = cell_key(cx, cy, cz);
   const uint32_t hsh = cell_hash(cx, cy, cz, c.T);
   c.cellh[i] = hsh;
   atomicAdd(c.bucket_count + hsh, 1);
@@ -737,51 +794,68 @@ __global__ void k_scatter(ContactArgs c) {
   if (i >= c.n || !c.active[i]) return;
   const uint32_t hsh = c.cellh[i];
   const int pos = c.bucket_start[hsh] + atomicAdd(c.bucket_fill + hsh, 1);
-  c.sorted[pos] = (int32_t)i;
+  const long long key = c.cellkey[i];
+  c.srec[pos] = make_int4((int)i, packed_grain(c.u[i].w), (int)(key & 0xffffffffll), (int)(key >> 32));
 }
 
-template <bool FILL>
-__global__ void k_candidates(ContactArgs c) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n) return;
-  if (!c.active[i]) {
-    if (!FILL) c.cand_count[i] = 0;
-    return;
-  }
+// Search: every record of the 27 neighbouring cells' buckets is one 16-byte
+// load (node, grain, cell key); records of other cells sharing the bucket and
+// of the node's own grain are skipped before any position is read.  Threads
+// walk the binned nodes in bucket order, so the nodes of one cell sit in
+// neighbouring lanes and read the same buckets.  Hits go to a fixed-width
+// scratch row; counts beyond the width raise the overflow flag.  Rows of
+// nodes that were not binned stay at zero (cleared before the launch).
+__global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
+  const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e0 >= c.bucket_start[c.T]) return;
+  const int4 me = c.srec[e0];
+  const int64_t i = me.x;
+  const int gi = me.y;
   const double4 ui = c.u[i];
-  const int gi = packed_grain(ui.w);
-  const int cx = c.cellc[3 * i], cy = c.cellc[3 * i + 1], cz = c.cellc[3 * i + 2];
+  const long long key = ((long long)me.w << 32) | (long long)(uint32_t)me.z;
+  const int cx = (int)((key >> 42) & 0x1fffff) - (1 << 20);
+  const int cy = (int)((key >> 21) & 0x1fffff) - (1 << 20);
+  const int cz = (int)(key & 0x1fffff) - (1 << 20);
   const double Xx = c.X[i], Xy = c.X[c.n + i], Xz = c.X[2 * c.n + i];
+  int32_t* row = c.cand_scratch + i * (int64_t)c.scratch_w;
   int cnt = 0;
-  int64_t base = 0;
-  if (FILL) base = c.cand_count[i];  // already scanned into row pointers
   for (int d = 0; d < kCellDirs; ++d) {
     const int nx = cx + d % 3 - 1, ny = cy + (d / 3) % 3 - 1, nz = cz + d / 9 - 1;
+    const long long nkey = cell_key(nx, ny, nz);
+    const int klo = (int)(nkey & 0xffffffffll), khi = (int)(nkey >> 32);
     const uint32_t hsh = cell_hash(nx, ny, nz, c.T);
-    for (int e = c.bucket_start[hsh]; e < c.bucket_start[hsh + 1]; ++e) {
-      const int j = c.sorted[e];
-      if (c.cellc[3 * j] != nx || c.cellc[3 * j + 1] != ny || c.cellc[3 * j + 2] != nz) continue;
+    const int e1 = c.bucket_start[hsh + 1];
+    for (int e = c.bucket_start[hsh]; e < e1; ++e) {
+      const int4 r = c.srec[e];
+      if (r.z != klo || r.w != khi || r.y == gi) continue;
+      const int j = r.x;
       const double4 uj = c.u[j];
-      if (packed_grain(uj.w) == gi) continue;
       double yx, yy, yz;
       const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y,
                                    c.X[2 * c.n + j], Xz, uj.z, ui.z, yx, yy, yz);
       if (!(d2 < c.cut2)) continue;
-      if (FILL) {
-        const int64_t slot = base + cnt;
-        if (slot < c.capacity) c.cand[slot] = j;
-      }
+      if (cnt < c.scratch_w) row[cnt] = j;
       ++cnt;
     }
   }
-  if (!FILL) {
-    c.cand_count[i] = cnt;
-    return;
+  if (cnt > c.scratch_w) {
+    atomicOr(c.status, ST_CAND_OVERFLOW);
+    cnt = c.scratch_w;
   }
-  // ascending order inside the row
+  c.cand_count[i] = cnt;
+}
+
+// scratch row -> CSR row (ascending; rows past the total capacity are cut and flagged)
+__global__ __launch_bounds__(256) void k_cand_compact(ContactArgs c) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n) return;
+  const int64_t base = c.cand_count[i];  // scanned row pointers
+  const int cnt = (int)(c.cand_count[i + 1] - base);
+  if (cnt == 0) return;
+  const int32_t* row = c.cand_scratch + i * (int64_t)c.scratch_w;
   const int64_t end = base + cnt < c.capacity ? base + cnt : c.capacity;
-  for (int64_t a = base + 1; a < end; ++a) {
-    const int32_t x = c.cand[a];
+  for (int64_t a = base; a < end; ++a) {
+    const int32_t x = row[a - base];
     int64_t q = a - 1;
     while (q >= base && c.cand[q] > x) {
       c.cand[q + 1] = c.cand[q];
@@ -989,19 +1063,20 @@ hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStrea
   hipLaunchKernelGGL(k_skin, dim3(g), dim3(256), 0, s, c, check_skin);
   hipLaunchKernelGGL(k_box_init, dim3(grid_for(6 * (int64_t)c.n_grains, 256)), dim3(256), 0, s, c);
   hipLaunchKernelGGL(k_box, dim3((unsigned)c.n_box_chunks), dim3(256), 0, s, c);
-  const unsigned gg = grid_for(c.n_grains, 64);
-  hipLaunchKernelGGL(k_box_pairs<false>, dim3(gg), dim3(64), 0, s, c, cut);
+  const unsigned gg = (unsigned)c.n_grains;
+  hipLaunchKernelGGL(k_box_pairs<false>, dim3(gg), dim3(kWave), 0, s, c, cut);
   if ((e = scan_i32(c.gpair_count, c.gpair_count, c.n_grains, c.scan_scratch, s)) != hipSuccess) return e;
-  hipLaunchKernelGGL(k_box_pairs<true>, dim3(gg), dim3(64), 0, s, c, cut);
+  hipLaunchKernelGGL(k_box_pairs<true>, dim3(gg), dim3(kWave), 0, s, c, cut);
   hipLaunchKernelGGL(k_active, dim3(g), dim3(256), 0, s, c, cut);
   hipLaunchKernelGGL(k_bin, dim3(g), dim3(256), 0, s, c);
   if ((e = scan_i32(c.bucket_count, c.bucket_start, (int64_t)c.T, c.scan_scratch, s)) != hipSuccess)
     return e;
   hipLaunchKernelGGL(k_scatter, dim3(g), dim3(256), 0, s, c);
-  hipLaunchKernelGGL(k_candidates<false>, dim3(g), dim3(256), 0, s, c);
+  if ((e = launch_fill_i32(c.cand_count, 0, c.n, s)) != hipSuccess) return e;
+  hipLaunchKernelGGL(k_cand_search, dim3(g), dim3(256), 0, s, c);
   if ((e = scan_i32(c.cand_count, c.cand_count, c.n, c.scan_scratch, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_cand_capacity, dim3(1), dim3(64), 0, s, c);
-  hipLaunchKernelGGL(k_candidates<true>, dim3(g), dim3(256), 0, s, c);
+  hipLaunchKernelGGL(k_cand_compact, dim3(g), dim3(256), 0, s, c);
   return hipGetLastError();
 }
 

@@ -424,23 +424,26 @@ def _hard_core_seeds(rng: np.random.Generator, n: int, L: float, dmin: float) ->
 def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1850.0,
                   h: float = 7e-5, dt: float = 7e-9, confinement: float = 10e6,
                   platen_speed: float = 10.0, axial_strain: float = 0.05,
-                  servo_gain: float = 5e-7, gap_factor: float = 1.01, material: Material = SAND,
-                  rebuild_every: int = 20, min_grain_nodes: int = 20) -> Workload:
+                  servo_gain: float = 5e-7, gap_factor: float = 0.0, material: Material = SAND,
+                  rebuild_every: int = 20, min_grain_nodes: int = 20,
+                  contact_damping: float = 0.0) -> Workload:
     """A dense aggregate of polyhedral grains filling a box, confined by six walls.
 
     The grains are the cells of a Voronoi tessellation of hard-core random
-    seeds, meshed on one cubic lattice with node centres at (i + 1/2) h.  A node
-    is kept when its distance to every bisector plane of its cell is at least
-    half the gap g = gap_factor * R_c, so nodes of different grains start at
-    least g apart (just out of contact) and the aggregate needs no settling.
-    The bottom wall (normal +z) is fixed, the top wall moves down at
+    seeds, meshed on one cubic lattice with node centres at (i + 1/2) h, so
+    nodes of different grains are at least h > R_c apart: neighbouring grains
+    touch face to face without pressing, and the aggregate needs no settling.
+    With gap_factor > 0 a node is kept only when its distance to every
+    bisector plane of its cell is at least gap_factor * R_c / 2 (a looser
+    packing).  The walls sit one lattice spacing beyond the outermost nodes:
+    the bottom wall (normal +z) is fixed, the top wall moves down at
     platen_speed, and the four lateral walls are servo-controlled to the
-    confining stress.  Every wall starts gap_factor * R_c from the nearest node.
-    steps covers axial_strain of the initial wall spacing.
+    confining stress.  steps covers axial_strain of the initial wall spacing.
     """
     rng = np.random.default_rng(seed)
     from scipy.spatial import cKDTree
     params = default_params(h, dt, rebuild_every=rebuild_every)
+    params.contact_damping = contact_damping
     Rc = params.contact_radius
     g = gap_factor * Rc
     n_side = int(math.ceil((n_grains * nodes_per_grain) ** (1.0 / 3.0)))
@@ -457,23 +460,17 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
     kq = min(16, n_grains)
     dist, idx = cKDTree(seeds).query(x, k=kq)
     own = idx[:, 0]
-    si = seeds[own]
-    margin = np.full(x.shape[0], np.inf)
-    for q in range(1, kq):
-        sj = seeds[idx[:, q]]
-        dsep = np.linalg.norm(sj - si, axis=1)
-        margin = np.minimum(margin, (dist[:, q] ** 2 - dist[:, 0] ** 2) / (2.0 * dsep))
-    keep = margin >= 0.5 * g
-    # exhaustive check: drop any node of a pair of grains closer than g
-    pos = x[keep]
+    keep = np.ones(x.shape[0], dtype=bool)
+    if g > 0:
+        si = seeds[own]
+        margin = np.full(x.shape[0], np.inf)
+        for q in range(1, kq):
+            sj = seeds[idx[:, q]]
+            dsep = np.linalg.norm(sj - si, axis=1)
+            margin = np.minimum(margin, (dist[:, q] ** 2 - dist[:, 0] ** 2) / (2.0 * dsep))
+        keep = margin >= 0.5 * g
     gid = own[keep]
     lat_k = lat[:, keep]
-    pairs = cKDTree(pos).query_pairs(g * (1.0 - 1e-12), output_type="ndarray")
-    if pairs.size:
-        bad = pairs[gid[pairs[:, 0]] != gid[pairs[:, 1]]][:, 1]
-        ok = np.ones(pos.shape[0], dtype=bool)
-        ok[bad] = False
-        pos, gid, lat_k = pos[ok], gid[ok], lat_k[:, ok]
     blocks = []
     for gr in range(n_grains):
         m = gid == gr
@@ -483,8 +480,8 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
         blocks.append((ijk, origin, h, 0))
     wl = _assemble("rve_aggregate", blocks, [material], params, [], [], 1,
                    info={"seed": seed, "n_grains": len(blocks), "box": L})
-    lo = wl.X.min(axis=1) - g
-    hi = wl.X.max(axis=1) + g
+    lo = wl.X.min(axis=1) - max(g, h)
+    hi = wl.X.max(axis=1) + max(g, h)
     span = hi - lo
     area = [span[1] * span[2], span[0] * span[2], span[0] * span[1]]
     wl.walls = [

@@ -27,7 +27,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pdm_param_count.restype = C.c_int64
     L.pdm_set_params.argtypes = [P, P, C.c_int64]
     L.pdm_get_params.argtypes = [P, P, C.c_int64]
-    L.pdm_set_adam.argtypes = [P, C.c_float, C.c_float, C.c_float]
+    L.pdm_set_adam.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float]
     L.pdm_forward.argtypes = [P, P, C.c_int64, P]
     L.pdm_gradients.argtypes = [P, P, P, C.c_int64, C.POINTER(C.c_float), P]
     L.pdm_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, C.POINTER(C.c_float)]
@@ -87,8 +87,8 @@ class Net:
         self._check(lib().pdm_get_params(self.h, p.ctypes.data_as(P), p.size))
         return p
 
-    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8):
-        self._check(lib().pdm_set_adam(self.h, beta1, beta2, eps))
+    def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
+        self._check(lib().pdm_set_adam(self.h, beta1, beta2, eps, weight_decay))
 
     def forward(self, x):
         x = self._dev(x, self.dims[0])

@@ -23,13 +23,14 @@ FLAG_TABLE_LITERAL, FLAG_ABS_STRETCH, FLAG_NO_GRAPH = 1, 2, 4
 
 FIELDS = dict(displacement=0, velocity=1, accel=2, force_density=3, damage=4, intact_count=5,
               initial_count=6, bond_rowptr=7, bond_col=8, bond_broken=9, contact_rowptr=10,
-              contact_col=11, wall_force=12, wall_offset=13, energy=14, step=15)
+              contact_col=11, wall_force=12, wall_offset=13, energy=14, step=15,
+              wall_impulse=16)
 _FIELD_DTYPE = dict(displacement=np.float64, velocity=np.float64, accel=np.float64,
                     force_density=np.float64, damage=np.float64, intact_count=np.int32,
                     initial_count=np.int32, bond_rowptr=np.int64, bond_col=np.int32,
                     bond_broken=np.uint8, contact_rowptr=np.int64, contact_col=np.int32,
                     wall_force=np.float64, wall_offset=np.float64, energy=np.float64,
-                    step=np.int64)
+                    step=np.int64, wall_impulse=np.float64)
 
 P = C.c_void_p
 
@@ -53,7 +54,7 @@ class pd_params(C.Structure):
                 ("contact_radius", C.c_double), ("contact_horizon", C.c_double),
                 ("skin", C.c_double), ("rebuild_every", C.c_int32),
                 ("candidate_capacity_per_node", C.c_int32), ("dt", C.c_double),
-                ("gravity", C.c_double * 3)]
+                ("gravity", C.c_double * 3), ("contact_damping", C.c_double)]
 
 
 class pd_wall(C.Structure):
@@ -177,7 +178,10 @@ class TorchPlumbing:
                 return None
 
         def _free(ptr, user):
-            self.torch.cuda.caching_allocator_delete(int(ptr))
+            cuda = getattr(self.torch, "cuda", None)
+            if cuda is None:  # interpreter shutdown: the process releases the memory
+                return
+            cuda.caching_allocator_delete(int(ptr))
 
         self.alloc = ALLOC_FN(_alloc)
         self.free = FREE_FN(_free)
@@ -222,6 +226,7 @@ class Sim:
         prm.candidate_capacity_per_node = candidate_capacity_per_node
         prm.dt = p.dt
         prm.gravity[:] = list(p.gravity)
+        prm.contact_damping = getattr(p, "contact_damping", 0.0)
         walls = (pd_wall * max(self.n_walls, 1))(*[make_wall(w) for w in wl.walls])
         h = P()
         if plumbing is not None:
@@ -268,7 +273,7 @@ class Sim:
         out = out[: nb // np.dtype(dt).itemsize]
         if name in ("displacement", "velocity", "accel", "force_density"):
             return out.reshape(3, self.n)
-        if name == "wall_force":
+        if name in ("wall_force", "wall_impulse"):
             return out.reshape(self.n_walls, 3)
         return out
 

@@ -105,6 +105,18 @@ def test_adam_step_matches_oracle_update():
     assert np.abs(p1 - expect).max() <= 1e-6 + 1e-5 * 1e-3
 
 
+def test_adam_weight_decay_matches_oracle_update():
+    net, p, X, Y, torch = setup(batch=128)
+    net.set_adam(weight_decay=0.05)
+    xt, yt = torch.tensor(X, dtype=torch.float32, device="cuda"), torch.tensor(Y, dtype=torch.float32, device="cuda")
+    _, g = net.gradients(xt, yt)
+    net.train_step(xt, yt, lr=1e-3)
+    p1 = net.get_params().astype(np.float64)
+    expect, _, _ = M.adam_step(p, g.astype(np.float64), np.zeros_like(p), np.zeros_like(p), 1, lr=1e-3,
+                               weight_decay=0.05)
+    assert np.abs(p1 - expect).max() <= 1e-6 + 1e-5 * 1e-3
+
+
 def test_training_reduces_loss_on_a_smooth_target():
     import torch
     from paper_2506_05362_amd import mlp

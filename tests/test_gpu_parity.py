@@ -188,9 +188,11 @@ def test_runs_are_bitwise_deterministic():
     assert np.array_equal(out[0][1], out[1][1])
 
 
-def test_checkpoint_resume_is_bitwise():
+@pytest.mark.parametrize("beta", [0.0, 5e21])
+def test_checkpoint_resume_is_bitwise(beta):
     from paper_2506_05362_amd import pd
     wl = I.two_spheres(radius_cells=6, speed=30.0, gap=0.0, rebuild_every=7)
+    wl.params.contact_damping = beta
     a = gpu_sim(wl)
     a.step(25)
     blob = a.get_state()
@@ -255,3 +257,43 @@ def test_graph_replay_matches_direct_launches():
     a.step(20)
     n, ms = a.timing()
     assert n == 20 and ms > 0
+
+
+@pytest.mark.parametrize("beta", [0.0, 2.8e22])
+def test_confined_rve_with_servo_walls(oracle_lib, beta):
+    """Tessellated aggregate between a fixed floor, a moving platen and four
+    servo-controlled lateral walls, with and without normal contact damping:
+    state 1e-9, reactions and impulses 1e-6, and the servo-driven wall offsets
+    1e-9 relative to the box size."""
+    wl = I.rve_aggregate(seed=3, n_grains=12, nodes_per_grain=300, confinement=15e6,
+                         platen_speed=20.0, rebuild_every=10)
+    wl.params.contact_damping = beta
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    box = wl.info["span0"][2]
+    for _ in range(4):
+        sim.step(100)
+        ora.step(100)
+        fo, oo = ora.walls()
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        assert np.abs(sim.get("wall_offset") - oo).max() <= 1e-9 * box
+        assert rel_inf(sim.get("wall_impulse"), ora.wall_impulse()) <= 1e-6
+    assert np.all(np.abs(ora.wall_impulse()[1:]).max(axis=1) > 0)  # platen and servo walls loaded
+    assert_state_close(sim, ora, what="rve")
+
+
+def test_damped_collision_matches_oracle(oracle_lib):
+    """Two spheres colliding with normal contact damping (Sec. 3.4): state 1e-9
+    after 800 steps, and the damped run ends with less kinetic energy."""
+    runs = {}
+    for beta in (0.0, 5e21):
+        wl = I.two_spheres(radius_cells=5, speed=5.0, gap=0.0)
+        wl.params.contact_damping = beta
+        sim = gpu_sim(wl)
+        ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+        for _ in range(4):
+            sim.step(200)
+            ora.step(200)
+        assert_state_close(sim, ora, what=f"beta={beta}")
+        runs[beta] = ora.energy()["kinetic"]
+    assert runs[5e21] < runs[0.0]

@@ -56,3 +56,11 @@ def test_adam_first_step_is_signed_learning_rate():
     g = np.array([3.0, -2e-3, 0.5])
     p, m, v = M.adam_step(np.zeros(3), g, np.zeros(3), np.zeros(3), 1, lr=1e-2)
     assert np.allclose(p, -1e-2 * g / (np.abs(g) + 1e-8), rtol=1e-12)
+
+
+def test_adam_weight_decay_is_decoupled():
+    """With zero gradient the moments stay zero and decoupled decay shrinks every
+    parameter by the factor (1 - lr wd)."""
+    p0 = np.array([2.0, -0.5, 0.0])
+    p, m, v = M.adam_step(p0, np.zeros(3), np.zeros(3), np.zeros(3), 1, lr=1e-2, weight_decay=0.1)
+    assert np.allclose(p, p0 * (1.0 - 1e-3), rtol=1e-15) and not m.any() and not v.any()
