@@ -211,6 +211,35 @@ pd_status pd_timing(pd_ctx* ctx, int64_t* launches, double* total_ms);
 /* Counts: n_nodes, nnz (real bonds), padded slots, candidates, steps. */
 pd_status pd_info(pd_ctx* ctx, int64_t* out5);
 
+/* How pd_step launches the step.  GRAPH, DIRECT and PERSISTENT, with any
+   slices_per_block and xcd_remap, compute bitwise the same node state and wall
+   reactions (same per-node order; wall reactions are reduced per slice and then
+   in slice order).  PER_GRAIN computes bitwise the same node state when no wall
+   is servo-controlled; its reactions agree to rounding (a slice holding nodes
+   of two grains is reduced in two parts).
+     PD_LOOP_GRAPH       all grains in one fused force+contact+walls+Verlet launch
+                         per step; runs of rebuild_every steps (doubled when odd)
+                         replay one captured HIP graph (default);
+     PD_LOOP_DIRECT      the same launches, issued one by one;
+     PD_LOOP_PERSISTENT  one cooperative launch per run of steps between candidate
+                         rebuilds: workgroups stay resident and meet at a grid
+                         barrier between steps;
+     PD_LOOP_PER_GRAIN   unbatched reference: one launch per grain per step.
+   slices_per_block: 64-node slices (wavefronts) per workgroup, 1, 2, 4 or 8
+   (GRAPH and DIRECT; the others use 4).  xcd_remap: 1 maps consecutive
+   workgroups to contiguous slice ranges per XCD, 0 keeps dispatch order.
+   persistent_blocks: workgroups of the persistent launch, 0 = as many as can be
+   resident.  Setting a configuration drops the captured graph. */
+enum { PD_LOOP_GRAPH = 0, PD_LOOP_DIRECT = 1, PD_LOOP_PERSISTENT = 2, PD_LOOP_PER_GRAIN = 3 };
+typedef struct {
+  int32_t loop;
+  int32_t slices_per_block;
+  int32_t xcd_remap;
+  int32_t persistent_blocks;
+} pd_launch;
+pd_status pd_set_launch(pd_ctx* ctx, const pd_launch* launch);
+pd_status pd_get_launch(pd_ctx* ctx, pd_launch* launch);
+
 void pd_destroy(pd_ctx* ctx);
 const char* pd_last_error(const pd_ctx* ctx);
 const char* pd_status_string(pd_status status);

@@ -89,6 +89,12 @@ struct pd_ctx {
   int timing = 0;
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
+  // launch configuration (pd_set_launch) and its per-grain tables
+  pd_launch launch{PD_LOOP_GRAPH, kSlicesPerBlock, 1, 0};
+  std::vector<int64_t> pg_slice_lo, pg_slice_hi, pg_part_base;
+  int64_t pg_cols = 0;  // wall-partial columns of the per-grain launches (shared slices twice)
+  int64_t partial_cols = 0;  // columns allocated in wall_partial
+  uint32_t* barrier = nullptr;  // [2]: arrival count, generation
   // captured step loop of graph_len steps
   int use_graph = 1;
   int64_t graph_len = 0;
@@ -202,6 +208,13 @@ StepArgs step_args(pd_ctx* c) {
   A.vh_cur = c->vh[c->cur];
   A.vh_next = c->vh[c->cur ^ 1];
   A.beta = c->beta;
+  A.slice_base = 0;
+  A.slice_end = c->nslices;
+  A.node_lo = 0;
+  A.node_hi = c->n;
+  A.partial_base = 0;
+  A.partial_stride = c->nslices;
+  A.xcd_remap = c->launch.xcd_remap;
   A.fixed = c->fixed;
   A.grains = c->grains;
   A.stencil = c->stencil;
@@ -281,9 +294,54 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
   if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
-  HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+  if (c->launch.loop == PD_LOOP_PER_GRAIN) {
+    // one launch per grain over the slices that hold its nodes; a slice shared
+    // by two grains is visited by both launches, each lane working for its own
+    A.partial_stride = c->pg_cols;
+    for (int32_t g = 0; g < c->n_grains; ++g) {
+      StepArgs Ag = A;
+      Ag.slice_base = c->pg_slice_lo[(size_t)g];
+      Ag.slice_end = c->pg_slice_hi[(size_t)g];
+      Ag.node_lo = c->grain_begin[(size_t)g];
+      Ag.node_hi = c->grain_begin[(size_t)g + 1];
+      Ag.partial_base = c->pg_part_base[(size_t)g];
+      Ag.xcd_remap = 0;
+      HIPCHK(c, launch_step_spb(Ag, kSlicesPerBlock, c->stream));
+    }
+  } else if (c->launch.slices_per_block != kSlicesPerBlock) {
+    HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream));
+  } else {
+    HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+  }
   if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
   HIPCHK(c, launch_wall_finalize(A, c->stream));
+  return PD_OK;
+}
+
+// PD_LOOP_PERSISTENT: steps c->step+1 .. c->step+k in one launch, k chosen so
+// that no candidate rebuild falls inside (a rebuild due at the first step runs
+// before the launch).
+pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t ev0, hipEvent_t ev1) {
+  const int64_t s = c->step + 1;
+  const int64_t R = c->rebuild_every;
+  const int64_t k = std::min<int64_t>(left, (s / R + 1) * R - s);
+  if (s % R == 0) {
+    ContactArgs C = contact_args(c, c->cur ^ 1);
+    HIPCHK(c, launch_contact_rebuild(C, c->n_grains > 1 ? 1 : 0, c->stream));
+  }
+  if (!c->barrier) TRY(alloc_n(c, &c->barrier, 2, "grid barrier"));
+  HIPCHK(c, launch_fill_i32(reinterpret_cast<int32_t*>(c->barrier), 0, 2, c->stream));
+  c->cur ^= 1;
+  StepArgs A = step_args(c);
+  const int32_t maxb = persistent_max_blocks(A);
+  if (maxb <= 0) return fail(c, PD_ERR_HIP, "no resident workgroups for the persistent step kernel");
+  const int32_t nb = c->launch.persistent_blocks > 0 ? std::min(c->launch.persistent_blocks, maxb) : maxb;
+  BarrierArgs B{c->barrier, c->barrier + 1, 1u << 24};
+  if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
+  HIPCHK(c, launch_step_persistent(A, k, nb, B, c->stream));
+  if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
+  if ((k - 1) & 1) c->cur ^= 1;  // the kernel flipped the buffers k - 1 more times
+  *done = k;
   return PD_OK;
 }
 
@@ -305,6 +363,20 @@ pd_status capture_graph(pd_ctx* c) {
   if (ec != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorName(ec));
   c->graph = g;
   HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  return PD_OK;
+}
+
+pd_status next_events(pd_ctx* c, hipEvent_t* e0, hipEvent_t* e1) {
+  *e0 = *e1 = nullptr;
+  if (!c->timing) return PD_OK;
+  while (c->ev_pool.size() < c->ev_used + 2) {
+    hipEvent_t e;
+    HIPCHK(c, hipEventCreate(&e));
+    c->ev_pool.push_back(e);
+  }
+  *e0 = c->ev_pool[c->ev_used];
+  *e1 = c->ev_pool[c->ev_used + 1];
+  c->ev_used += 2;
   return PD_OK;
 }
 
@@ -340,6 +412,7 @@ pd_status report_status(pd_ctx* c) {
   if (st & ST_PENETRATION) why += " node at or beyond -R_c behind a wall;";
   if (st & ST_SKIN) why += " displacement since the last candidate rebuild exceeded skin/2;";
   if (st & ST_CAND_OVERFLOW) why += " contact candidate capacity exceeded;";
+  if (st & ST_BARRIER) why += " a grid barrier of the persistent step loop timed out;";
   return fail(c, PD_ERR_UNSTABLE, "instability flagged:%s", why.c_str());
 }
 
@@ -454,6 +527,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->beta = P.contact_damping;
   c->rebuild_every = P.rebuild_every;
   c->use_graph = (P.flags & PD_FLAG_NO_GRAPH) ? 0 : 1;
+  if (!c->use_graph) c->launch.loop = PD_LOOP_DIRECT;
   c->graph_len = (P.rebuild_every % 2 == 0) ? P.rebuild_every : 2 * (int64_t)P.rebuild_every;
   c->cap_per_node = P.candidate_capacity_per_node > 0 ? P.candidate_capacity_per_node : 16;
   for (int q = 0; q < 3; ++q) c->g[q] = P.gravity[q];
@@ -794,8 +868,21 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
     HIPCHK(c, hipMemcpyAsync(c->box_chunks, ch.data(), sizeof(int64_t) * ch.size(), hipMemcpyHostToDevice, s));
     HIPCHK(c, hipStreamSynchronize(s));
   }
-  const int32_t nblocks = step_grid_blocks(c->nslices);
-  TRY(alloc_n(c, &c->wall_partial, (int64_t)std::max(nblocks, 1) * 3 * std::max(c->n_walls, 1), "wall partials"));
+  // per-grain launch geometry (PD_LOOP_PER_GRAIN) and wall partial columns for
+  // the largest grid of any mode (one slice per workgroup, or the per-grain sum)
+  c->pg_slice_lo.assign((size_t)G, 0);
+  c->pg_slice_hi.assign((size_t)G, 0);
+  c->pg_part_base.assign((size_t)G, 0);
+  c->pg_cols = 0;
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t b = c->grain_begin[(size_t)g], e = c->grain_begin[(size_t)g + 1];
+    c->pg_slice_lo[(size_t)g] = b / kWave;
+    c->pg_slice_hi[(size_t)g] = e > b ? (e - 1) / kWave + 1 : b / kWave;
+    c->pg_part_base[(size_t)g] = c->pg_cols;
+    c->pg_cols += c->pg_slice_hi[(size_t)g] - c->pg_slice_lo[(size_t)g];
+  }
+  c->partial_cols = std::max<int64_t>(std::max<int64_t>(c->nslices, c->pg_cols), 1);
+  TRY(alloc_n(c, &c->wall_partial, c->partial_cols * 3 * std::max(c->n_walls, 1), "wall partials"));
 
   // first candidate list at u0, then F^0 and a^0 (velocity untouched)
   ContactArgs C = contact_args(c, c->cur);
@@ -814,9 +901,18 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   if (n_steps < 0) return fail(c, PD_ERR_INVALID, "n_steps < 0");
   int64_t left = n_steps;
+  while (left > 0 && c->launch.loop == PD_LOOP_PERSISTENT) {
+    hipEvent_t e0, e1;
+    TRY(next_events(c, &e0, &e1));
+    int64_t k = 0;
+    TRY(enqueue_persistent(c, left, &k, e0, e1));
+    c->step += k;
+    left -= k;
+  }
   while (left > 0) {
     // timing brackets each step kernel with events, so it launches directly
-    const bool aligned = c->use_graph && !c->timing && c->step % c->graph_len == 0 && left >= c->graph_len;
+    const bool aligned = c->use_graph && c->launch.loop == PD_LOOP_GRAPH && !c->timing &&
+                         c->step % c->graph_len == 0 && left >= c->graph_len;
     if (aligned) {
       TRY(capture_graph(c));
       HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
@@ -829,6 +925,34 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
     }
   }
   return report_status(c);
+}
+
+pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
+  if (!c || !l) return PD_ERR_INVALID;
+  if (l->loop < PD_LOOP_GRAPH || l->loop > PD_LOOP_PER_GRAIN)
+    return fail(c, PD_ERR_INVALID, "unknown step loop %d", l->loop);
+  const int spb = l->slices_per_block;
+  if (!(spb == 1 || spb == 2 || spb == 4 || spb == 8))
+    return fail(c, PD_ERR_INVALID, "slices_per_block must be 1, 2, 4 or 8");
+  if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(c, PD_ERR_INVALID, "xcd_remap must be 0 or 1");
+  if (l->persistent_blocks < 0) return fail(c, PD_ERR_INVALID, "persistent_blocks must be >= 0");
+  if (c->graph_exec) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+    c->graph_exec = nullptr;
+  }
+  if (c->graph) {
+    HIPCHK(c, hipGraphDestroy(c->graph));
+    c->graph = nullptr;
+  }
+  c->launch = *l;
+  return PD_OK;
+}
+
+pd_status pd_get_launch(pd_ctx* c, pd_launch* l) {
+  if (!c || !l) return PD_ERR_INVALID;
+  *l = c->launch;
+  return PD_OK;
 }
 
 pd_status pd_set_timing(pd_ctx* c, int32_t enable) {

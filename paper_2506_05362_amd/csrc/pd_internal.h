@@ -79,6 +79,7 @@ enum : uint32_t {
   ST_PENETRATION = 2u,
   ST_SKIN = 4u,
   ST_CAND_OVERFLOW = 8u,
+  ST_BARRIER = 16u,  // a grid-barrier wait of the persistent kernel gave up
 };
 
 enum ForceMode { MODE_FIRST = 0, MODE_STEP = 1, MODE_FORCE_ONLY = 2 };
@@ -109,7 +110,7 @@ struct StepArgs {
   const double* X;      // SoA, contact path only
   const double* Kn;     // [n_mat * n_mat]
   WallDev* walls;
-  double* wall_partial;  // [n_walls][3][nblocks] (component-major)
+  double* wall_partial;  // [n_walls][3][partial_stride]: one column per slice (component-major)
   int64_t* step;         // device step counter
   int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;
@@ -122,6 +123,20 @@ struct StepArgs {
   double g[3];
   double beta;           // normal damping coefficient, 0 = off
   int32_t abs_stretch;
+  // launch geometry: the slices [slice_base, slice_end) of this launch, nodes
+  // outside [node_lo, node_hi) idle (per-grain launches), and the column of
+  // wall_partial that slice s writes (partial_base + s - slice_base of partial_stride)
+  int64_t slice_base, slice_end;
+  int64_t node_lo, node_hi;
+  int64_t partial_base, partial_stride;
+  int32_t xcd_remap;     // 1: workgroup -> XCD-contiguous slice ranges
+};
+
+// grid barrier state of the persistent step kernel (zeroed before each launch)
+struct BarrierArgs {
+  uint32_t* count;
+  uint32_t* gen;
+  uint32_t spin_limit;  // iterations of a wait before it gives up and flags ST_BARRIER
 };
 
 struct BuildArgs {
@@ -181,6 +196,16 @@ hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s);
 hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s);
 hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s);
+// MODE_STEP with slices_per_block in {1, 2, 4, 8}
+hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s);
+// nsteps steps with no rebuild in between, one cooperative launch of nblocks
+// workgroups (4 slices each) that loop over the slices with a grid barrier
+// between steps
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks,
+                                  const BarrierArgs& b, hipStream_t s);
+// workgroups of the persistent kernel that fit on the device at once
+int32_t persistent_max_blocks(const StepArgs& a);
+int32_t step_blocks_spb(int64_t nslices, int slices_per_block);
 // wall reactions, next wall offsets and the step counter after a step launch
 hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s);
 

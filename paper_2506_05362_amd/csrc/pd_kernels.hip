@@ -252,22 +252,16 @@ __device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) {
   return fma(p, x, 0.5);
 }
 
-template <int MODE, bool ABS>
-__global__ __launch_bounds__(kBlock) __attribute__((amdgpu_waves_per_eu(PD_STEP_WAVES_PER_EU)))
-void k_step(StepArgs A) {
-  extern __shared__ StencilC s_st[];
-  __shared__ double s_wall[kSlicesPerBlock][kMaxWalls * 3];
+// The fused step of one workgroup: SPB slices (one wavefront each) starting at
+// slice slice_base + SPB * blk.  s_st holds the stencil tables in LDS.
+template <int MODE, bool ABS, int SPB>
+__device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_st, int64_t blk) {
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int rows = A.n_classes * (A.n_stencil + 1);
-  for (int k = tid; k < rows; k += kBlock) s_st[k] = A.stencil[k];
-  __syncthreads();
-
-  const int64_t blk = xcd_remap(blockIdx.x, gridDim.x);
-  const int64_t slice = blk * kSlicesPerBlock + wid;
-  const bool slice_ok = slice < A.nslices;
+  const int64_t slice = A.slice_base + blk * SPB + wid;
+  const bool slice_ok = slice < A.slice_end;
   const int64_t i = slice * kWave + lane;
-  const bool valid = slice_ok && i < A.n;
+  const bool valid = slice_ok && i >= A.node_lo && i < A.node_hi;
 
   double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
   if (valid) ui = A.ucur[i];
@@ -344,7 +338,7 @@ void k_step(StepArgs A) {
       fx = fma(coef, yx, fx);
       fy = fma(coef, yy, fy);
       fz = fma(coef, yz, fz);
-      if (MODE != MODE_FORCE_ONLY && over) {
+      if (MODE != MODE_FORCE_ONLY && over && valid) {
         cp[(k + u) * kWave] = mine;  // the bond stays broken from now on
         ++nbroke;
       }
@@ -435,10 +429,13 @@ void k_step(StepArgs A) {
         r1 = wave_sum(vm * Wd->n[1]);
         r2 = wave_sum(vm * Wd->n[2]);
       }
-      if (lane == 0) {
-        s_wall[wid][3 * w] = r0;
-        s_wall[wid][3 * w + 1] = r1;
-        s_wall[wid][3 * w + 2] = r2;
+      // one partial per slice (wavefront), component-major: the finalize sums
+      // them in slice order, whatever the workgroup size or launch split
+      if (lane == 0 && slice_ok) {
+        const int64_t col = A.partial_base + (slice - A.slice_base);
+        A.wall_partial[(int64_t)(3 * w) * A.partial_stride + col] = r0;
+        A.wall_partial[(int64_t)(3 * w + 1) * A.partial_stride + col] = r1;
+        A.wall_partial[(int64_t)(3 * w + 2) * A.partial_stride + col] = r2;
       }
     }
   }
@@ -487,68 +484,83 @@ void k_step(StepArgs A) {
     }
   }
 
-  if (MODE != MODE_FORCE_ONLY && A.n_walls > 0) {
-    // per-workgroup wall partials; k_wall_finalize sums them in a fixed order
-    // (a kernel boundary is the cheap way to make them visible across XCDs)
-    __syncthreads();
-    if (tid < 3 * A.n_walls) {
-      double s = 0.0;
-      for (int q = 0; q < kSlicesPerBlock; ++q) s += s_wall[q][tid];
-      A.wall_partial[(int64_t)tid * gridDim.x + blk] = s;  // component-major
-    }
-  }
 }
 
-// reaction forces (fixed-order sum of block partials) and the wall positions
+__device__ __forceinline__ void stage_stencil(const StepArgs& A, StencilC* s_st) {
+  const int rows = A.n_classes * (A.n_stencil + 1);
+  for (int k = threadIdx.x; k < rows; k += blockDim.x) s_st[k] = A.stencil[k];
+  __syncthreads();
+}
+
+template <int MODE, bool ABS, int SPB>
+__global__ __launch_bounds__(SPB * kWave) __attribute__((amdgpu_waves_per_eu(PD_STEP_WAVES_PER_EU)))
+void k_step(StepArgs A) {
+  extern __shared__ StencilC s_st[];
+  stage_stencil(A, s_st);
+  const int64_t blk = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  step_body<MODE, ABS, SPB>(A, s_st, blk);
+}
+
+// reaction forces (fixed-order sum of slice partials) and the wall positions
 // of the next step: prescribed velocity or servo on the measured stress.
-// One workgroup of 1024 threads; thread t sums blocks t, t + 1024, ... of
-// every component, then a fixed-order reduction over lanes and waves.
-__global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblocks) {
-  __shared__ double red[kMaxWalls * 3][1024 / kWave];
+// The sum order is that of 1024 threads whatever NT is: virtual thread v sums
+// columns v, v + 1024, ... of a component, each virtual wave of 64 is reduced
+// across lanes, then the 16 wave sums in order; so every step-loop mode gives
+// bitwise the same reactions.  Components are taken CB at a time with 4 blocks
+// of loads in flight per virtual thread.
+template <int NT>
+__device__ __forceinline__ void finalize_body(const StepArgs& A, int64_t nblocks,
+                                              double (*red)[1024 / kWave], double* tot,
+                                              int64_t* s_step) {
+  constexpr int VT = 1024 / NT;
+  constexpr int CB = NT >= 1024 ? 8 : 2;  // components per batch (register budget)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nc = 3 * A.n_walls;
-  double acc[kMaxWalls * 3];
+  for (int c0 = 0; c0 < nc; c0 += CB) {
+    double acc[CB][VT];
 #pragma unroll
-  for (int c = 0; c < kMaxWalls * 3; ++c) acc[c] = 0.0;
-  // component-major partials: lanes read consecutive blocks (coalesced); the
-  // loads of 8 components x 4 blocks are issued together, then summed in block order
+    for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
-  for (int c0 = 0; c0 < kMaxWalls * 3; c0 += 8) {
-    if (c0 >= nc) break;
-    for (int b0 = tid; b0 < nblocks; b0 += 4 * 1024) {
-      double v[8][4];
+      for (int k = 0; k < VT; ++k) acc[cc][k] = 0.0;
+    for (int64_t b0 = 0; b0 < nblocks; b0 += 4 * 1024) {
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc)
+      for (int k = 0; k < VT; ++k) {
+        const int64_t v0 = b0 + tid + (int64_t)NT * k;  // virtual thread tid + NT k
+        double v[CB][4];
 #pragma unroll
-        for (int k = 0; k < 4; ++k) {
-          const int c = c0 + cc, b = b0 + 1024 * k;
-          v[cc][k] = (c < nc && b < nblocks) ? A.wall_partial[(int64_t)c * nblocks + b] : 0.0;
-        }
+        for (int cc = 0; cc < CB; ++cc)
 #pragma unroll
-      for (int cc = 0; cc < 8; ++cc)
+          for (int r = 0; r < 4; ++r) {
+            const int c = c0 + cc;
+            const int64_t bb = v0 + 1024 * r;
+            v[cc][r] = (c < nc && bb < nblocks) ? A.wall_partial[(int64_t)c * nblocks + bb] : 0.0;
+          }
 #pragma unroll
-        for (int k = 0; k < 4; ++k) acc[c0 + cc] += v[cc][k];
+        for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+          for (int r = 0; r < 4; ++r) acc[cc][k] += v[cc][r];
+      }
     }
-  }
 #pragma unroll
-  for (int c = 0; c < kMaxWalls * 3; ++c) {
-    if (c < nc) {
-      const double t = wave_sum(acc[c]);
-      if (lane == 0) red[c][wv] = t;
+    for (int cc = 0; cc < CB; ++cc) {
+      if (c0 + cc < nc) {
+#pragma unroll
+        for (int k = 0; k < VT; ++k) {
+          const double t = wave_sum(acc[cc][k]);
+          if (lane == 0) red[c0 + cc][wv + (NT / kWave) * k] = t;
+        }
+      }
     }
   }
   __syncthreads();
-  // one thread per component sums the 16 wave partials (fixed order)
-  __shared__ double tot[kMaxWalls * 3];
-  __shared__ int64_t s_step;
   if (tid < nc) {
     double t = 0.0;
     for (int k = 0; k < 1024 / kWave; ++k) t += red[tid][k];
     tot[tid] = t;
   }
-  if (tid == 0) s_step = *A.step + A.advance;  // the step this evaluation belonged to
+  if (tid == 0) *s_step = *A.step + A.advance;  // the step this evaluation belonged to
   __syncthreads();
-  const int64_t s = s_step;
+  const int64_t s = *s_step;
   if (tid == 0) *A.step = s;
   // one thread per wall: its loads are independent of the other walls'
   if (tid < A.n_walls) {
@@ -568,6 +580,71 @@ __global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int32_t nblo
       W.off = W.off + A.dt * W.rate;
     }
     A.walls[tid] = W;
+  }
+}
+
+__global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int64_t nblocks) {
+  __shared__ double red[kMaxWalls * 3][1024 / kWave];
+  __shared__ double tot[kMaxWalls * 3];
+  __shared__ int64_t s_step;
+  finalize_body<1024>(A, nblocks, red, tot, &s_step);
+}
+
+// ---------------------------------------------------------------------------
+// persistent step loop: nsteps steps (no candidate rebuild among them) in one
+// cooperative launch.  Workgroups walk the slice blocks of each step, meet at
+// a grid barrier, workgroup 0 reduces the wall reactions, and all meet again
+// before the next step reads the drifted positions.  Every wait has a spin
+// limit, so each wave exits even if a barrier were never completed.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void grid_barrier(const BarrierArgs& B, uint32_t nblocks, uint32_t* status) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __threadfence();  // release this workgroup's writes to every XCD
+    const uint32_t g = __hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+    if (atomicAdd(B.count, 1u) == nblocks - 1u) {
+      atomicExch(B.count, 0u);
+      __threadfence();
+      atomicAdd(B.gen, 1u);
+    } else {
+      uint32_t spins = 0;
+      while (__hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(1);
+        if (++spins > B.spin_limit) {
+          atomicOr(status, ST_BARRIER);
+          break;
+        }
+      }
+    }
+    __threadfence();  // acquire the other workgroups' writes
+  }
+  __syncthreads();
+}
+
+template <bool ABS>
+__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(4)))
+void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs B) {
+  extern __shared__ StencilC s_st[];
+  __shared__ double red[kMaxWalls * 3][1024 / kWave];
+  __shared__ double tot[kMaxWalls * 3];
+  __shared__ int64_t s_step;
+  stage_stencil(A, s_st);
+  for (int64_t k = 0; k < nsteps; ++k) {
+    for (int64_t vb = blockIdx.x; vb < nvblocks; vb += gridDim.x) {
+      const int64_t blk = A.xcd_remap ? xcd_remap(vb, nvblocks) : vb;
+      step_body<MODE_STEP, ABS, 4>(A, s_st, blk);
+    }
+    grid_barrier(B, gridDim.x, A.status);
+    if (blockIdx.x == 0) finalize_body<4 * kWave>(A, A.partial_stride, red, tot, &s_step);
+    grid_barrier(B, gridDim.x, A.status);
+    // the drift just written is the next step's position; mid-step velocities likewise
+    const double4* uc = A.ucur;
+    A.ucur = A.unext;
+    A.unext = const_cast<double4*>(uc);
+    const double4* vc = A.vh_cur;
+    A.vh_cur = A.vh_next;
+    A.vh_next = const_cast<double4*>(vc);
   }
 }
 
@@ -1027,29 +1104,71 @@ hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s) {
   return hipGetLastError();
 }
 
-int32_t step_grid_blocks(int64_t nslices) { return (int32_t)grid_for(nslices, kSlicesPerBlock); }
+int32_t step_blocks_spb(int64_t nslices, int slices_per_block) {
+  return (int32_t)grid_for(nslices, slices_per_block);
+}
+int32_t step_grid_blocks(int64_t nslices) { return step_blocks_spb(nslices, kSlicesPerBlock); }
 
 hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(1024), 0, s, a, step_grid_blocks(a.nslices));
+  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(1024), 0, s, a, (int64_t)a.partial_stride);
   return hipGetLastError();
 }
 
+static size_t step_lds(const StepArgs& a) {
+  return sizeof(StencilC) * (size_t)(a.n_stencil + 1) * (size_t)a.n_classes;
+}
+
+template <int MODE, int SPB>
+static void launch_step_t(const StepArgs& a, hipStream_t s) {
+  const int32_t nb = step_blocks_spb(a.slice_end - a.slice_base, SPB);
+  if (nb == 0) return;
+  if (a.abs_stretch) hipLaunchKernelGGL((k_step<MODE, true, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
+  else hipLaunchKernelGGL((k_step<MODE, false, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
+}
+
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
-  const int32_t nb = step_grid_blocks(a.nslices);
-  if (nb == 0) return hipSuccess;
-  const size_t lds = sizeof(StencilC) * (size_t)(a.n_stencil + 1) * (size_t)a.n_classes;
-  const bool abs_s = a.abs_stretch != 0;
-  if (mode == MODE_FIRST) {
-    if (abs_s) hipLaunchKernelGGL((k_step<MODE_FIRST, true>), dim3(nb), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_step<MODE_FIRST, false>), dim3(nb), dim3(kBlock), lds, s, a);
-  } else if (mode == MODE_STEP) {
-    if (abs_s) hipLaunchKernelGGL((k_step<MODE_STEP, true>), dim3(nb), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_step<MODE_STEP, false>), dim3(nb), dim3(kBlock), lds, s, a);
-  } else {
-    if (abs_s) hipLaunchKernelGGL((k_step<MODE_FORCE_ONLY, true>), dim3(nb), dim3(kBlock), lds, s, a);
-    else hipLaunchKernelGGL((k_step<MODE_FORCE_ONLY, false>), dim3(nb), dim3(kBlock), lds, s, a);
+  if (mode == MODE_FIRST) launch_step_t<MODE_FIRST, kSlicesPerBlock>(a, s);
+  else if (mode == MODE_STEP) launch_step_t<MODE_STEP, kSlicesPerBlock>(a, s);
+  else launch_step_t<MODE_FORCE_ONLY, kSlicesPerBlock>(a, s);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s) {
+  switch (slices_per_block) {
+    case 1: launch_step_t<MODE_STEP, 1>(a, s); break;
+    case 2: launch_step_t<MODE_STEP, 2>(a, s); break;
+    case 4: launch_step_t<MODE_STEP, 4>(a, s); break;
+    case 8: launch_step_t<MODE_STEP, 8>(a, s); break;
+    default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
+}
+
+int32_t persistent_max_blocks(const StepArgs& a) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  const void* fn = a.abs_stretch ? reinterpret_cast<const void*>(&k_step_persistent<true>)
+                                 : reinterpret_cast<const void*>(&k_step_persistent<false>);
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, fn, 4 * kWave, step_lds(a)) != hipSuccess)
+    return 0;
+  return per_cu * cus;
+}
+
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks,
+                                  const BarrierArgs& b, hipStream_t s) {
+  if (nsteps <= 0) return hipSuccess;
+  int64_t nv = step_blocks_spb(a.slice_end - a.slice_base, 4);
+  if (nv == 0) return hipSuccess;
+  StepArgs aa = a;
+  BarrierArgs bb = b;
+  void* args[] = {&aa, &nsteps, &nv, &bb};
+  const void* fn = a.abs_stretch ? reinterpret_cast<const void*>(&k_step_persistent<true>)
+                                 : reinterpret_cast<const void*>(&k_step_persistent<false>);
+  // a cooperative launch fails rather than start more workgroups than can be
+  // resident at once, which the grid barrier relies on
+  return hipLaunchCooperativeKernel(fn, dim3((unsigned)nblocks), dim3(4 * kWave), args,
+                                    (unsigned)step_lds(a), s);
 }
 
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s) {

@@ -274,12 +274,14 @@ def notched_plate(nx: int = 200, ny: int = 200, nz: int = 18, h: float = 5e-4,
 # level-set grains (spheres perturbed by real spherical harmonics, l = 2..6)
 # ----------------------------------------------------------------------------
 
-def _real_sph_harm(l: int, m: int, theta: np.ndarray, phi: np.ndarray) -> np.ndarray:
-    """Real spherical harmonic, theta = polar angle, phi = azimuth."""
+def _real_sph_harm(l: int, m: int, theta: np.ndarray, phi: np.ndarray, p=None) -> np.ndarray:
+    """Real spherical harmonic, theta = polar angle, phi = azimuth.  p may carry
+    the associated Legendre values P_l^|m|(cos theta) already evaluated."""
     from scipy.special import lpmv
     am = abs(m)
     norm = math.sqrt((2 * l + 1) / (4 * math.pi) * math.factorial(l - am) / math.factorial(l + am))
-    p = lpmv(am, l, np.cos(theta))
+    if p is None:
+        p = lpmv(am, l, np.cos(theta))
     if m > 0:
         return math.sqrt(2.0) * norm * p * np.cos(m * phi)
     if m < 0:
@@ -307,9 +309,14 @@ class LevelSetShape:
         self.smax = float(np.max(np.abs(self._S(T, P)))) or 1.0
 
     def _S(self, theta, phi):
+        from scipy.special import lpmv
+        c = np.cos(theta)
+        leg = {}
         s = np.zeros_like(theta)
         for l, m, a in self.coef:
-            s = s + a * _real_sph_harm(l, m, theta, phi)
+            if (l, abs(m)) not in leg:
+                leg[(l, abs(m))] = lpmv(abs(m), l, c)
+            s = s + a * _real_sph_harm(l, m, theta, phi, leg[(l, abs(m))])
         return s
 
     def radius_at(self, d: np.ndarray) -> np.ndarray:

@@ -63,6 +63,16 @@ class pd_wall(C.Structure):
                 ("target_stress", C.c_double), ("servo_gain", C.c_double), ("area", C.c_double)]
 
 
+class pd_launch(C.Structure):
+    _fields_ = [("loop", C.c_int32), ("slices_per_block", C.c_int32), ("xcd_remap", C.c_int32),
+                ("persistent_blocks", C.c_int32)]
+
+
+LOOP_GRAPH, LOOP_DIRECT, LOOP_PERSISTENT, LOOP_PER_GRAIN = 0, 1, 2, 3
+LOOP_NAMES = {LOOP_GRAPH: "graph", LOOP_DIRECT: "direct", LOOP_PERSISTENT: "persistent",
+              LOOP_PER_GRAIN: "per_grain"}
+
+
 class pd_cut(C.Structure):
     _fields_ = [("kind", C.c_int32), ("grain", C.c_int32), ("plane", C.c_int64 * 4),
                 ("lo", C.c_int64 * 3), ("hi", C.c_int64 * 3), ("center", C.c_int64 * 3),
@@ -74,7 +84,7 @@ FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
 
 EXPORTS = ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get", "pd_set_wall",
            "pd_get_state", "pd_set_state", "pd_info", "pd_set_timing", "pd_timing", "pd_destroy",
-           "pd_last_error", "pd_status_string"]
+           "pd_last_error", "pd_status_string", "pd_set_launch", "pd_get_launch"]
 
 
 def load_library(path: str = _LIB_PATH) -> C.CDLL:
@@ -97,6 +107,8 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_info.argtypes = [P, P]
     L.pd_set_timing.argtypes = [P, C.c_int32]
     L.pd_timing.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
+    L.pd_set_launch.argtypes = [P, C.POINTER(pd_launch)]
+    L.pd_get_launch.argtypes = [P, C.POINTER(pd_launch)]
     L.pd_destroy.argtypes = [P]
     L.pd_last_error.argtypes = [P]
     L.pd_last_error.restype = C.c_char_p
@@ -104,7 +116,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_status_string.restype = C.c_char_p
     for name in ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get",
                  "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_set_timing",
-                 "pd_timing"]:
+                 "pd_timing", "pd_set_launch", "pd_get_launch"]:
         getattr(L, name).restype = C.c_int32
     return L
 
@@ -285,6 +297,17 @@ class Sim:
         self._check(lib().pd_info(self.h, _ptr(o)))
         return dict(n_nodes=int(o[0]), nnz=int(o[1]), padded=int(o[2]), candidates=int(o[3]),
                     step=int(o[4]))
+
+    def set_launch(self, loop: int = LOOP_GRAPH, slices_per_block: int = 4, xcd_remap: int = 1,
+                   persistent_blocks: int = 0):
+        cfg = pd_launch(int(loop), int(slices_per_block), int(xcd_remap), int(persistent_blocks))
+        self._check(lib().pd_set_launch(self.h, C.byref(cfg)))
+
+    def get_launch(self) -> dict:
+        cfg = pd_launch()
+        self._check(lib().pd_get_launch(self.h, C.byref(cfg)))
+        return dict(loop=cfg.loop, slices_per_block=cfg.slices_per_block, xcd_remap=cfg.xcd_remap,
+                    persistent_blocks=cfg.persistent_blocks)
 
     def set_timing(self, enable: bool):
         self._check(lib().pd_set_timing(self.h, 1 if enable else 0))

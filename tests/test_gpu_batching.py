@@ -1,0 +1,119 @@
+"""Batched step loops: the captured graph, direct launches and the persistent
+cooperative kernel, with 1-8 slices per workgroup and with and without the
+XCD-aware order, compute bitwise the same node state and wall reactions; one
+launch per grain gives bitwise the same node state without servo walls and the
+same reactions to rounding.  The launch autotuner restores the state it
+measured on and caches its choice."""
+import json
+
+import numpy as np
+import pytest
+
+from paper_2506_05362_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+FIELDS = ["displacement", "velocity", "accel", "bond_broken", "intact_count", "wall_force",
+          "wall_offset", "wall_impulse", "step"]
+
+
+def modes():
+    from paper_2506_05362_amd import pd
+    return [
+        dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=1),
+        dict(loop=pd.LOOP_DIRECT, slices_per_block=1, xcd_remap=0),
+        dict(loop=pd.LOOP_GRAPH, slices_per_block=2, xcd_remap=1),
+        dict(loop=pd.LOOP_GRAPH, slices_per_block=8, xcd_remap=0),
+        dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=1),
+        dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=0, persistent_blocks=7),
+        dict(loop=pd.LOOP_PER_GRAIN, slices_per_block=4, xcd_remap=1),
+    ]
+
+
+def cases():
+    agg = I.grain_aggregate(n_grains=6, grid=(3, 2, 1), n_min=800, n_max=3000, seed=2,
+                            platen_speed=5.0, rebuild_every=10)
+    rve = I.rve_aggregate(seed=3, n_grains=12, nodes_per_grain=300, confinement=15e6,
+                          platen_speed=20.0, rebuild_every=10, contact_damping=2.8e22)
+    return {"aggregate": agg, "rve_damped_servo": rve}
+
+
+def run(wl, cfg, steps):
+    from paper_2506_05362_amd import pd
+    sim = pd.Sim(wl)
+    sim.set_launch(**cfg)
+    assert sim.get_launch()["loop"] == cfg["loop"]
+    sim.step(steps)
+    out = {f: sim.get(f) for f in FIELDS}
+    sim.close()
+    return out
+
+
+@pytest.mark.parametrize("case", ["aggregate", "rve_damped_servo"])
+def test_step_loop_modes_are_bitwise_identical(case):
+    wl = cases()[case]
+    steps = 65  # several rebuild periods and a ragged last run
+    print(f"[{case}] {wl.n_nodes} nodes, {wl.n_grains} grains", flush=True)
+    ms = modes()
+    ref = run(wl, ms[0], steps)
+    assert ref["step"][0] == steps
+    servo = any(w.mode == I.WALL_SERVO for w in wl.walls)
+    for cfg in ms[1:]:
+        got = run(wl, cfg, steps)
+        for f in FIELDS:
+            if cfg["loop"] == 3 and (f in ("wall_force", "wall_impulse") or servo):
+                scale = max(np.abs(ref[f]).max(), 1e-300)
+                assert np.abs(got[f].astype(np.float64) - ref[f]).max() <= 1e-9 * scale, f"{cfg}: {f}"
+            else:
+                assert np.array_equal(got[f], ref[f]), f"{cfg}: {f} differs"
+
+
+def test_launch_argument_errors():
+    from paper_2506_05362_amd import pd
+    sim = pd.Sim(cases()["aggregate"])
+    for bad in (dict(loop=9), dict(slices_per_block=3), dict(xcd_remap=2), dict(persistent_blocks=-1)):
+        with pytest.raises(pd.PDError) as e:
+            sim.set_launch(**bad)
+        assert e.value.status == pd.PD_ERR_INVALID
+
+
+def test_uneven_aggregate_full_size_batched_equals_per_grain():
+    """100 grains of 2e3-5e4 nodes (1.5 M nodes) between platens: the batched
+    launch and one launch per grain agree bitwise, and the pairwise internal
+    forces cancel, so the nodes' total force balances the wall reactions."""
+    from paper_2506_05362_amd import pd
+    wl = I.grain_aggregate(seed=0, rebuild_every=20)
+    print(f"[full] {wl.n_nodes} nodes", flush=True)
+    a = pd.Sim(wl)
+    a.step(40)
+    b = pd.Sim(wl)
+    b.set_launch(loop=pd.LOOP_PER_GRAIN)
+    b.step(40)
+    for f in ("displacement", "velocity", "bond_broken"):
+        assert np.array_equal(a.get(f), b.get(f)), f
+    fa, fb = a.get("wall_force"), b.get("wall_force")
+    assert np.abs(fa - fb).max() <= 1e-12 * np.abs(fa).max()
+    F = a.get("force_density")
+    V = (wl.grain_h ** 3)[wl.grain_of_node()]
+    total = (F * V).sum(axis=1)
+    walls = a.get("wall_force").sum(axis=0)
+    scale = np.abs(F * V).sum(axis=1).max()
+    assert np.abs(total + walls).max() <= 1e-9 * scale
+
+
+def test_autotune_restores_state_and_caches(tmp_path):
+    from paper_2506_05362_amd import autotune, pd
+    wl = cases()["aggregate"]
+    sim = pd.Sim(wl)
+    sim.step(20)
+    u0 = sim.get("displacement")
+    path = str(tmp_path / "tune.json")
+    r = autotune.tune(sim, steps=20, path=path)
+    assert not r["cached"] and np.isfinite(min(r["times"].values()))
+    assert np.array_equal(sim.get("displacement"), u0) and sim.get("step")[0] == 20
+    assert sim.get_launch()["loop"] == r["config"]["loop"]
+    table = json.load(open(path))
+    assert r["key"] in table
+    other = pd.Sim(wl)
+    r2 = autotune.tune(other, path=path)
+    assert r2["cached"] and r2["config"] == r["config"]
