@@ -56,6 +56,8 @@ struct pd_ctx {
   double* Kn = nullptr;
   WallDev* walls = nullptr;
   double* wall_partial = nullptr;
+  double* wall_chunk = nullptr;
+  uint32_t* fin_counter = nullptr;
   int64_t* box_chunks = nullptr;
   int32_t n_box_chunks = 0;
   int64_t* step_d = nullptr;
@@ -233,6 +235,8 @@ StepArgs step_args(pd_ctx* c) {
   A.Kn = c->Kn;
   A.walls = c->walls;
   A.wall_partial = c->wall_partial;
+  A.wall_chunk = c->wall_chunk;
+  A.finalize_counter = c->fin_counter;
   A.step = c->step_d;
   A.advance = 1;
   A.status = c->status;
@@ -632,6 +636,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->walls, kMaxWalls, "walls"));
   TRY(alloc_n(c, &c->step_d, 1, "step"));
   TRY(alloc_n(c, &c->status, 1, "status"));
+  TRY(alloc_n(c, &c->fin_counter, 1, "finalize counter"));
   if (mesh->fixed) TRY(alloc_n(c, &c->fixed, N, "fixed"));
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(c->X, mesh->X, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
@@ -643,6 +648,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (mesh->fixed) HIPCHK(c, hipMemcpyAsync(c->fixed, mesh->fixed, (size_t)N, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemsetAsync(c->step_d, 0, sizeof(int64_t), s));
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), s));
+  HIPCHK(c, hipMemsetAsync(c->fin_counter, 0, sizeof(uint32_t), s));
   if (mesh->v0)
     HIPCHK(c, hipMemcpyAsync(c->v, mesh->v0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
   else
@@ -883,6 +889,8 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   }
   c->partial_cols = std::max<int64_t>(std::max<int64_t>(c->nslices, c->pg_cols), 1);
   TRY(alloc_n(c, &c->wall_partial, c->partial_cols * 3 * std::max(c->n_walls, 1), "wall partials"));
+  TRY(alloc_n(c, &c->wall_chunk, ((c->partial_cols + kChunk - 1) / kChunk) * 3 * std::max(c->n_walls, 1),
+              "wall chunk sums"));
 
   // first candidate list at u0, then F^0 and a^0 (velocity untouched)
   ContactArgs C = contact_args(c, c->cur);

@@ -19,6 +19,7 @@ constexpr int kMaxWalls = 8;
 constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
+constexpr int kChunk = 1024;        // wall-partial columns reduced by one workgroup
 #ifndef PD_BOND_UNROLL
 #define PD_BOND_UNROLL 4
 #endif
@@ -111,6 +112,8 @@ struct StepArgs {
   const double* Kn;     // [n_mat * n_mat]
   WallDev* walls;
   double* wall_partial;  // [n_walls][3][partial_stride]: one column per slice (component-major)
+  double* wall_chunk;    // [n_walls][3][chunks]: sums of 1024-column chunks of wall_partial
+  uint32_t* finalize_counter;  // arrivals at the wall finalize (zero between launches)
   int64_t* step;         // device step counter
   int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;

@@ -19,6 +19,8 @@
 // Sec. 3.1 eq. (peri-damage) with nodal quadrature, Sec. 6.1): no atomics, so
 // results are bitwise reproducible run to run.
 
+#include <algorithm>
+
 #include "pd_internal.h"
 
 namespace pdk {
@@ -237,8 +239,17 @@ __device__ __forceinline__ double wave_sum(double x) {
 #endif
 
 // 1 - (1 + x)^(-1/2) = x * sum_k (-1)^k a_{k+1} x^k with a_k = C(2k, k) / 4^k.
-// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange.
+// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange;
+// five terms suffice for |x| <= kPolyTiny (first omitted term < 1.5e-19 relative).
 constexpr double kPolyRange = 0.02;
+constexpr double kPolyTiny = 2e-4;
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x_5(double x) {
+  double p = 63.0 / 256.0;
+  p = fma(p, x, -35.0 / 128.0);
+  p = fma(p, x, 5.0 / 16.0);
+  p = fma(p, x, -3.0 / 8.0);
+  return fma(p, x, 0.5);
+}
 __device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) {
   double p = -46189.0 / 262144.0;
   p = fma(p, x, 12155.0 / 65536.0);
@@ -287,7 +298,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   // Bond law (Sec. 3.1): the force on i is c s V_j y/|y|, y = xi + eta, and
   //   c V s / |y| = (c V / |xi|) g,   g = 1 - |xi|/|y| = 1 - (1 + x)^(-1/2),
   //   x = (|y|^2 - |xi|^2) / |xi|^2,   |y|^2 - |xi|^2 = eta . (2 xi + eta).
-  // g comes from its power series when |x| <= kPolyRange (no square root or
+  // g comes from its power series when |x| <= kPolyRange (five terms when every
+  // lane of the wavefront has |x| <= kPolyTiny; no square root or
   // division), else from g = (|y|^2 - |xi|^2) / (|y| (|y| + |xi|)); neither
   // form subtracts nearly equal numbers.
   int64_t off = 0;
@@ -328,11 +340,16 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
       bool over = d > S.thr_d;
       if (ABS) over = over || d < -abs_ratio * S.thr_d;
       const double x = d * S.inv_l0sq;
-      double g = x * one_minus_rsqrt1p_over_x(x);
-      if (!(fabs(x) <= kPolyRange)) {
-        const double lsq = S.l0sq + d;
-        const double l = lsq * rsqrt_full(lsq);
-        g = d * rcp_full(fma(l, S.l0, lsq));
+      double g;
+      if (__all(fabs(x) <= kPolyTiny)) {  // wave-uniform: the short series for every lane
+        g = x * one_minus_rsqrt1p_over_x_5(x);
+      } else {
+        g = x * one_minus_rsqrt1p_over_x(x);
+        if (!(fabs(x) <= kPolyRange)) {
+          const double lsq = S.l0sq + d;
+          const double l = lsq * rsqrt_full(lsq);
+          g = d * rcp_full(fma(l, S.l0, lsq));
+        }
       }
       const double coef = over ? 0.0 : S.civ * g;
       fx = fma(coef, yx, fx);
@@ -501,62 +518,78 @@ void k_step(StepArgs A) {
   step_body<MODE, ABS, SPB>(A, s_st, blk);
 }
 
-// reaction forces (fixed-order sum of slice partials) and the wall positions
-// of the next step: prescribed velocity or servo on the measured stress.
-// The sum order is that of 1024 threads whatever NT is: virtual thread v sums
-// columns v, v + 1024, ... of a component, each virtual wave of 64 is reduced
-// across lanes, then the 16 wave sums in order; so every step-loop mode gives
-// bitwise the same reactions.  Components are taken CB at a time with 4 blocks
-// of loads in flight per virtual thread.
+// Wall reactions are reduced in a fixed order in two levels, the same in every
+// step-loop mode: (1) chunk q of 1024 slice columns of a component is summed by
+// one wavefront, lane l taking columns 1024 q + l + 64 k (k = 0..15) in turn,
+// then across the lanes; (2) the chunk sums of a component are summed as by
+// 1024 threads (virtual thread v takes chunks v, v + 1024, ...), across each
+// virtual wave's lanes and over the 16 virtual waves in order.  With at most 64
+// chunks only virtual wave 0 holds data and (2) is one wavefront's lane sum.
+__device__ __forceinline__ double chunk_sum(const StepArgs& A, int c, int64_t q) {
+  const int lane = threadIdx.x & 63;
+  const int64_t n = A.partial_stride, b = q * kChunk + lane;
+  const double* p = A.wall_partial + (int64_t)c * n;
+  double v[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) v[k] = b + 64 * k < n ? p[b + 64 * k] : 0.0;
+  double s = 0.0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) s += v[k];
+  return wave_sum(s);
+}
+
+// Level (2) by one workgroup of NT threads from the chunk sums in wall_chunk,
+// then the reactions and the wall positions of the next step: prescribed
+// velocity or servo on the measured stress.
 template <int NT>
-__device__ __forceinline__ void finalize_body(const StepArgs& A, int64_t nblocks,
-                                              double (*red)[1024 / kWave], double* tot,
-                                              int64_t* s_step) {
+__device__ __forceinline__ void finalize_level2(const StepArgs& A, double (*red)[1024 / kWave],
+                                                double* tot, int64_t* s_step) {
   constexpr int VT = 1024 / NT;
   constexpr int CB = NT >= 1024 ? 8 : 2;  // components per batch (register budget)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int nc = 3 * A.n_walls;
-  for (int c0 = 0; c0 < nc; c0 += CB) {
-    double acc[CB][VT];
-#pragma unroll
-    for (int cc = 0; cc < CB; ++cc)
-#pragma unroll
-      for (int k = 0; k < VT; ++k) acc[cc][k] = 0.0;
-    for (int64_t b0 = 0; b0 < nblocks; b0 += 4 * 1024) {
-#pragma unroll
-      for (int k = 0; k < VT; ++k) {
-        const int64_t v0 = b0 + tid + (int64_t)NT * k;  // virtual thread tid + NT k
-        double v[CB][4];
-#pragma unroll
-        for (int cc = 0; cc < CB; ++cc)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) {
-            const int c = c0 + cc;
-            const int64_t bb = v0 + 1024 * r;
-            v[cc][r] = (c < nc && bb < nblocks) ? A.wall_partial[(int64_t)c * nblocks + bb] : 0.0;
-          }
-#pragma unroll
-        for (int cc = 0; cc < CB; ++cc)
-#pragma unroll
-          for (int r = 0; r < 4; ++r) acc[cc][k] += v[cc][r];
+  const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
+  if (nq <= kWave) {
+    if (wv == 0)
+      for (int c = 0; c < nc; ++c) {
+        const double t = wave_sum(lane < nq ? A.wall_chunk[(int64_t)c * nq + lane] : 0.0);
+        if (lane == 0) tot[c] = t;
       }
-    }
+  } else {
+    for (int c0 = 0; c0 < nc; c0 += CB) {
+      double acc[CB][VT];
 #pragma unroll
-    for (int cc = 0; cc < CB; ++cc) {
-      if (c0 + cc < nc) {
+      for (int cc = 0; cc < CB; ++cc)
+#pragma unroll
+        for (int k = 0; k < VT; ++k) acc[cc][k] = 0.0;
+      for (int64_t b0 = 0; b0 < nq; b0 += 1024) {
 #pragma unroll
         for (int k = 0; k < VT; ++k) {
-          const double t = wave_sum(acc[cc][k]);
-          if (lane == 0) red[c0 + cc][wv + (NT / kWave) * k] = t;
+          const int64_t b = b0 + tid + (int64_t)NT * k;  // virtual thread tid + NT k
+#pragma unroll
+          for (int cc = 0; cc < CB; ++cc) {
+            const int c = c0 + cc;
+            if (c < nc && b < nq) acc[cc][k] += A.wall_chunk[(int64_t)c * nq + b];
+          }
+        }
+      }
+#pragma unroll
+      for (int cc = 0; cc < CB; ++cc) {
+        if (c0 + cc < nc) {
+#pragma unroll
+          for (int k = 0; k < VT; ++k) {
+            const double t = wave_sum(acc[cc][k]);
+            if (lane == 0) red[c0 + cc][wv + (NT / kWave) * k] = t;
+          }
         }
       }
     }
-  }
-  __syncthreads();
-  if (tid < nc) {
-    double t = 0.0;
-    for (int k = 0; k < 1024 / kWave; ++k) t += red[tid][k];
-    tot[tid] = t;
+    __syncthreads();
+    if (tid < nc) {
+      double t = 0.0;
+      for (int k = 0; k < 1024 / kWave; ++k) t += red[tid][k];
+      tot[tid] = t;
+    }
   }
   if (tid == 0) *s_step = *A.step + A.advance;  // the step this evaluation belonged to
   __syncthreads();
@@ -583,11 +616,32 @@ __device__ __forceinline__ void finalize_body(const StepArgs& A, int64_t nblocks
   }
 }
 
-__global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A, int64_t nblocks) {
+// One wavefront per (component, chunk) pair computes level (1); the last one to
+// finish (device-scope counter) runs level (2) and the wall update, then resets
+// the counter.  The fences make the chunk sums of every XCD visible to it.
+__global__ __launch_bounds__(kWave) void k_wall_finalize(StepArgs A, uint32_t* counter) {
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
-  finalize_body<1024>(A, nblocks, red, tot, &s_step);
+  __shared__ uint32_t last;
+  const int nc = 3 * A.n_walls;
+  const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
+  const int64_t pairs = (int64_t)nc * nq;
+  if ((int64_t)blockIdx.x < pairs) {
+    const int c = (int)(blockIdx.x / nq);
+    const int64_t q = blockIdx.x % nq;
+    const double t = chunk_sum(A, c, q);
+    if (threadIdx.x == 0) A.wall_chunk[(int64_t)c * nq + q] = t;
+  }
+  if (threadIdx.x == 0) {
+    __threadfence();
+    last = atomicAdd(counter, 1u) == gridDim.x - 1u ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!last) return;
+  __threadfence();
+  finalize_level2<kWave>(A, red, tot, &s_step);
+  if (threadIdx.x == 0) atomicExch(counter, 0u);
 }
 
 // ---------------------------------------------------------------------------
@@ -636,7 +690,17 @@ void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs
       step_body<MODE_STEP, ABS, 4>(A, s_st, blk);
     }
     grid_barrier(B, gridDim.x, A.status);
-    if (blockIdx.x == 0) finalize_body<4 * kWave>(A, A.partial_stride, red, tot, &s_step);
+    if (blockIdx.x == 0) {
+      // level (1) by this workgroup's wavefronts, then level (2)
+      const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
+      for (int64_t pq = threadIdx.x >> 6; pq < (int64_t)(3 * A.n_walls) * nq; pq += 4) {
+        const double t = chunk_sum(A, (int)(pq / nq), pq % nq);
+        if ((threadIdx.x & 63) == 0) A.wall_chunk[pq] = t;
+      }
+      __threadfence_block();
+      __syncthreads();
+      finalize_level2<4 * kWave>(A, red, tot, &s_step);
+    }
     grid_barrier(B, gridDim.x, A.status);
     // the drift just written is the next step's position; mid-step velocities likewise
     const double4* uc = A.ucur;
@@ -1110,7 +1174,9 @@ int32_t step_blocks_spb(int64_t nslices, int slices_per_block) {
 int32_t step_grid_blocks(int64_t nslices) { return step_blocks_spb(nslices, kSlicesPerBlock); }
 
 hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s) {
-  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(1024), 0, s, a, (int64_t)a.partial_stride);
+  const int64_t nq = (a.partial_stride + kChunk - 1) / kChunk;
+  const int64_t pairs = std::max<int64_t>((int64_t)(3 * a.n_walls) * nq, 1);
+  hipLaunchKernelGGL(k_wall_finalize, dim3((unsigned)pairs), dim3(kWave), 0, s, a, a.finalize_counter);
   return hipGetLastError();
 }
 
