@@ -91,6 +91,9 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="also run the representative-volume surrogate pipeline (64 simulated "
+                         "paths, training, held-out error, inference speed; several minutes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -186,6 +189,18 @@ def main():
     sim.close()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, nnz, args.cpu_budget)
+    if args.surrogate:
+        from paper_2506_05362_amd import surrogate
+        r = surrogate.run(log=lambda s: print(s, file=sys.stderr, flush=True))
+        out["surrogate"] = {
+            "metric": "RVE surrogate speedup per path at held-out axial stress error",
+            "speedup_per_path": r["speedup_per_path"],
+            "held_out_axial_rel_l2_mean": r["axial_rel_l2_mean"],
+            "interpolation_axial_rel_l2_mean": r["interp_axial_rel_l2_mean"],
+            "sim_seconds_per_path": r["sim_seconds_per_path"],
+            "network_seconds_per_path": r["inference"]["seconds_per_path"],
+            "paths": r["paths"], "held_out": r["held_out"], "dtype": "bf16 matrix cores, fp32 accumulate",
+        }
     print(json.dumps(out), flush=True)
 
 

@@ -49,8 +49,16 @@ pd_status pdm_get_params(pdm_net* net, float* params, int64_t n);
    the gradient moments. */
 pd_status pdm_set_adam(pdm_net* net, float beta1, float beta2, float eps, float weight_decay);
 /* Inference: y[batch][dims[n-1]] = net(x[batch][dims[0]]); any batch size
-   (processed in chunks of max_batch). */
+   (processed in chunks of max_batch).  For dims {din <= 16, 256, 256, 256,
+   dout <= 16} a fused path runs by default: two kernels with a weight matrix
+   resident in LDS, the first hidden pair's activations kept in registers and
+   only the second hidden layer's BF16 activations stored between them; its
+   operands are rounded to BF16 where the layer-by-layer path rounds them. */
 pd_status pdm_forward(pdm_net* net, const float* x, int64_t batch, float* y);
+/* Choose the inference path: fused != 0 selects the fused kernels (error
+   PD_ERR_UNSUPPORTED when the dims or the device do not allow them), 0 the
+   layer-by-layer kernels used for training. */
+pd_status pdm_set_inference(pdm_net* net, int32_t fused);
 /* Loss and gradient (host vector of pdm_param_count entries) of the mean
    squared error, without updating the parameters. */
 pd_status pdm_gradients(pdm_net* net, const float* x, const float* y, int64_t batch, float* loss,

@@ -15,6 +15,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <algorithm>
 #include <new>
 #include <string>
 #include <vector>
@@ -167,6 +168,171 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
   p[i] = pi - lr * ((mi / c1) / (sqrtf(vi / c2) + eps) + wd * pi);
 }
 
+// ---------------------------------------------------------------------------
+// Fused inference for din <= 16 -> 256 -> 256 -> 256 -> dout <= 16.
+// Phase A: layer 1 on the vector units (its 6-wide products are too small for
+// the matrix cores), its GELU outputs become the BF16 A operand of layer 2
+// directly in registers; layer 2 on the matrix cores with W2 resident in LDS;
+// GELU; BF16 H2 to HBM.  Phase B: layer 3 from H2 with W3 in LDS; each 16 x 16
+// output tile is GELU'd and turned into the A operand of layer 4 through a
+// small per-wavefront LDS tile, so layer 4 runs on the matrix cores as it goes.
+// Operands are rounded to BF16 exactly where the layer-by-layer path rounds
+// them (x, W1, activations, W2..W4); accumulation is FP32.
+// Each workgroup keeps a weight matrix in LDS and walks 64-row tiles of the
+// batch (4 wavefronts x 16 rows).
+// ---------------------------------------------------------------------------
+
+constexpr int kH = 256;          // hidden width of the fused path
+constexpr int kWRow = kH + 4;    // LDS row of a transposed weight matrix (bf16), padded
+constexpr int kTRow = 16 + 4;    // per-wavefront transpose tile row (bf16)
+
+__device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
+
+struct Infer {
+  const float* x;
+  int64_t M;
+  int din, dout;
+  const float* W1;   // [din][kH] fp32 (rounded to bf16 on use)
+  const float* b1;
+  const short* W2t;  // [kH][kH] bf16, transposed (n-major)
+  const float* b2;
+  const short* W3t;
+  const float* b3;
+  const short* W4t;  // [16][kH] bf16, rows >= dout zero
+  const float* b4;
+  short* H2;         // [M][kH] bf16
+  float* y;          // [M][dout]
+};
+
+// out[n][k] = bf16(W[k][n]) for n < N, zero rows for N <= n < rows_out
+__global__ void k_pack_t(const float* W, int K, int N, int rows_out, short* out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= (int64_t)rows_out * K) return;
+  const int n = (int)(i / K), k = (int)(i % K);
+  out[i] = n < N ? to_bf16(W[(int64_t)k * N + n]) : (short)0;
+}
+
+__device__ __forceinline__ void stage_weights_t(const short* src, int rows, short* dst) {
+  // rows x kH bf16 (8-byte pieces) into LDS rows of kWRow
+  for (int i = threadIdx.x; i < rows * (kH / 4); i += blockDim.x) {
+    const int r = i / (kH / 4), c = (i % (kH / 4)) * 4;
+    *reinterpret_cast<v4s*>(dst + r * kWRow + c) = *reinterpret_cast<const v4s*>(src + (int64_t)r * kH + c);
+  }
+}
+
+template <int DINP>
+__global__ __launch_bounds__(256) void k_infer_a(Infer a) {
+  extern __shared__ __align__(16) char smem[];
+  short* sW = reinterpret_cast<short*>(smem);                                   // [kH][kWRow]
+  float* sW1 = reinterpret_cast<float*>(smem + sizeof(short) * kH * kWRow);     // [16][kH]
+  float* sb1 = sW1 + 16 * kH;
+  float* sb2 = sb1 + kH;
+  const int tid = threadIdx.x;
+  stage_weights_t(a.W2t, kH, sW);
+  for (int i = tid; i < 16 * kH; i += 256) sW1[i] = i < a.din * kH ? bf16_to_f(to_bf16(a.W1[i])) : 0.0f;
+  for (int i = tid; i < kH; i += 256) {
+    sb1[i] = a.b1[i];
+    sb2[i] = a.b2[i];
+  }
+  __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  const int64_t ntiles = (a.M + 63) / 64;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t r0 = t * 64 + wv * 16;
+    const int64_t row = r0 + lr;
+    float xv[DINP];
+#pragma unroll
+    for (int i = 0; i < DINP; ++i) xv[i] = (i < a.din && row < a.M) ? bf16_to_f(to_bf16(a.x[row * a.din + i])) : 0.0f;
+    // k-step outer: the layer-1 output for this k-step is the A operand of all
+    // 16 output tiles of layer 2, each with its own accumulator
+    v4f acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      v4s A;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = kk * 16 + 4 * lg + j;
+        float z = 0.0f;
+#pragma unroll
+        for (int i = 0; i < DINP; ++i) z = fmaf(xv[i], sW1[i * kH + k], z);
+        A[j] = to_bf16(gelu(z + sb1[k]));
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const v4s b = *reinterpret_cast<const v4s*>(sW + (q * 16 + lr) * kWRow + kk * 16 + 4 * lg);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b, acc[q], 0, 0, 0);
+      }
+    }
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = q * 16 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) {
+        const int64_t rr = r0 + 4 * lg + e;
+        if (rr < a.M) a.H2[rr * kH + col] = to_bf16(gelu(acc[q][e] + sb2[col]));
+      }
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_infer_b(Infer a) {
+  extern __shared__ __align__(16) char smem[];
+  short* sW = reinterpret_cast<short*>(smem);                  // [kH][kWRow]
+  short* sW4 = sW + kH * kWRow;                                // [16][kWRow]
+  short* sT = sW4 + 16 * kWRow;                                // [4][16][kTRow]
+  float* sb3 = reinterpret_cast<float*>(sT + 4 * 16 * kTRow);  // [kH]
+  float* sb4 = sb3 + kH;                                       // [16]
+  const int tid = threadIdx.x;
+  stage_weights_t(a.W3t, kH, sW);
+  stage_weights_t(a.W4t, 16, sW4);
+  for (int i = tid; i < kH; i += 256) sb3[i] = a.b3[i];
+  if (tid < 16) sb4[tid] = tid < a.dout ? a.b4[tid] : 0.0f;
+  __syncthreads();
+  const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  short* T = sT + wv * 16 * kTRow;
+  const int64_t ntiles = (a.M + 63) / 64;
+  for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
+    const int64_t r0 = t * 64 + wv * 16;
+    const int64_t row = r0 + lr;
+    v4f acc[16];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 2
+    for (int kk = 0; kk < 16; ++kk) {
+      const v4s A = row < a.M ? *reinterpret_cast<const v4s*>(a.H2 + row * kH + kk * 16 + 4 * lg)
+                              : v4s{0, 0, 0, 0};
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        const v4s b = *reinterpret_cast<const v4s*>(sW + (q * 16 + lr) * kWRow + kk * 16 + 4 * lg);
+        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b, acc[q], 0, 0, 0);
+      }
+    }
+    // each 16 x 16 tile of layer 3: GELU, then transposed into the A operand of layer 4
+    v4f acc4 = v4f{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int q = 0; q < 16; ++q) {
+      const int col = q * 16 + lr;
+#pragma unroll
+      for (int e = 0; e < 4; ++e) T[(4 * lg + e) * kTRow + lr] = to_bf16(gelu(acc[q][e] + sb3[col]));
+      __syncthreads();
+      const v4s a4 = *reinterpret_cast<const v4s*>(T + lr * kTRow + 4 * lg);
+      const v4s b4 = *reinterpret_cast<const v4s*>(sW4 + lr * kWRow + q * 16 + 4 * lg);
+      acc4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc4, 0, 0, 0);
+      __syncthreads();
+    }
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      const int64_t rr = r0 + 4 * lg + e;
+      if (rr < a.M && lr < a.dout) a.y[rr * a.dout + lr] = acc4[e] + sb4[lr];
+    }
+  }
+}
+
+constexpr size_t kLdsA = sizeof(short) * kH * kWRow + sizeof(float) * (16 * kH + 2 * kH);
+constexpr size_t kLdsB = sizeof(short) * (kH * kWRow + 16 * kWRow + 4 * 16 * kTRow) + sizeof(float) * (kH + 16);
+
 }  // namespace
 
 struct pdm_net {
@@ -182,6 +348,9 @@ struct pdm_net {
   int nloss_blocks = 0;
   std::vector<int64_t> woff, boff;  // offsets of W_l, b_l in the parameter vector
   float beta1 = 0.9f, beta2 = 0.999f, eps = 1e-8f, weight_decay = 0.0f;
+  // fused inference path (din <= 16 -> 256 -> 256 -> 256 -> dout <= 16)
+  int fused_ok = 0, use_fused = 0, cus = 0;
+  short *W2t = nullptr, *W3t = nullptr, *W4t = nullptr, *H2 = nullptr;
   int64_t t = 0;
   std::vector<void*> owned;
 };
@@ -364,6 +533,26 @@ pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t
     TRY(alloc(n, &n->dZ[l], max_batch * dims[l + 1]));
   }
   TRY(alloc(n, &n->yhat, max_batch * dims[L]));
+  if (n_dims == 5 && dims[1] == kH && dims[2] == kH && dims[3] == kH && dims[0] <= 16 && dims[4] <= 16) {
+    int dev = 0, lds = 0;
+    if (hipGetDevice(&dev) == hipSuccess &&
+        hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
+        hipDeviceGetAttribute(&n->cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+        (size_t)lds >= kLdsA && (size_t)lds >= kLdsB &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_a<8>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsA) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_a<16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsA) == hipSuccess &&
+        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_b),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsB) == hipSuccess) {
+      TRY(alloc(n, &n->W2t, (int64_t)kH * kH));
+      TRY(alloc(n, &n->W3t, (int64_t)kH * kH));
+      TRY(alloc(n, &n->W4t, (int64_t)16 * kH));
+      TRY(alloc(n, &n->H2, max_batch * kH));
+      n->fused_ok = n->use_fused = 1;
+    }
+    (void)hipGetLastError();
+  }
   n->nloss_blocks = 256;
   TRY(alloc(n, &n->partial, n->nloss_blocks));
   HIPCHK(n, hipMemsetAsync(n->params, 0, sizeof(float) * o, n->stream));
@@ -405,12 +594,57 @@ pd_status pdm_set_adam(pdm_net* n, float b1, float b2, float eps, float weight_d
   return PD_OK;
 }
 
+pd_status pdm_set_inference(pdm_net* n, int32_t fused) {
+  if (!n) return PD_ERR_INVALID;
+  if (fused && !n->fused_ok)
+    return fail(n, PD_ERR_UNSUPPORTED, "the fused inference path needs dims din<=16,256,256,256,dout<=16 "
+                                       "and enough LDS per workgroup");
+  n->use_fused = fused ? 1 : 0;
+  return PD_OK;
+}
+
 pd_status pdm_forward(pdm_net* n, const float* x, int64_t batch, float* y) {
   if (!n || (!x && batch > 0) || (!y && batch > 0) || batch < 0) return PD_ERR_INVALID;
   const int64_t din = n->dims.front(), dout = n->dims.back();
-  for (int64_t b0 = 0; b0 < batch; b0 += n->max_batch) {
-    const int64_t cb = batch - b0 < n->max_batch ? batch - b0 : n->max_batch;
-    TRY(forward_chunk(n, x + b0 * din, cb, y + b0 * dout, false));
+  if (n->use_fused && batch > 0) {
+    // BF16 transposed copies of W2, W3, W4 (parameters may have changed since the last call)
+    const int64_t e = (int64_t)kH * kH;
+    hipLaunchKernelGGL(k_pack_t, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, n->stream,
+                       n->params + n->woff[1], kH, kH, kH, n->W2t);
+    hipLaunchKernelGGL(k_pack_t, dim3((unsigned)((e + 255) / 256)), dim3(256), 0, n->stream,
+                       n->params + n->woff[2], kH, kH, kH, n->W3t);
+    hipLaunchKernelGGL(k_pack_t, dim3((unsigned)((16 * kH + 255) / 256)), dim3(256), 0, n->stream,
+                       n->params + n->woff[3], kH, (int)dout, 16, n->W4t);
+    HIPCHK(n, hipGetLastError());
+    for (int64_t b0 = 0; b0 < batch; b0 += n->max_batch) {
+      const int64_t cb = batch - b0 < n->max_batch ? batch - b0 : n->max_batch;
+      Infer a{};
+      a.x = x + b0 * din;
+      a.M = cb;
+      a.din = (int)din;
+      a.dout = (int)dout;
+      a.W1 = n->params + n->woff[0];
+      a.b1 = n->params + n->boff[0];
+      a.W2t = n->W2t;
+      a.b2 = n->params + n->boff[1];
+      a.W3t = n->W3t;
+      a.b3 = n->params + n->boff[2];
+      a.W4t = n->W4t;
+      a.b4 = n->params + n->boff[3];
+      a.H2 = n->H2;
+      a.y = y + b0 * dout;
+      const int64_t tiles = (cb + 63) / 64;
+      const unsigned grid = (unsigned)std::min<int64_t>(tiles, std::max(n->cus, 1));
+      if (din <= 8) hipLaunchKernelGGL(k_infer_a<8>, dim3(grid), dim3(256), kLdsA, n->stream, a);
+      else hipLaunchKernelGGL(k_infer_a<16>, dim3(grid), dim3(256), kLdsA, n->stream, a);
+      hipLaunchKernelGGL(k_infer_b, dim3(grid), dim3(256), kLdsB, n->stream, a);
+      HIPCHK(n, hipGetLastError());
+    }
+  } else {
+    for (int64_t b0 = 0; b0 < batch; b0 += n->max_batch) {
+      const int64_t cb = batch - b0 < n->max_batch ? batch - b0 : n->max_batch;
+      TRY(forward_chunk(n, x + b0 * din, cb, y + b0 * dout, false));
+    }
   }
   HIPCHK(n, hipStreamSynchronize(n->stream));
   return PD_OK;

@@ -21,7 +21,7 @@ constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
 constexpr int kChunk = 1024;        // wall-partial columns reduced by one workgroup
 #ifndef PD_BOND_UNROLL
-#define PD_BOND_UNROLL 4
+#define PD_BOND_UNROLL 8
 #endif
 constexpr int kUnroll = PD_BOND_UNROLL;  // bond entries in flight per lane; slice widths are padded to it
 

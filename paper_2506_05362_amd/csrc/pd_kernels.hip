@@ -677,7 +677,7 @@ __device__ __forceinline__ void grid_barrier(const BarrierArgs& B, uint32_t nblo
 }
 
 template <bool ABS>
-__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(4)))
+__global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(kUnroll > 4 ? 3 : 4)))
 void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs B) {
   extern __shared__ StencilC s_st[];
   __shared__ double red[kMaxWalls * 3][1024 / kWave];

@@ -29,13 +29,14 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pdm_get_params.argtypes = [P, P, C.c_int64]
     L.pdm_set_adam.argtypes = [P, C.c_float, C.c_float, C.c_float, C.c_float]
     L.pdm_forward.argtypes = [P, P, C.c_int64, P]
+    L.pdm_set_inference.argtypes = [P, C.c_int32]
     L.pdm_gradients.argtypes = [P, P, P, C.c_int64, C.POINTER(C.c_float), P]
     L.pdm_train_step.argtypes = [P, P, P, C.c_int64, C.c_float, C.POINTER(C.c_float)]
     L.pdm_destroy.argtypes = [P]
     L.pdm_last_error.argtypes = [P]
     L.pdm_last_error.restype = C.c_char_p
     for name in ["pdm_create", "pdm_set_params", "pdm_get_params", "pdm_set_adam", "pdm_forward",
-                 "pdm_gradients", "pdm_train_step"]:
+                 "pdm_gradients", "pdm_train_step", "pdm_set_inference"]:
         getattr(L, name).restype = C.c_int32
     return L
 
@@ -89,6 +90,9 @@ class Net:
 
     def set_adam(self, beta1=0.9, beta2=0.999, eps=1e-8, weight_decay=0.0):
         self._check(lib().pdm_set_adam(self.h, beta1, beta2, eps, weight_decay))
+
+    def set_inference(self, fused: bool):
+        self._check(lib().pdm_set_inference(self.h, 1 if fused else 0))
 
     def forward(self, x):
         x = self._dev(x, self.dims[0])

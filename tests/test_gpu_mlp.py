@@ -83,6 +83,39 @@ def test_forward_large_batch_chunks_and_ragged_tail():
     assert np.abs(y - emu).max() <= 3e-3 * np.abs(emu).max()
 
 
+def test_fused_inference_matches_emulation_and_layer_path():
+    """The fused two-kernel inference path (weights in LDS) against the BF16
+    emulation and against the layer-by-layer kernels, over several max_batch
+    chunks, a ragged tail and a tile that is only partly filled."""
+    net, p, _, _, torch = setup()
+    rng = np.random.default_rng(5)
+    X = rng.normal(size=(1291, DIMS[0]))
+    xt = torch.tensor(X, dtype=torch.float32)
+    net.set_inference(True)
+    yf = net.forward(xt).cpu().numpy()
+    net.set_inference(False)
+    yl = net.forward(xt).cpu().numpy()
+    emu, _ = forward_bf16(p, DIMS, X)
+    for y in (yf, yl):
+        assert np.linalg.norm(y - emu) <= 2e-4 * np.linalg.norm(emu)
+        assert np.abs(y - emu).max() <= 3e-3 * np.abs(emu).max()
+    assert np.linalg.norm(yf - yl) <= 2e-4 * np.linalg.norm(yl)
+    for m in (1, 17, 64, 65):  # short and partial tiles
+        net.set_inference(True)
+        ym = net.forward(xt[:m]).cpu().numpy()
+        assert np.linalg.norm(ym - emu[:m]) <= 2e-4 * np.linalg.norm(emu[:m])
+
+
+def test_fused_inference_unsupported_shape():
+    import torch
+    from paper_2506_05362_amd import mlp
+    net = mlp.Net([5, 32, 32, 32, 3], max_batch=64)
+    with pytest.raises(mlp.MLPError):
+        net.set_inference(True)
+    net.set_inference(False)
+    assert net.forward(torch.zeros((3, 5))).shape == (3, 3)
+
+
 def test_gradients_match_oracle():
     net, p, X, Y, torch = setup(batch=257)
     loss, g = net.gradients(torch.tensor(X, dtype=torch.float32), torch.tensor(Y, dtype=torch.float32))
