@@ -109,6 +109,13 @@ typedef struct {
                               i relative to j, e the unit vector from i to j; against a wall
                               -beta_d (v . n - wall rate) |S| n.  Velocities are the mid-step
                               values v_n + dt/2 a_n (v_0 in the first evaluation). */
+  double friction;         /* mu of the regularised stick-slip friction law (Sec. 3.3), >= 0;
+                              0 disables it.  Per contact pair, with w_t the tangential part
+                              of i's mid-step velocity relative to its partner (a wall moves
+                              only along its normal), f_r the repulsive force density the
+                              partner exerts on i (K_n (R_c - d) V_j, or K_n (R_c - |c - p|) |S|
+                              for a wall) and rho i's density: slip, -mu f_r w_t/|w_t|, when
+                              |w_t| > mu f_r dt / rho; stick, -(rho/dt) w_t, otherwise. */
 } pd_params;
 
 enum { PD_WALL_FIXED = 0, PD_WALL_VELOCITY = 1, PD_WALL_SERVO = 2 };

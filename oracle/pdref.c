@@ -28,6 +28,14 @@
  *      velocity is the mid-step value v_n + dt/2 a_n, the one known when the
  *      force at u_{n+1} is evaluated (v_0 in the first evaluation).  Against a
  *      wall the partner moves with the wall's rate along its normal.
+ *   R17 stick-slip friction (Sec. 3.3) acts per contact pair on the pair's force
+ *      density: f_r is the repulsive force density the partner exerts on the
+ *      node (K_n (R_c - d) V_j; against a wall K_n (R_c - |c - p|) |S|), so that
+ *      v_thr = mu f_r dt / rho is a speed and the stick force (rho/dt) |w_t|
+ *      meets the slip force mu f_r at the threshold.  The force opposes the
+ *      node's own tangential relative velocity w_t (the prose; the printed
+ *      e_perp(y,x) would push along it).  rho is the node's density; the
+ *      velocities are the mid-step ones of R15; f_r excludes the damping term.
  */
 #include "pdref.h"
 
@@ -69,7 +77,8 @@ struct pdref {
   int m;
   double Rc, eps, skin, dt, g[3];
   double beta;   /* normal damping coefficient beta_d, Sec. 3.4 */
-  double* vh;    /* velocity that the damping law sees: v + dt/2 a (v at the build) */
+  double mu;     /* friction coefficient of the stick-slip law, Sec. 3.3 */
+  double* vh;    /* velocity the damping and friction laws see: v + dt/2 a (v at the build) */
   int rebuild_every;
   int32_t n_walls;
   wall_t* walls;
@@ -169,6 +178,7 @@ pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double
   s->g[1] = params[7];
   s->g[2] = params[8];
   s->beta = params[9];
+  s->mu = params[10];
   s->flags = flags;
   s->grain_of = (int32_t*)malloc(sizeof(int32_t) * (size_t)(n + 1));
   for (int32_t g = 0; g < n_grains; ++g)
@@ -467,6 +477,24 @@ static double stretch(const double xi[3], const double eta[3], double l0, double
 }
 
 /* returns nonzero when an instability was seen (NaN force, wall penetration) */
+
+/* Regularised Coulomb friction, Sec. 3.3, eq. (regularized-friction), added to F.
+ * wt: tangential velocity of the node relative to its partner; fr: magnitude of
+ * the repulsive force density the partner exerts on the node; rho: the node's
+ * density.  Slip (|wt| above v_thr = mu fr dt / rho): magnitude mu fr against wt.
+ * Stick: -(1/eps_f) wt with eps_f = dt / rho, the force that stops wt in one step. */
+static void add_friction(double mu, double fr, double rho, double dt, const double wt[3],
+                         double F[3]) {
+  const double vt = sqrt((wt[0] * wt[0] + wt[1] * wt[1]) + wt[2] * wt[2]);
+  const double vthr = mu * fr * dt / rho;
+  if (vt > vthr) {
+    for (int q = 0; q < 3; ++q) F[q] -= mu * fr * wt[q] / vt;
+  } else {
+    const double eps_f = dt / rho;
+    for (int q = 0; q < 3; ++q) F[q] -= wt[q] / eps_f;
+  }
+}
+
 static int eval_force(pdref* s) {
   const int64_t n = s->n;
   const double Rc = s->Rc;
@@ -520,6 +548,18 @@ static int eval_force(pdref* s) {
         coef -= s->beta * s->gV[gj] * w / d2;
       }
       for (int q = 0; q < 3; ++q) Fi[q] += coef * y[q];
+      if (s->mu > 0.0) {
+        /* stick-slip friction, Sec. 3.3: the tangential part of the velocity of i
+           relative to j, against the repulsive force density K_n (R_c - d) V_j */
+        double e[3], w[3], wt[3], wn = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          e[q] = y[q] / d;
+          w[q] = s->vh[q * n + i] - s->vh[q * n + j];
+          wn += w[q] * e[q];
+        }
+        for (int q = 0; q < 3; ++q) wt[q] = w[q] - wn * e[q];
+        add_friction(s->mu, Kn * (Rc - d) * s->gV[gj], s->grho[g], s->dt, wt, Fi);
+      }
     }
     for (int q = 0; q < 3; ++q) {
       s->F[q * n + i] = Fi[q];
@@ -556,10 +596,22 @@ static int eval_force(pdref* s) {
         double vn = (W->n[0] * s->vh[i] + W->n[1] * s->vh[n + i]) + W->n[2] * s->vh[2 * n + i];
         mag -= s->beta * (vn - W->rate) * vol;
       }
+      double f[3];
+      for (int q = 0; q < 3; ++q) f[q] = mag * W->n[q];
+      if (s->mu > 0.0) {
+        /* friction against the wall (Sec. 4.1 with V_y -> |S_l|): the partner moves
+           with the wall's rate along n, so only v's tangential part counts */
+        double w[3], wt[3], wn = 0.0;
+        for (int q = 0; q < 3; ++q) {
+          w[q] = s->vh[q * n + i] - W->rate * W->n[q];
+          wn += w[q] * W->n[q];
+        }
+        for (int q = 0; q < 3; ++q) wt[q] = w[q] - wn * W->n[q];
+        add_friction(s->mu, Kn * (Rc - ell) * vol, s->grho[g], s->dt, wt, f);
+      }
       for (int q = 0; q < 3; ++q) {
-        double f = mag * W->n[q];
-        s->F[q * n + i] += f;
-        W->force[q] -= s->gV[g] * f;
+        s->F[q * n + i] += f[q];
+        W->force[q] -= s->gV[g] * f[q];
       }
     }
   }

@@ -16,6 +16,9 @@
  *   - repulsive contact -K_n (R_c - |p_y - p_x|) e between nodes of different
  *     grains (Sec. 3.2 eq. (repulsive-force)), K_n = 18 k / (pi eps^5) with the
  *     harmonic-mean bulk modulus;
+ *   - normal contact damping (Sec. 3.4 eq. (damping-force)) and regularised
+ *     stick-slip friction (Sec. 3.3 eq. (regularized-friction)) on the mid-step
+ *     velocity, between grains and against walls;
  *   - rigid planar walls, spherical-cap law (Sec. 4.1), walls summed (Sec. 4.1.1);
  *   - body force (Sec. 5.1 eq. (intra_particle)) and velocity Verlet (Sec. 6.2).
  *
@@ -41,8 +44,8 @@ extern "C" {
 /* packed cut record (16 int64):
  *   kind grain a b c d lox loy loz hix hiy hiz cx cy cz radius2     (half-lattice units) */
 #define PDREF_CUT_INTS 16
-/* params (10 doubles): m R_c eps skin rebuild_every dt gx gy gz beta_d */
-#define PDREF_PARAM_DOUBLES 10
+/* params (11 doubles): m R_c eps skin rebuild_every dt gx gy gz beta_d mu */
+#define PDREF_PARAM_DOUBLES 11
 
 typedef struct pdref pdref;
 

@@ -134,7 +134,8 @@ class Oracle:
             mat=np.array([[m.bulk_modulus, m.density, m.fracture_energy] for m in wl.materials],
                          dtype=np.float64),
             par=np.array([p.horizon_factor, p.contact_radius, p.contact_horizon, p.skin,
-                          p.rebuild_every, p.dt, *p.gravity, p.contact_damping],
+                          p.rebuild_every, p.dt, *p.gravity, p.contact_damping,
+                          getattr(p, "friction", 0.0)],
                          dtype=np.float64),
             walls=pack_walls(wl.walls), cuts=pack_cuts(wl.cuts))
         k = self._keep

@@ -28,7 +28,7 @@ struct pd_ctx {
   int64_t n = 0;
   int32_t n_grains = 0, n_mat = 0, n_walls = 0;
   int32_t m = 3, flags = 0, rebuild_every = 1, cap_per_node = 16;
-  double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0}, beta = 0;
+  double Rc = 0, eps = 0, skin = 0, dt = 0, g[3] = {0, 0, 0}, beta = 0, mu = 0;
   hipStream_t stream = nullptr;
   int own_stream = 0;
   pd_alloc_fn alloc = nullptr;
@@ -46,7 +46,7 @@ struct pd_ctx {
   std::vector<void*> owned;
   // device state
   double4* u4[2] = {nullptr, nullptr};
-  double4* vh[2] = {nullptr, nullptr};  // mid-step velocities, indexed like u4 (beta > 0)
+  double4* vh[2] = {nullptr, nullptr};  // mid-step velocities, indexed like u4 (beta or mu > 0)
   double *v = nullptr, *a = nullptr, *X = nullptr, *F = nullptr;
   uint8_t* fixed = nullptr;
   GrainC* grains = nullptr;
@@ -210,6 +210,7 @@ StepArgs step_args(pd_ctx* c) {
   A.vh_cur = c->vh[c->cur];
   A.vh_next = c->vh[c->cur ^ 1];
   A.beta = c->beta;
+  A.mu = c->mu;
   A.slice_base = 0;
   A.slice_end = c->nslices;
   A.node_lo = 0;
@@ -514,6 +515,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (P.rebuild_every < 1) return fail(c, PD_ERR_INVALID, "rebuild_every must be >= 1");
   if (!(P.contact_damping >= 0) || !isfinite(P.contact_damping))
     return fail(c, PD_ERR_INVALID, "contact_damping must be finite and >= 0");
+  if (!(P.friction >= 0) || !isfinite(P.friction))
+    return fail(c, PD_ERR_INVALID, "friction must be finite and >= 0");
   if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
@@ -529,6 +532,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->skin = P.skin;
   c->dt = P.dt;
   c->beta = P.contact_damping;
+  c->mu = P.friction;
   c->rebuild_every = P.rebuild_every;
   c->use_graph = (P.flags & PD_FLAG_NO_GRAPH) ? 0 : 1;
   if (!c->use_graph) c->launch.loop = PD_LOOP_DIRECT;
@@ -654,8 +658,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   else
     HIPCHK(c, hipMemsetAsync(c->v, 0, sizeof(double) * 3 * N, s));
   HIPCHK(c, hipMemsetAsync(c->a, 0, sizeof(double) * 3 * N, s));
-  if (c->beta > 0) {
-    // the first evaluation's damping sees v_0 (zero on fixed nodes)
+  if (c->beta > 0 || c->mu > 0) {
+    // the first evaluation's damping and friction see v_0 (zero on fixed nodes)
     TRY(alloc_n(c, &c->vh[0], N, "mid-step velocity"));
     TRY(alloc_n(c, &c->vh[1], N, "mid-step velocity'"));
     std::vector<double4> vh0((size_t)N, make_double4(0.0, 0.0, 0.0, 0.0));
@@ -1181,13 +1185,13 @@ pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
 
 // checkpoint layout: header[8] (magic, n, padded, n_walls, step, cur, nnz, crc-less size),
 // then u4[cur], u4[cur^1], v, a, live column words, intact, u_build, walls,
-// [vh[cur], vh[cur^1] when damping is on], crc32
+// [vh[cur], vh[cur^1] when damping or friction is on], crc32
 pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   if (!c || !bytes) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   const int64_t N = c->n;
   const int64_t words = c->padded;
-  const int64_t nvh = c->beta > 0 ? 2 * 32 * N : 0;
+  const int64_t nvh = (c->beta > 0 || c->mu > 0) ? 2 * 32 * N : 0;
   const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
                        (int64_t)sizeof(WallDev) * c->n_walls + nvh;
   const int64_t total = body + 4;
@@ -1233,7 +1237,7 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   int64_t hdr[8];
   memcpy(hdr, p, sizeof hdr);
   const int64_t N = c->n, words = c->padded;
-  const int64_t nvh = c->beta > 0 ? 2 * 32 * N : 0;
+  const int64_t nvh = (c->beta > 0 || c->mu > 0) ? 2 * 32 * N : 0;
   const int64_t body = 8 * 8 + 2 * 32 * N + 2 * 24 * N + 4 * words + 4 * N + 24 * N +
                        (int64_t)sizeof(WallDev) * c->n_walls + nvh;
   if (hdr[0] != (int64_t)kMagic || hdr[1] != N || hdr[2] != c->padded || hdr[3] != c->n_walls ||

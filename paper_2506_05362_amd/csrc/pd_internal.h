@@ -92,7 +92,7 @@ struct StepArgs {
   double* v;            // SoA
   double* a;            // SoA
   double* Fout;         // MODE_FORCE_ONLY output (SoA)
-  const double4* vh_cur;  // mid-step velocity seen by the damping law (beta > 0 only)
+  const double4* vh_cur;  // mid-step velocity seen by damping and friction (beta or mu > 0)
   double4* vh_next;       // ... written for the next evaluation
   const uint8_t* fixed;
   const GrainC* grains;
@@ -125,6 +125,7 @@ struct StepArgs {
   double dt;
   double g[3];
   double beta;           // normal damping coefficient, 0 = off
+  double mu;             // stick-slip friction coefficient, 0 = off
   int32_t abs_stretch;
   // launch geometry: the slices [slice_base, slice_end) of this launch, nodes
   // outside [node_lo, node_hi) idle (per-grain launches), and the column of

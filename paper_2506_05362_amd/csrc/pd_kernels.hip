@@ -265,6 +265,20 @@ __device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) {
 
 // The fused step of one workgroup: SPB slices (one wavefront each) starting at
 // slice slice_base + SPB * blk.  s_st holds the stencil tables in LDS.
+// Regularised Coulomb friction (Sec. 3.3) added to f: t is the tangential
+// velocity of the node relative to its partner, mu_fr = mu times the repulsive
+// force density of the pair.  Slip when |t| exceeds the threshold mu_fr dt / rho:
+// magnitude mu_fr against t; otherwise stick, -(rho / dt) t, which would stop t
+// in one step.  The two branches agree at the threshold.
+__device__ __forceinline__ void stick_slip(double mu_fr, double rho, double dt, double tx, double ty,
+                                           double tz, double& fx, double& fy, double& fz) {
+  const double vt = sqrt(tx * tx + ty * ty + tz * tz);
+  const double k = vt > mu_fr * dt / rho ? mu_fr / vt : rho / dt;
+  fx = fma(-k, tx, fx);
+  fy = fma(-k, ty, fy);
+  fz = fma(-k, tz, fz);
+}
+
 template <int MODE, bool ABS, int SPB>
 __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_st, int64_t blk) {
   const int tid = threadIdx.x, lane = tid & 63;
@@ -362,10 +376,12 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
     }
   }
 
-  // mid-step velocity of this node for the normal damping law (Sec. 3.4)
-  const bool damp = A.beta > 0.0;
+  // mid-step velocity of this node for the normal damping (Sec. 3.4) and
+  // stick-slip friction (Sec. 3.3) laws
+  const bool damp = A.beta > 0.0, fric = A.mu > 0.0, vdep = damp || fric;
   double4 vhi = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (damp && valid) vhi = A.vh_cur[i];
+  if (vdep && valid) vhi = A.vh_cur[i];
+  const double rho_i = G->rho;
 
   // ---- repulsive contact with candidates of other grains (Sec. 3.2) ----
   if (valid && A.cand_ptr != nullptr) {
@@ -384,16 +400,26 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
         if (d2 < A.Rc2 && d2 > 0.0) {
           const GrainC* Gj = A.grains + packed_grain(uj.w);
           const double d = sqrt(d2);
-          double coef = -A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V / d;
+          const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
+          double coef = -rep / d;
+          double4 vhj = make_double4(0.0, 0.0, 0.0, 0.0);
+          if (vdep) vhj = A.vh_cur[j];
+          const double wx = vhi.x - vhj.x, wy = vhi.y - vhj.y, wz = vhi.z - vhj.z;
           if (damp) {
             // -beta (w . e) e V_j, w = velocity of i relative to j, e = y / d
-            const double4 vhj = A.vh_cur[j];
-            const double w = (vhi.x - vhj.x) * yx + (vhi.y - vhj.y) * yy + (vhi.z - vhj.z) * yz;
+            const double w = wx * yx + wy * yy + wz * yz;
             coef -= A.beta * Gj->V * w / d2;
           }
           fx = fma(coef, yx, fx);
           fy = fma(coef, yy, fy);
           fz = fma(coef, yz, fz);
+          if (fric) {
+            // tangential part of w against the repulsive force density rep
+            const double inv_d = 1.0 / d;
+            const double ex = yx * inv_d, ey = yy * inv_d, ez = yz * inv_d;
+            const double wn = wx * ex + wy * ey + wz * ez;
+            stick_slip(A.mu * rep, rho_i, A.dt, wx - wn * ex, wy - wn * ey, wz - wn * ez, fx, fy, fz);
+          }
         }
       }
     }
@@ -403,7 +429,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   for (int w = 0; w < A.n_walls; ++w) {
     const WallDev* Wd = A.walls + w;
     bool hit = false;
-    double mag = 0.0;
+    double mag = 0.0, ftx = 0.0, fty = 0.0, ftz = 0.0;  // normal magnitude, friction
     if (valid) {
       const double px = lattice_pos(G->origin[0], h, ix) + ui.x;
       const double py = lattice_pos(G->origin[1], h, iy) + ui.y;
@@ -421,30 +447,39 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
           const double H = A.Rc - d, q = 2.0 * A.Rc + d;
           const double vol = (M_PI / 3.0) * H * H * q;
           const double ell = 0.75 * (A.Rc + d) * (A.Rc + d) / q;
-          mag = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
+          const double rep = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
+          mag = rep;
+          const double rate = MODE == MODE_FORCE_ONLY ? Wd->rate_used : Wd->rate;
           if (damp) {
             // damping against the wall: relative normal velocity v . n - wall rate
-            const double rate = MODE == MODE_FORCE_ONLY ? Wd->rate_used : Wd->rate;
             const double vn = Wd->n[0] * vhi.x + Wd->n[1] * vhi.y + Wd->n[2] * vhi.z;
             mag -= A.beta * (vn - rate) * vol;
+          }
+          if (fric) {
+            // the wall moves along its normal only: friction sees v's tangential part
+            const double wx = vhi.x - rate * Wd->n[0], wy = vhi.y - rate * Wd->n[1],
+                         wz = vhi.z - rate * Wd->n[2];
+            const double wn = wx * Wd->n[0] + wy * Wd->n[1] + wz * Wd->n[2];
+            stick_slip(A.mu * rep, rho_i, A.dt, wx - wn * Wd->n[0], wy - wn * Wd->n[1],
+                       wz - wn * Wd->n[2], ftx, fty, ftz);
           }
           hit = true;
         }
       }
     }
     if (hit) {
-      fx = fma(mag, Wd->n[0], fx);
-      fy = fma(mag, Wd->n[1], fy);
-      fz = fma(mag, Wd->n[2], fz);
+      fx = fma(mag, Wd->n[0], fx) + ftx;
+      fy = fma(mag, Wd->n[1], fy) + fty;
+      fz = fma(mag, Wd->n[2], fz) + ftz;
     }
     if (MODE != MODE_FORCE_ONLY) {
       const uint64_t any = __ballot(hit);
       double r0 = 0.0, r1 = 0.0, r2 = 0.0;
       if (any) {
-        const double vm = hit ? G->V * mag : 0.0;
-        r0 = wave_sum(vm * Wd->n[0]);
-        r1 = wave_sum(vm * Wd->n[1]);
-        r2 = wave_sum(vm * Wd->n[2]);
+        const double vm = hit ? G->V * mag : 0.0, vf = hit ? G->V : 0.0;
+        r0 = wave_sum(fma(vf, ftx, vm * Wd->n[0]));
+        r1 = wave_sum(fma(vf, fty, vm * Wd->n[1]));
+        r2 = wave_sum(fma(vf, ftz, vm * Wd->n[2]));
       }
       // one partial per slice (wavefront), component-major: the finalize sums
       // them in slice order, whatever the workgroup size or launch split
@@ -492,8 +527,8 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
         un.z = fma(hdt2, anz, fma(dt, vz, ui.z));
       }
       A.unext[i] = un;
-      if (damp) {
-        // the next evaluation's damping sees v_{n+1} + dt/2 a_{n+1}
+      if (vdep) {
+        // the next evaluation's damping and friction see v_{n+1} + dt/2 a_{n+1}
         A.vh_next[i] = fixed ? make_double4(0.0, 0.0, 0.0, 0.0)
                              : make_double4(fma(hdt, anx, vx), fma(hdt, any, vy), fma(hdt, anz, vz), 0.0);
       }

@@ -54,7 +54,8 @@ class pd_params(C.Structure):
                 ("contact_radius", C.c_double), ("contact_horizon", C.c_double),
                 ("skin", C.c_double), ("rebuild_every", C.c_int32),
                 ("candidate_capacity_per_node", C.c_int32), ("dt", C.c_double),
-                ("gravity", C.c_double * 3), ("contact_damping", C.c_double)]
+                ("gravity", C.c_double * 3), ("contact_damping", C.c_double),
+                ("friction", C.c_double)]
 
 
 class pd_wall(C.Structure):
@@ -239,6 +240,7 @@ class Sim:
         prm.dt = p.dt
         prm.gravity[:] = list(p.gravity)
         prm.contact_damping = getattr(p, "contact_damping", 0.0)
+        prm.friction = getattr(p, "friction", 0.0)
         walls = (pd_wall * max(self.n_walls, 1))(*[make_wall(w) for w in wl.walls])
         h = P()
         if plumbing is not None:

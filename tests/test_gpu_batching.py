@@ -35,7 +35,9 @@ def cases():
                             platen_speed=5.0, rebuild_every=10)
     rve = I.rve_aggregate(seed=3, n_grains=12, nodes_per_grain=300, confinement=15e6,
                           platen_speed=20.0, rebuild_every=10, contact_damping=2.8e22)
-    return {"aggregate": agg, "rve_damped_servo": rve}
+    fric = I.rve_aggregate(seed=4, n_grains=12, nodes_per_grain=300, confinement=15e6,
+                           platen_speed=20.0, rebuild_every=10, friction=0.5)
+    return {"aggregate": agg, "rve_damped_servo": rve, "rve_friction_servo": fric}
 
 
 def run(wl, cfg, steps):
@@ -49,7 +51,7 @@ def run(wl, cfg, steps):
     return out
 
 
-@pytest.mark.parametrize("case", ["aggregate", "rve_damped_servo"])
+@pytest.mark.parametrize("case", ["aggregate", "rve_damped_servo", "rve_friction_servo"])
 def test_step_loop_modes_are_bitwise_identical(case):
     wl = cases()[case]
     steps = 65  # several rebuild periods and a ragged last run

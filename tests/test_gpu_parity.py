@@ -28,11 +28,17 @@ def rel_inf(a, b):
     return np.abs(a - b).max() / scale
 
 
-def assert_state_close(sim, ora, rel=REL, what=""):
+def assert_state_close(sim, ora, rel=REL, what="", a_scale=None):
+    """u, v, a and F within rel (infinity norm relative to the oracle's field).
+    a_scale, if given, replaces the acceleration's own magnitude as its scale:
+    for a body at rest a is the residual of forces of size rho a_scale."""
     so = ora.state()
     for name, key in (("displacement", "u"), ("velocity", "v"), ("accel", "a")):
         g = sim.get(name)
-        r = rel_inf(g, so[key])
+        if name == "accel" and a_scale is not None:
+            r = np.abs(g - so[key]).max() / a_scale
+        else:
+            r = rel_inf(g, so[key])
         assert r <= rel, f"{what} {name}: rel err {r:.3e}"
     Fg = sim.get("force_density")
     r = rel_inf(Fg, so["F"])
@@ -188,11 +194,12 @@ def test_runs_are_bitwise_deterministic():
     assert np.array_equal(out[0][1], out[1][1])
 
 
-@pytest.mark.parametrize("beta", [0.0, 5e21])
-def test_checkpoint_resume_is_bitwise(beta):
+@pytest.mark.parametrize("beta,mu", [(0.0, 0.0), (5e21, 0.0), (0.0, 0.4)])
+def test_checkpoint_resume_is_bitwise(beta, mu):
     from paper_2506_05362_amd import pd
     wl = I.two_spheres(radius_cells=6, speed=30.0, gap=0.0, rebuild_every=7)
     wl.params.contact_damping = beta
+    wl.params.friction = mu
     a = gpu_sim(wl)
     a.step(25)
     blob = a.get_state()
@@ -259,15 +266,16 @@ def test_graph_replay_matches_direct_launches():
     assert n == 20 and ms > 0
 
 
-@pytest.mark.parametrize("beta", [0.0, 2.8e22])
-def test_confined_rve_with_servo_walls(oracle_lib, beta):
+@pytest.mark.parametrize("beta,mu", [(0.0, 0.0), (2.8e22, 0.0), (0.0, 0.5), (2.8e22, 0.5)])
+def test_confined_rve_with_servo_walls(oracle_lib, beta, mu):
     """Tessellated aggregate between a fixed floor, a moving platen and four
-    servo-controlled lateral walls, with and without normal contact damping:
-    state 1e-9, reactions and impulses 1e-6, and the servo-driven wall offsets
-    1e-9 relative to the box size."""
+    servo-controlled lateral walls, with and without normal contact damping and
+    stick-slip friction: state 1e-9, reactions and impulses 1e-6, and the
+    servo-driven wall offsets 1e-9 relative to the box size."""
     wl = I.rve_aggregate(seed=3, n_grains=12, nodes_per_grain=300, confinement=15e6,
                          platen_speed=20.0, rebuild_every=10)
     wl.params.contact_damping = beta
+    wl.params.friction = mu
     sim = gpu_sim(wl)
     ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
     box = wl.info["span0"][2]
@@ -297,3 +305,54 @@ def test_damped_collision_matches_oracle(oracle_lib):
         assert_state_close(sim, ora, what=f"beta={beta}")
         runs[beta] = ora.energy()["kinetic"]
     assert runs[5e21] < runs[0.0]
+
+
+def test_sliding_node_friction_matches_oracle(oracle_lib):
+    """One node pressed on a floor by its weight and launched sideways: stick-slip
+    friction (Sec. 3.3) against the wall slows it to rest.  State 1e-9 and the
+    wall's reaction, tangential part included, 1e-6 through slip and stick."""
+    h, dt = 1e-4, 1e-9
+    off = np.zeros((3, 1), dtype=np.int64)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, dt)
+    d = 0.9 * params.contact_radius
+    floor = I.Wall(normal=(0.0, 0.0, 1.0), offset=-d, mode=I.WALL_FIXED, area=1.0)
+    probe = I.assemble("node", [(ijk, origin, h, 0)], [I.SAND], params, [floor], [], 1)
+    gn = oracle_lib.Oracle(probe).state()["F"][2, 0] / I.SAND.density
+    params.gravity, params.friction = (0.1 * gn, 0.0, -gn), 0.4
+    v0 = np.array([[1500 * dt * 0.3 * gn], [0.2 * 1500 * dt * 0.3 * gn], [0.0]])
+    wl = I.assemble("node", [(ijk, origin, h, 0)], [I.SAND], params, [floor], [], 1, v0=v0)
+    sim = gpu_sim(wl)
+    ora = oracle_lib.Oracle(wl)
+    for n in (500, 1000, 1000):  # slipping, then stuck and creeping
+        sim.step(n)
+        ora.step(n)
+        # at rest the acceleration is the residual of the weight and the wall's
+        # push, so it is compared on the scale of the weight
+        assert_state_close(sim, ora, what=f"step {ora.step_count}", a_scale=gn)
+        fo, _ = ora.walls()
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        assert rel_inf(sim.get("wall_impulse"), ora.wall_impulse()) <= 1e-6
+    assert abs(ora.wall_impulse()[0, 0]) > 0
+
+
+def test_oblique_collision_with_friction_matches_oracle(oracle_lib):
+    """Two spheres meeting with a sideways relative velocity: friction between the
+    grains and normal damping, state 1e-9 after 800 steps; friction takes
+    tangential momentum out of the relative motion."""
+    tang = {}
+    for mu in (0.0, 0.5):
+        wl = I.two_spheres(radius_cells=5, speed=5.0, gap=0.0)
+        nA = int(wl.grain_begin[1])
+        wl.v0[1, nA:] = 3.0
+        wl.params.contact_damping = 5e21
+        wl.params.friction = mu
+        sim = gpu_sim(wl)
+        ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+        for _ in range(4):
+            sim.step(200)
+            ora.step(200)
+        assert_state_close(sim, ora, what=f"mu={mu}")
+        v = ora.state()["v"]
+        tang[mu] = v[1, nA:].mean() - v[1, :nA].mean()
+    assert tang[0.5] < tang[0.0]

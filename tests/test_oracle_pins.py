@@ -419,3 +419,112 @@ def test_wall_damping_uses_the_wall_rate(oracle_lib):
     F2 = force(2e21, I.WALL_FIXED, -2.0)
     assert F1[2] > Ff[2]
     assert (F2[2] - Ff[2]) == pytest.approx(2.0 * (F1[2] - Ff[2]), rel=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# stick-slip friction (Sec. 3.3) on a wall and between grains
+# ---------------------------------------------------------------------------
+
+def _node_on_floor(h, dt, d, gravity=(0.0, 0.0, 0.0), v=(0.0, 0.0, 0.0), mu=0.0, beta=0.0):
+    off = np.zeros((3, 1), dtype=np.int64)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, dt)
+    params.gravity, params.friction, params.contact_damping = gravity, mu, beta
+    floor = I.Wall(normal=(0.0, 0.0, 1.0), offset=-d, mode=I.WALL_FIXED, area=1.0)
+    return I.assemble("node", [(ijk, origin, h, 0)], [I.SAND], params, [floor], [], 1,
+                      v0=np.array(v, dtype=float).reshape(3, 1))
+
+
+def _floor_setup(oracle_lib, h=1e-4, dt=1e-9):
+    """Depth 0.9 R_c on a floor and the weight g_n that the wall law holds there."""
+    Rc = I.default_params(h, dt).contact_radius
+    d = 0.9 * Rc
+    gn = oracle_lib.Oracle(_node_on_floor(h, dt, d)).state()["F"][2, 0] / I.SAND.density
+    return h, dt, d, gn
+
+
+def test_friction_sliding_block_stops_at_the_coulomb_distance(oracle_lib):
+    """A node resting on a floor under its weight, launched sideways at v0, slides
+    with constant deceleration mu g_n and stops after v0^2 / (2 mu g_n), then stays
+    (Coulomb's block); the wall takes the node's momentum."""
+    h, dt, d, gn = _floor_setup(oracle_lib)
+    mu = 0.4
+    v0 = 2000 * dt * mu * gn  # stops after 2000 steps
+    o = oracle_lib.Oracle(_node_on_floor(h, dt, d, (0.0, 0.0, -gn), (v0, 0.0, 0.0), mu))
+    o.step(1000)
+    s = o.state()
+    assert s["v"][0, 0] == pytest.approx(v0 - mu * gn * 1000 * dt, rel=1e-9)
+    assert s["v"][1, 0] == 0.0 and abs(s["v"][2, 0]) < 1e-9 * v0
+    o.step(1500)
+    s = o.state()
+    assert abs(s["v"][0, 0]) <= mu * gn * dt  # at rest within one step's threshold speed
+    assert s["u"][0, 0] == pytest.approx(v0 * v0 / (2 * mu * gn), rel=1e-6)
+    # momentum taken by the wall: rho V v0, up to half a step of deceleration
+    imp = o.wall_impulse()
+    assert imp[0, 0] == pytest.approx(I.SAND.density * h ** 3 * v0, rel=1e-3)
+    assert imp[0, 1] == 0.0
+    # without friction the node keeps its speed
+    o = oracle_lib.Oracle(_node_on_floor(h, dt, d, (0.0, 0.0, -gn), (v0, 0.0, 0.0), 0.0))
+    o.step(100)
+    assert o.state()["v"][0, 0] == v0
+
+
+@pytest.mark.parametrize("ratio", [0.5, 3.0])
+def test_friction_on_an_incline(oracle_lib, ratio):
+    """Tangential gravity g_t = ratio mu g_n.  Below the friction angle the node
+    creeps at the regularised law's speed g_t dt (stick force (rho/dt) |w_t| equal
+    to the pull); above it the node accelerates at g_t - mu g_n."""
+    h, dt, d, gn = _floor_setup(oracle_lib)
+    mu = 0.4
+    gt = ratio * mu * gn
+    o = oracle_lib.Oracle(_node_on_floor(h, dt, d, (gt, 0.0, -gn), mu=mu))
+    n = 1000
+    o.step(n)
+    vx = o.state()["v"][0, 0]
+    if ratio < 1.0:
+        assert vx == pytest.approx(gt * dt, rel=1e-9)
+    else:
+        assert vx == pytest.approx((gt - mu * gn) * n * dt, rel=1e-3)
+
+
+def _pair(h, dt, gap, v_rel, mu, beta=0.0, approach=0.0):
+    """Two one-node grains gap apart along x; relative velocity v_rel along y and
+    closing speed `approach` along x, split evenly."""
+    off = np.zeros((3, 1), dtype=np.int64)
+    blocks = []
+    for x0 in (0.0, gap):
+        ijk, origin = I.grain_block(off, np.array([x0, 0.0, 0.0]), h)
+        blocks.append((ijk, origin, h, 0))
+    params = I.default_params(h, dt)
+    params.friction, params.contact_damping = mu, beta
+    v0 = np.zeros((3, 2))
+    v0[1, 0], v0[1, 1] = 0.5 * v_rel, -0.5 * v_rel
+    v0[0, 0], v0[0, 1] = 0.5 * approach, -0.5 * approach
+    return I.assemble("pair", blocks, [I.SAND], params, [], [], 1, v0=v0)
+
+
+def test_contact_friction_slip_stick_and_momentum(oracle_lib):
+    """Between grains: slip friction is mu times the repulsive force (not the
+    damping) and opposes the relative tangential velocity; stick friction is
+    -(rho/dt) w_t; equal and opposite forces conserve momentum."""
+    h, dt = 1e-4, 1e-9
+    Rc = 0.95 * h
+    gap = 0.6 * Rc
+    F_rep = oracle_lib.Oracle(_pair(h, dt, gap, 0.0, 0.0)).state()["F"]
+    mu = 0.3
+    F = oracle_lib.Oracle(_pair(h, dt, gap, 2.0, mu, beta=1e21, approach=1.5)).state()["F"]
+    assert F[1, 0] == pytest.approx(-mu * abs(F_rep[0, 0]), rel=1e-13)
+    assert F[1, 1] == pytest.approx(mu * abs(F_rep[0, 1]), rel=1e-13)
+    assert abs(F[0, 0]) > abs(F_rep[0, 0])  # the approach is damped along the normal
+    # stick: below the threshold speed mu |f_r| dt / rho
+    vthr = mu * abs(F_rep[0, 0]) * dt / I.SAND.density
+    F = oracle_lib.Oracle(_pair(h, dt, gap, 0.5 * vthr, mu)).state()["F"]
+    assert F[1, 0] == pytest.approx(-I.SAND.density * 0.5 * vthr / dt, rel=1e-12)
+    # momentum of the pair stays zero while friction and repulsion act
+    o = oracle_lib.Oracle(_pair(h, dt, gap, 2.0, mu))
+    p0 = I.SAND.density * h ** 3 * 1.0
+    for _ in range(20):
+        o.step(10)
+        v = o.state()["v"]
+        assert np.all(np.abs(v[:, 0] + v[:, 1]) <= 1e-12 * p0 / (I.SAND.density * h ** 3))
+    assert v[1, 0] - v[1, 1] < 2.0  # the relative sliding slowed down
