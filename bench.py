@@ -91,6 +91,8 @@ def main():
     ap.add_argument("--cpu-budget", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--bond-path", choices=["auto", "slices", "tiles"], default="auto",
+                    help="bond loop: LDS tiles where the mesh allows (auto), or force one")
     ap.add_argument("--surrogate", action="store_true",
                     help="also run the representative-volume surrogate pipeline (64 simulated "
                          "paths, training, held-out error, inference speed; several minutes)")
@@ -112,6 +114,14 @@ def main():
     sim = pd.Sim(wl)
     torch.cuda.synchronize()
     build_s = time.perf_counter() - t0
+    bond_path = pd.BONDS_SLICES
+    if args.bond_path in ("auto", "tiles"):
+        try:
+            sim.set_launch(bond_path=pd.BONDS_TILES)
+            bond_path = pd.BONDS_TILES
+        except pd.PDError:
+            if args.bond_path == "tiles":
+                raise
     info = sim.info()
     nnz, N = info["nnz"], info["n_nodes"]
     print(f"[bench] {args.workload}: {N} nodes, {nnz} bonds, padded {info['padded']}, "
@@ -175,14 +185,16 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "nodes": N, "bonds": nnz,
-                   "step_loop": "hip graph replay", "direct_launch_ms_per_step": direct_ms / args.steps,
+                   "step_loop": "hip graph replay", "bond_path": pd.BOND_PATH_NAMES[bond_path],
+                   "direct_launch_ms_per_step": direct_ms / args.steps,
                    "padded_slots": info["padded"], "dt": wl.params.dt,
                    "horizon_factor": wl.params.horizon_factor,
                    "rebuild_every": wl.params.rebuild_every, "walls": len(wl.walls),
                    "build_s": round(build_s, 3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step<MODE_STEP>", "avg_launch_us": avg_kernel_s * 1e6,
+                     "kernel": "k_step_tile" if bond_path == pd.BONDS_TILES else "k_step<MODE_STEP>",
+                     "avg_launch_us": avg_kernel_s * 1e6,
                      "launches": launches, "algorithmic_bytes_per_launch": bytes_launch,
                      "kernel_bond_updates_per_s": nnz / avg_kernel_s},
     }

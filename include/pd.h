@@ -236,13 +236,31 @@ pd_status pd_info(pd_ctx* ctx, int64_t* out5);
    (GRAPH and DIRECT; the others use 4).  xcd_remap: 1 maps consecutive
    workgroups to contiguous slice ranges per XCD, 0 keeps dispatch order.
    persistent_blocks: workgroups of the persistent launch, 0 = as many as can be
-   resident.  Setting a configuration drops the captured graph. */
+   resident.
+   bond_path: how the bond sum (Sec. 3.1) reads its neighbours.
+     PD_BONDS_SLICES  sliced-ELL rows of column words, neighbour u gathered from
+                      HBM (default; every loop);
+     PD_BONDS_TILES   workgroups over 4 x 4 x 16-cell tiles of each grain's
+                      lattice with u of the tile and a 3-cell halo staged in LDS,
+                      the bond memory in per-node class masks.  Needs the bonds
+                      built, horizon factor 3 and every grain's nodes in
+                      lexicographic lattice order along some axis order
+                      (PD_ERR_UNSUPPORTED otherwise), and the GRAPH or DIRECT
+                      loop.  Node state is bitwise the same as with slices (the
+                      same per-bond arithmetic in the same order); wall
+                      reactions are reduced per tile wavefront and agree to
+                      rounding, so with servo walls the node state does too.
+   Switching the bond path hands the bond memory over; pd_get, pd_get_state
+   and pd_set_state see the same bond state either way.  Setting a
+   configuration drops the captured graph. */
 enum { PD_LOOP_GRAPH = 0, PD_LOOP_DIRECT = 1, PD_LOOP_PERSISTENT = 2, PD_LOOP_PER_GRAIN = 3 };
+enum { PD_BONDS_SLICES = 0, PD_BONDS_TILES = 1 };
 typedef struct {
   int32_t loop;
   int32_t slices_per_block;
   int32_t xcd_remap;
   int32_t persistent_blocks;
+  int32_t bond_path;
 } pd_launch;
 pd_status pd_set_launch(pd_ctx* ctx, const pd_launch* launch);
 pd_status pd_get_launch(pd_ctx* ctx, pd_launch* launch);

@@ -92,11 +92,23 @@ struct pd_ctx {
   std::vector<hipEvent_t> ev_pool;
   size_t ev_used = 0;
   // launch configuration (pd_set_launch) and its per-grain tables
-  pd_launch launch{PD_LOOP_GRAPH, kSlicesPerBlock, 1, 0};
+  pd_launch launch{PD_LOOP_GRAPH, kSlicesPerBlock, 1, 0, PD_BONDS_SLICES};
   std::vector<int64_t> pg_slice_lo, pg_slice_hi, pg_part_base;
   int64_t pg_cols = 0;  // wall-partial columns of the per-grain launches (shared slices twice)
   int64_t partial_cols = 0;  // columns allocated in wall_partial
   uint32_t* barrier = nullptr;  // [2]: arrival count, generation
+  // tiled bond loop (PD_BONDS_TILES): available when the horizon factor is 3
+  // and every grain's nodes are in lexicographic order of some axis order
+  int tile_ok = 0;
+  int64_t n_tiles = 0;
+  int4* tiles = nullptr;
+  TileGrain* tgrain = nullptr;
+  int32_t* tmap = nullptr;
+  StencilC* ttab = nullptr;
+  int16_t* ctob = nullptr;  // [6][n_stencil]: slice-path class -> mask bit per axis order
+  uint32_t* mask = nullptr;  // [kMaskWords][N]
+  std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
+  std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
   // captured step loop of graph_len steps
   int use_graph = 1;
   int64_t graph_len = 0;
@@ -250,6 +262,12 @@ StepArgs step_args(pd_ctx* c) {
   A.dt = c->dt;
   for (int q = 0; q < 3; ++q) A.g[q] = c->g[q];
   A.abs_stretch = (c->flags & PD_FLAG_ABS_STRETCH) ? 1 : 0;
+  A.tiles = c->tiles;
+  A.n_tiles = c->n_tiles;
+  A.tgrain = c->tgrain;
+  A.tmap = c->tmap;
+  A.ttab = c->ttab;
+  A.mask = c->mask;
   return A;
 }
 
@@ -299,7 +317,10 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
   if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
-  if (c->launch.loop == PD_LOOP_PER_GRAIN) {
+  if (c->launch.bond_path == PD_BONDS_TILES) {
+    A.partial_stride = kTS * c->n_tiles;  // one wall-partial column per tile wavefront
+    HIPCHK(c, launch_step_tile(A, c->stream));
+  } else if (c->launch.loop == PD_LOOP_PER_GRAIN) {
     // one launch per grain over the slices that hold its nodes; a slice shared
     // by two grains is visited by both launches, each lane working for its own
     A.partial_stride = c->pg_cols;
@@ -436,6 +457,149 @@ uint32_t crc32_update(uint32_t crc, const void* data, size_t n) {
   crc = ~crc;
   for (size_t i = 0; i < n; ++i) crc = table[(crc ^ p[i]) & 0xff] ^ (crc >> 8);
   return ~crc;
+}
+
+bool any_servo(const pd_ctx* c) {
+  for (const WallDev& w : c->walls_h)
+    if (w.mode == PD_WALL_SERVO) return true;
+  return false;
+}
+
+// The six axis orders (slowest first), as in the tile kernels.
+constexpr int kAxisOrders[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+// Tiles of the bond loop: for every grain an axis order in which its node
+// indices ascend lexicographically (the order of the slice path's sorted rows),
+// its box on those axes, a cell -> node map, the 4 x 4 x 16-cell tiles that hold
+// nodes, the bond table of each (stencil class, axis order) in tile class order
+// and the class masks of the built bonds.  Leaves tile_ok = 0 when some grain
+// has no such order or the horizon factor is not 3.
+pd_status build_tiles(pd_ctx* c) {
+  c->tile_ok = 0;
+  if (c->m != kTileR || c->n_stencil != kTileClasses) return PD_OK;
+  const int64_t N = c->n;
+  const int32_t G = c->n_grains;
+  std::vector<TileGrain> tg((size_t)G);
+  std::vector<int4> tiles;
+  int64_t map_total = 0;
+  std::vector<int> table_of((size_t)6 * c->n_classes, -1);
+  int n_tables = 0;
+  for (int32_t g = 0; g < G; ++g) {
+    const int64_t b = c->grain_begin[(size_t)g], e = c->grain_begin[(size_t)g + 1];
+    int perm = -1;
+    for (int p = 0; p < 6 && perm < 0; ++p) {
+      const int* P = kAxisOrders[p];
+      bool ok = true;
+      int64_t prev = -1;
+      for (int64_t i = b; i < e && ok; ++i) {
+        const int64_t key = ((int64_t)c->ijk_h[P[0] * N + i] << 20) | ((int64_t)c->ijk_h[P[1] * N + i] << 10) |
+                            (int64_t)c->ijk_h[P[2] * N + i];
+        ok = key > prev;
+        prev = key;
+      }
+      if (ok) perm = p;
+    }
+    if (perm < 0) return PD_OK;  // this grain's node order is not a lattice order
+    const int* P = kAxisOrders[perm];
+    int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
+    for (int64_t i = b; i < e; ++i)
+      for (int q = 0; q < 3; ++q) {
+        lo[q] = std::min(lo[q], c->ijk_h[P[q] * N + i]);
+        hi[q] = std::max(hi[q], c->ijk_h[P[q] * N + i]);
+      }
+    if (e == b) lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = 0;
+    TileGrain& T = tg[(size_t)g];
+    T.perm = perm;
+    T.lo_s = lo[0];
+    T.lo_m = lo[1];
+    T.lo_f = lo[2];
+    T.es = hi[0] - lo[0] + 1;
+    T.em = hi[1] - lo[1] + 1;
+    T.ef = hi[2] - lo[2] + 1;
+    T.map_off = map_total;
+    map_total += (int64_t)T.es * T.em * T.ef;
+    const int cls = c->grains_h[(size_t)g].cls;
+    int& tab = table_of[(size_t)perm * c->n_classes + cls];
+    if (tab < 0) tab = n_tables++;
+    T.table = tab;
+    // tiles holding at least one node, in (s, m, f) tile order
+    const int nts = (T.es + kTS - 1) / kTS, ntm = (T.em + kTM - 1) / kTM, ntf = (T.ef + kTF - 1) / kTF;
+    std::vector<uint8_t> used((size_t)nts * ntm * ntf, 0);
+    for (int64_t i = b; i < e; ++i) {
+      const int ts = (c->ijk_h[P[0] * N + i] - lo[0]) / kTS, tm = (c->ijk_h[P[1] * N + i] - lo[1]) / kTM,
+                tf = (c->ijk_h[P[2] * N + i] - lo[2]) / kTF;
+      used[((size_t)ts * ntm + tm) * ntf + tf] = 1;
+    }
+    for (int ts = 0; ts < nts; ++ts)
+      for (int tm = 0; tm < ntm; ++tm)
+        for (int tf = 0; tf < ntf; ++tf)
+          if (used[((size_t)ts * ntm + tm) * ntf + tf]) tiles.push_back(make_int4(g, ts * kTS, tm * kTM, tf * kTF));
+  }
+  // tile class K of axis order p is the offset (ds, dm, df) K-th in lexicographic
+  // order; (dx, dy, dz) puts ds on axis P[0] and so on
+  std::vector<int> cls_of_offset(15 * 15 * 15, -1);
+  for (int k = 0; k < c->n_stencil; ++k)
+    cls_of_offset[(size_t)(((c->sd_h[3 * k] + 7) * 15 + (c->sd_h[3 * k + 1] + 7)) * 15 + (c->sd_h[3 * k + 2] + 7))] = k;
+  std::vector<int16_t> ctob((size_t)6 * c->n_stencil, -1);
+  std::vector<std::vector<int>> btoc(6, std::vector<int>(kTileClasses, -1));
+  for (int p = 0; p < 6; ++p) {
+    const int* P = kAxisOrders[p];
+    int K = 0;
+    for (int a = -kTileR; a <= kTileR; ++a)
+      for (int bb = -kTileR; bb <= kTileR; ++bb)
+        for (int cc = -kTileR; cc <= kTileR; ++cc) {
+          const int d2 = a * a + bb * bb + cc * cc;
+          if (d2 == 0 || d2 > kTileR * kTileR) continue;
+          int d[3];
+          d[P[0]] = a;
+          d[P[1]] = bb;
+          d[P[2]] = cc;
+          const int k = cls_of_offset[(size_t)(((d[0] + 7) * 15 + (d[1] + 7)) * 15 + (d[2] + 7))];
+          if (k < 0) return fail(c, PD_ERR_HIP, "tile stencil: offset missing from the horizon stencil");
+          btoc[(size_t)p][(size_t)K] = k;
+          ctob[(size_t)p * c->n_stencil + k] = (int16_t)K;
+          ++K;
+        }
+  }
+  std::vector<StencilC> ttab((size_t)n_tables * kTileClasses);
+  for (int p = 0; p < 6; ++p)
+    for (int cl = 0; cl < c->n_classes; ++cl) {
+      const int t = table_of[(size_t)p * c->n_classes + cl];
+      if (t < 0) continue;
+      for (int K = 0; K < kTileClasses; ++K)
+        ttab[(size_t)t * kTileClasses + K] =
+            c->stencil_h[(size_t)cl * (c->n_stencil + 1) + btoc[(size_t)p][(size_t)K]];
+    }
+  hipStream_t s = c->stream;
+  c->n_tiles = (int64_t)tiles.size();
+  TRY(alloc_n(c, &c->tiles, std::max<int64_t>(c->n_tiles, 1), "tiles"));
+  TRY(alloc_n(c, &c->tgrain, std::max<int64_t>(G, 1), "tile grains"));
+  TRY(alloc_n(c, &c->tmap, std::max<int64_t>(map_total, 1), "tile cell map"));
+  TRY(alloc_n(c, &c->ttab, std::max<int64_t>((int64_t)ttab.size(), 1), "tile bond tables"));
+  TRY(alloc_n(c, &c->ctob, std::max<int64_t>((int64_t)ctob.size(), 1), "class to mask bit"));
+  TRY(alloc_n(c, &c->mask, std::max<int64_t>((int64_t)kMaskWords * N, 1), "class masks"));
+  if (c->n_tiles)
+    HIPCHK(c, hipMemcpyAsync(c->tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s));
+  if (G) HIPCHK(c, hipMemcpyAsync(c->tgrain, tg.data(), sizeof(TileGrain) * G, hipMemcpyHostToDevice, s));
+  if (!ttab.empty())
+    HIPCHK(c, hipMemcpyAsync(c->ttab, ttab.data(), sizeof(StencilC) * ttab.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->ctob, ctob.data(), sizeof(int16_t) * ctob.size(), hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_fill_i32(c->tmap, -1, map_total, s));
+  StepArgs A = step_args(c);
+  HIPCHK(c, launch_tile_map_fill(A, s));
+  HIPCHK(c, launch_cols_to_mask(A, c->ctob, c->colOrig, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  c->tile_ok = 1;
+  return PD_OK;
+}
+
+// the tile path keeps the bond memory in class masks; bring the column words
+// up to date before anything reads them
+pd_status sync_columns(pd_ctx* c) {
+  if (c->launch.bond_path != PD_BONDS_TILES) return PD_OK;
+  StepArgs A = step_args(c);
+  HIPCHK(c, launch_mask_to_cols(A, c->ctob, c->colOrig, c->stream));
+  return PD_OK;
 }
 
 }  // namespace
@@ -618,6 +782,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     // zero-force class: xi = 0, x = 0, c V / |xi| = 0 (broken bonds, padding)
     st.push_back(StencilC{0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 1.0});
   }
+  c->stencil_h = st;
+  c->sd_h = sd;
   int sbits = 0;
   while ((1 << sbits) < c->n_stencil + 1) ++sbits;
   c->node_bits = 32 - sbits;
@@ -891,7 +1057,8 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
     c->pg_part_base[(size_t)g] = c->pg_cols;
     c->pg_cols += c->pg_slice_hi[(size_t)g] - c->pg_slice_lo[(size_t)g];
   }
-  c->partial_cols = std::max<int64_t>(std::max<int64_t>(c->nslices, c->pg_cols), 1);
+  TRY(build_tiles(c));
+  c->partial_cols = std::max<int64_t>(std::max<int64_t>(std::max<int64_t>(c->nslices, c->pg_cols), kTS * c->n_tiles), 1);
   TRY(alloc_n(c, &c->wall_partial, c->partial_cols * 3 * std::max(c->n_walls, 1), "wall partials"));
   TRY(alloc_n(c, &c->wall_chunk, ((c->partial_cols + kChunk - 1) / kChunk) * 3 * std::max(c->n_walls, 1),
               "wall chunk sums"));
@@ -948,6 +1115,16 @@ pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
     return fail(c, PD_ERR_INVALID, "slices_per_block must be 1, 2, 4 or 8");
   if (l->xcd_remap != 0 && l->xcd_remap != 1) return fail(c, PD_ERR_INVALID, "xcd_remap must be 0 or 1");
   if (l->persistent_blocks < 0) return fail(c, PD_ERR_INVALID, "persistent_blocks must be >= 0");
+  if (l->bond_path != PD_BONDS_SLICES && l->bond_path != PD_BONDS_TILES)
+    return fail(c, PD_ERR_INVALID, "unknown bond path %d", l->bond_path);
+  if (l->bond_path == PD_BONDS_TILES) {
+    if (!c->built) return fail(c, PD_ERR_STATE, "the tiled bond loop needs the bonds built first");
+    if (!c->tile_ok)
+      return fail(c, PD_ERR_UNSUPPORTED,
+                  "the tiled bond loop needs horizon factor 3 and every grain's nodes in lattice order");
+    if (l->loop != PD_LOOP_GRAPH && l->loop != PD_LOOP_DIRECT)
+      return fail(c, PD_ERR_INVALID, "the tiled bond loop runs with the graph or direct step loop only");
+  }
   if (c->graph_exec) {
     HIPCHK(c, hipStreamSynchronize(c->stream));
     HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
@@ -956,6 +1133,13 @@ pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
   if (c->graph) {
     HIPCHK(c, hipGraphDestroy(c->graph));
     c->graph = nullptr;
+  }
+  if (c->built && l->bond_path != c->launch.bond_path) {
+    // hand the bond memory over: column words <-> class masks
+    StepArgs A = step_args(c);
+    if (l->bond_path == PD_BONDS_TILES) HIPCHK(c, launch_cols_to_mask(A, c->ctob, c->colOrig, c->stream));
+    else HIPCHK(c, launch_mask_to_cols(A, c->ctob, c->colOrig, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
   }
   c->launch = *l;
   return PD_OK;
@@ -1089,6 +1273,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       return deliver(host.data());
     }
     case PD_BOND_ROWPTR: case PD_BOND_COL: case PD_BOND_BROKEN: {
+      TRY(sync_columns(c));
       std::vector<int32_t> rl((size_t)N);
       std::vector<uint32_t> col((size_t)c->padded);
       const uint32_t node_mask = (1u << c->node_bits) - 1u;
@@ -1146,6 +1331,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       return deliver(host.data());
     }
     case PD_ENERGY: {
+      TRY(sync_columns(c));
       const int32_t nb = (int32_t)((N + kBlock - 1) / kBlock);
       if (!c->energy_partial) {
         TRY(alloc_n(c, &c->energy_partial, 4 * (int64_t)std::max(nb, 1), "energy partials"));
@@ -1214,6 +1400,7 @@ pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
   TRY(grab(c->u4[c->cur ^ 1], 32 * N));
   TRY(grab(c->v, 24 * N));
   TRY(grab(c->a, 24 * N));
+  TRY(sync_columns(c));
   TRY(grab(c->colE, 4 * words));
   TRY(grab(c->intact, 4 * N));
   TRY(grab(c->u_build, 24 * N));
@@ -1265,6 +1452,10 @@ pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
   if (nvh) {
     TRY(put(c->vh[c->cur], 32 * N));
     TRY(put(c->vh[c->cur ^ 1], 32 * N));
+  }
+  if (c->launch.bond_path == PD_BONDS_TILES) {
+    StepArgs A = step_args(c);
+    HIPCHK(c, launch_cols_to_mask(A, c->ctob, c->colOrig, s));
   }
   c->step = hdr[4];
   HIPCHK(c, hipMemcpyAsync(c->step_d, &c->step, 8, hipMemcpyHostToDevice, s));

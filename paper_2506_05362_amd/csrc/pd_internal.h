@@ -54,6 +54,29 @@ struct StencilC {
 constexpr int kMaxLdsTables = 48 * 1024;  // bytes of stencil tables a workgroup may stage
 constexpr int kMaxStencil = 1024;
 
+// ---- tiled bond loop (horizon factor 3): a workgroup owns a tile of
+// kTS x kTM x kTF lattice cells of one grain, in the grain's node-ordering axes
+// (s slowest, m, f fastest), and stages u of the tile plus a kTileR-cell halo in
+// LDS; the bond memory is a per-node bit mask over the 122 horizon classes in
+// lexicographic (ds, dm, df) order, the order of ascending neighbour index.
+constexpr int kTileR = 3;
+#ifndef PD_TILE_LAYERS
+#define PD_TILE_LAYERS 8
+#endif
+constexpr int kTS = PD_TILE_LAYERS, kTM = 4, kTF = 16;  // one s-layer of 4 x 16 cells per wavefront
+constexpr int kHS = kTS + 2 * kTileR, kHM = kTM + 2 * kTileR, kHF = kTF + 2 * kTileR;
+constexpr int kHalo = kHS * kHM * kHF;      // 3080 cells, 73920 B of FP64 planes (8 layers)
+constexpr int kTileClasses = 122;           // 0 < |d|^2 <= 9
+constexpr int kMaskWords = 4;
+
+struct TileGrain {
+  int64_t map_off;     // cell (s, m, f) of the grain's box -> node at tmap[map_off + (s em + m) ef + f]
+  int32_t es, em, ef;  // box extents in the node-ordering axes
+  int32_t table;       // bond table: ttab[table * kTileClasses + class] (slice-path StencilC rows)
+  int32_t perm;        // node-ordering axes (slowest first): index into the six axis orders
+  int32_t lo_s, lo_m, lo_f;  // lattice index of the box corner on those axes
+};
+
 struct WallDev {
   double n[3];
   double off0;      // offset at t = 0
@@ -134,6 +157,15 @@ struct StepArgs {
   int64_t node_lo, node_hi;
   int64_t partial_base, partial_stride;
   int32_t xcd_remap;     // 1: workgroup -> XCD-contiguous slice ranges
+  // tiled bond loop (launch_step_tile): tile records (grain, s0, m0, f0), the
+  // per-grain boxes and cell maps, bond tables and per-node class masks
+  // ([kMaskWords][n]); the tile kernel's wall partials use column kTS t + wave
+  const int4* tiles;
+  int64_t n_tiles;
+  const TileGrain* tgrain;
+  const int32_t* tmap;
+  const StencilC* ttab;
+  uint32_t* mask;
 };
 
 // grid barrier state of the persistent step kernel (zeroed before each launch)
@@ -225,5 +257,15 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
 int32_t step_grid_blocks(int64_t nslices);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// tiled bond loop: MODE_STEP over all tiles
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s);
+// per-node cell map of the tile grains: tmap[map_off + (s em + m) ef + f] = node
+hipError_t launch_tile_map_fill(const StepArgs& a, hipStream_t s);
+// bond state between the slice path's column words and the tile path's class
+// masks; ctob[perm][slice class] = mask bit (or -1)
+hipError_t launch_cols_to_mask(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig,
+                               hipStream_t s);
+hipError_t launch_mask_to_cols(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig,
+                               hipStream_t s);
 
 }  // namespace pdk

@@ -20,6 +20,7 @@
 // results are bitwise reproducible run to run.
 
 #include <algorithm>
+#include <utility>
 
 #include "pd_internal.h"
 
@@ -239,29 +240,29 @@ __device__ __forceinline__ double wave_sum(double x) {
 #endif
 
 // 1 - (1 + x)^(-1/2) = x * sum_k (-1)^k a_{k+1} x^k with a_k = C(2k, k) / 4^k.
-// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange;
-// five terms suffice for |x| <= kPolyTiny (first omitted term < 1.5e-19 relative).
+// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange.
 constexpr double kPolyRange = 0.02;
-constexpr double kPolyTiny = 2e-4;
-__device__ __forceinline__ double one_minus_rsqrt1p_over_x_5(double x) {
-  double p = 63.0 / 256.0;
-  p = fma(p, x, -35.0 / 128.0);
-  p = fma(p, x, 5.0 / 16.0);
-  p = fma(p, x, -3.0 / 8.0);
+// The ten-term series.  Its nine non-trivial coefficients may be held in
+// registers (Poly10), with the same arithmetic either way: as literals the
+// compiler rebuilds each 64-bit constant with two moves per use.
+struct Poly10 {
+  double c[9];
+};
+constexpr Poly10 kPoly10{{-46189.0 / 262144.0, 12155.0 / 65536.0, -6435.0 / 32768.0, 429.0 / 2048.0,
+                          -231.0 / 1024.0, 63.0 / 256.0, -35.0 / 128.0, 5.0 / 16.0, -3.0 / 8.0}};
+__device__ __forceinline__ Poly10 poly10_in_registers() {
+  Poly10 P = kPoly10;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(P.c[k]));
+  return P;
+}
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x, const Poly10& P) {
+  double p = fma(P.c[0], x, P.c[1]);
+#pragma unroll
+  for (int k = 2; k < 9; ++k) p = fma(p, x, P.c[k]);
   return fma(p, x, 0.5);
 }
-__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) {
-  double p = -46189.0 / 262144.0;
-  p = fma(p, x, 12155.0 / 65536.0);
-  p = fma(p, x, -6435.0 / 32768.0);
-  p = fma(p, x, 429.0 / 2048.0);
-  p = fma(p, x, -231.0 / 1024.0);
-  p = fma(p, x, 63.0 / 256.0);
-  p = fma(p, x, -35.0 / 128.0);
-  p = fma(p, x, 5.0 / 16.0);
-  p = fma(p, x, -3.0 / 8.0);
-  return fma(p, x, 0.5);
-}
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) { return one_minus_rsqrt1p_over_x(x, kPoly10); }
 
 // The fused step of one workgroup: SPB slices (one wavefront each) starting at
 // slice slice_base + SPB * blk.  s_st holds the stencil tables in LDS.
@@ -279,103 +280,34 @@ __device__ __forceinline__ void stick_slip(double mu_fr, double rho, double dt, 
   fz = fma(-k, tz, fz);
 }
 
-template <int MODE, bool ABS, int SPB>
-__device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_st, int64_t blk) {
-  const int tid = threadIdx.x, lane = tid & 63;
-  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
-  const int64_t slice = A.slice_base + blk * SPB + wid;
-  const bool slice_ok = slice < A.slice_end;
-  const int64_t i = slice * kWave + lane;
-  const bool valid = slice_ok && i >= A.node_lo && i < A.node_hi;
+// Everything after the bond sum for the node of this lane: contact with other
+// grains, damping and friction (Secs. 3.2-3.4), rigid walls (Sec. 4.1) with the
+// wavefront's reaction partial in wall_partial column col (written when col_ok),
+// and velocity Verlet (Sec. 6.2).  Every lane of the wavefront takes part (the
+// wall partials are wavefront sums); lanes without a node pass valid = false.
+// The node's velocity and previous acceleration, read by the Verlet update.
+struct NodeVA {
+  double vx, vy, vz, ax, ay, az;
+};
+__device__ __forceinline__ NodeVA load_va(const StepArgs& A, int64_t i, bool valid) {
+  NodeVA r{0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  if (valid) {
+    r.vx = A.v[i];
+    r.vy = A.v[A.n + i];
+    r.vz = A.v[2 * A.n + i];
+    r.ax = A.a[i];
+    r.ay = A.a[A.n + i];
+    r.az = A.a[2 * A.n + i];
+  }
+  return r;
+}
 
-  double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (valid) ui = A.ucur[i];
-  const int pi = packed_ijk(ui.w);
-  const int gi = valid ? packed_grain(ui.w) : 0;
-  const GrainC* G = A.grains + gi;
+template <int MODE>
+__device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool valid, const double4& ui,
+                                          const GrainC* G, int ix, int iy, int iz, double fx, double fy,
+                                          double fz, int nbroke, bool col_ok, int64_t col, const NodeVA& va) {
+  const int lane = threadIdx.x & 63;
   const double h = G->h;
-  const double abs_ratio = G->abs_ratio;
-  const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
-  const uint32_t node_mask = (1u << A.node_bits) - 1u;
-  const int node_bits = A.node_bits;
-
-  double fx = 0.0, fy = 0.0, fz = 0.0;
-  int nbroke = 0;
-
-  // ---- peridynamic bonds with bond memory ----
-  // Slice width W is a multiple of kUnroll: the column words of kUnroll entries
-  // are loaded one iteration ahead, then their kUnroll neighbour gathers, so
-  // each lane keeps several memory requests in flight.  Broken bonds and
-  // padding carry the zero-force class and point at the node itself, so every
-  // entry is evaluated the same way.
-  //
-  // Bond law (Sec. 3.1): the force on i is c s V_j y/|y|, y = xi + eta, and
-  //   c V s / |y| = (c V / |xi|) g,   g = 1 - |xi|/|y| = 1 - (1 + x)^(-1/2),
-  //   x = (|y|^2 - |xi|^2) / |xi|^2,   |y|^2 - |xi|^2 = eta . (2 xi + eta).
-  // g comes from its power series when |x| <= kPolyRange (five terms when every
-  // lane of the wavefront has |x| <= kPolyTiny; no square root or
-  // division), else from g = (|y|^2 - |xi|^2) / (|y| (|y| + |xi|)); neither
-  // form subtracts nearly equal numbers.
-  int64_t off = 0;
-  int W = 0;
-  if (slice_ok) {
-    off = A.slice_off[slice];
-    W = (int)((A.slice_off[slice + 1] - off) >> 6);
-  }
-  uint32_t* cp = A.colE + off + lane;
-  const char* ubase = reinterpret_cast<const char*>(A.ucur);
-  const char* tbase = reinterpret_cast<const char*>(s_st) +
-                      (uint32_t)G->cls * (uint32_t)(A.n_stencil + 1) * (uint32_t)sizeof(StencilC);
-  const uint32_t mine = (uint32_t)(valid ? i : 0) | A.sentinel_hi;
-  uint32_t cn[kUnroll];
-#pragma unroll
-  for (int u = 0; u < kUnroll; ++u) cn[u] = W > 0 ? cp[u * kWave] : mine;
-  for (int k = 0; k < W; k += kUnroll) {
-    uint32_t cw[kUnroll];
-    double4 uj[kUnroll];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) cw[u] = cn[u];
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u)
-      uj[u] = *reinterpret_cast<const double4*>(ubase + ((cw[u] & node_mask) << 5));
-    if (k + kUnroll < W) {
-#pragma unroll
-      for (int u = 0; u < kUnroll; ++u) cn[u] = cp[(k + kUnroll + u) * kWave];
-    }
-#pragma unroll
-    for (int u = 0; u < kUnroll; ++u) {
-      const StencilC& S =
-          *reinterpret_cast<const StencilC*>(tbase + (cw[u] >> node_bits) * (uint32_t)sizeof(StencilC));
-      const double ex = uj[u].x - ui.x, ey = uj[u].y - ui.y, ez = uj[u].z - ui.z;
-      const double yx = S.hx + ex, yy = S.hy + ey, yz = S.hz + ez;  // y = xi + eta
-      // |y|^2 - |xi|^2 = eta . (2 xi + eta)
-      const double d = fma(ex, yx + S.hx, fma(ey, yy + S.hy, ez * (yz + S.hz)));
-      // s > s0  <=>  |y|^2 - |xi|^2 > |xi|^2 ((1 + s0)^2 - 1)
-      bool over = d > S.thr_d;
-      if (ABS) over = over || d < -abs_ratio * S.thr_d;
-      const double x = d * S.inv_l0sq;
-      double g;
-      if (__all(fabs(x) <= kPolyTiny)) {  // wave-uniform: the short series for every lane
-        g = x * one_minus_rsqrt1p_over_x_5(x);
-      } else {
-        g = x * one_minus_rsqrt1p_over_x(x);
-        if (!(fabs(x) <= kPolyRange)) {
-          const double lsq = S.l0sq + d;
-          const double l = lsq * rsqrt_full(lsq);
-          g = d * rcp_full(fma(l, S.l0, lsq));
-        }
-      }
-      const double coef = over ? 0.0 : S.civ * g;
-      fx = fma(coef, yx, fx);
-      fy = fma(coef, yy, fy);
-      fz = fma(coef, yz, fz);
-      if (MODE != MODE_FORCE_ONLY && over && valid) {
-        cp[(k + u) * kWave] = mine;  // the bond stays broken from now on
-        ++nbroke;
-      }
-    }
-  }
-
   // mid-step velocity of this node for the normal damping (Sec. 3.4) and
   // stick-slip friction (Sec. 3.3) laws
   const bool damp = A.beta > 0.0, fric = A.mu > 0.0, vdep = damp || fric;
@@ -483,8 +415,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
       }
       // one partial per slice (wavefront), component-major: the finalize sums
       // them in slice order, whatever the workgroup size or launch split
-      if (lane == 0 && slice_ok) {
-        const int64_t col = A.partial_base + (slice - A.slice_base);
+      if (lane == 0 && col_ok) {
         A.wall_partial[(int64_t)(3 * w) * A.partial_stride + col] = r0;
         A.wall_partial[(int64_t)(3 * w + 1) * A.partial_stride + col] = r1;
         A.wall_partial[(int64_t)(3 * w + 2) * A.partial_stride + col] = r2;
@@ -505,11 +436,11 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
       const double anx = fixed ? 0.0 : fx / rho + A.g[0];
       const double any = fixed ? 0.0 : fy / rho + A.g[1];
       const double anz = fixed ? 0.0 : fz / rho + A.g[2];
-      double vx = A.v[i], vy = A.v[A.n + i], vz = A.v[2 * A.n + i];
+      double vx = va.vx, vy = va.vy, vz = va.vz;
       if (MODE == MODE_STEP) {
-        vx = fixed ? 0.0 : fma(hdt, A.a[i] + anx, vx);
-        vy = fixed ? 0.0 : fma(hdt, A.a[A.n + i] + any, vy);
-        vz = fixed ? 0.0 : fma(hdt, A.a[2 * A.n + i] + anz, vz);
+        vx = fixed ? 0.0 : fma(hdt, va.ax + anx, vx);
+        vy = fixed ? 0.0 : fma(hdt, va.ay + any, vy);
+        vz = fixed ? 0.0 : fma(hdt, va.az + anz, vz);
       } else if (fixed) {
         vx = vy = vz = 0.0;
       }
@@ -535,7 +466,101 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
       if (nbroke) A.intact[i] -= nbroke;
     }
   }
+}
 
+template <int MODE, bool ABS, int SPB>
+__device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_st, int64_t blk) {
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);  // wave-uniform
+  const int64_t slice = A.slice_base + blk * SPB + wid;
+  const bool slice_ok = slice < A.slice_end;
+  const int64_t i = slice * kWave + lane;
+  const bool valid = slice_ok && i >= A.node_lo && i < A.node_hi;
+
+  double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
+  if (valid) ui = A.ucur[i];
+  const int pi = packed_ijk(ui.w);
+  const int gi = valid ? packed_grain(ui.w) : 0;
+  const GrainC* G = A.grains + gi;
+  const double abs_ratio = G->abs_ratio;
+  const int ix = unpack_x(pi), iy = unpack_y(pi), iz = unpack_z(pi);
+  const uint32_t node_mask = (1u << A.node_bits) - 1u;
+  const int node_bits = A.node_bits;
+
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  int nbroke = 0;
+
+  // ---- peridynamic bonds with bond memory ----
+  // Slice width W is a multiple of kUnroll: the column words of kUnroll entries
+  // are loaded one iteration ahead, then their kUnroll neighbour gathers, so
+  // each lane keeps several memory requests in flight.  Broken bonds and
+  // padding carry the zero-force class and point at the node itself, so every
+  // entry is evaluated the same way.
+  //
+  // Bond law (Sec. 3.1): the force on i is c s V_j y/|y|, y = xi + eta, and
+  //   c V s / |y| = (c V / |xi|) g,   g = 1 - |xi|/|y| = 1 - (1 + x)^(-1/2),
+  //   x = (|y|^2 - |xi|^2) / |xi|^2,   |y|^2 - |xi|^2 = eta . (2 xi + eta).
+  // g comes from its ten-term power series when |x| <= kPolyRange (no square
+  // root or division), else from g = (|y|^2 - |xi|^2) / (|y| (|y| + |xi|));
+  // neither form subtracts nearly equal numbers.  The choice is made per lane,
+  // so any grouping of bonds (the tiled path) computes the same values.
+  int64_t off = 0;
+  int W = 0;
+  if (slice_ok) {
+    off = A.slice_off[slice];
+    W = (int)((A.slice_off[slice + 1] - off) >> 6);
+  }
+  uint32_t* cp = A.colE + off + lane;
+  const char* ubase = reinterpret_cast<const char*>(A.ucur);
+  const char* tbase = reinterpret_cast<const char*>(s_st) +
+                      (uint32_t)G->cls * (uint32_t)(A.n_stencil + 1) * (uint32_t)sizeof(StencilC);
+  const uint32_t mine = (uint32_t)(valid ? i : 0) | A.sentinel_hi;
+  uint32_t cn[kUnroll];
+#pragma unroll
+  for (int u = 0; u < kUnroll; ++u) cn[u] = W > 0 ? cp[u * kWave] : mine;
+  for (int k = 0; k < W; k += kUnroll) {
+    uint32_t cw[kUnroll];
+    double4 uj[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) cw[u] = cn[u];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u)
+      uj[u] = *reinterpret_cast<const double4*>(ubase + ((cw[u] & node_mask) << 5));
+    if (k + kUnroll < W) {
+#pragma unroll
+      for (int u = 0; u < kUnroll; ++u) cn[u] = cp[(k + kUnroll + u) * kWave];
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const StencilC& S =
+          *reinterpret_cast<const StencilC*>(tbase + (cw[u] >> node_bits) * (uint32_t)sizeof(StencilC));
+      const double ex = uj[u].x - ui.x, ey = uj[u].y - ui.y, ez = uj[u].z - ui.z;
+      const double yx = S.hx + ex, yy = S.hy + ey, yz = S.hz + ez;  // y = xi + eta
+      // |y|^2 - |xi|^2 = eta . (2 xi + eta)
+      const double d = fma(ex, yx + S.hx, fma(ey, yy + S.hy, ez * (yz + S.hz)));
+      // s > s0  <=>  |y|^2 - |xi|^2 > |xi|^2 ((1 + s0)^2 - 1)
+      bool over = d > S.thr_d;
+      if (ABS) over = over || d < -abs_ratio * S.thr_d;
+      const double x = d * S.inv_l0sq;
+      double g = x * one_minus_rsqrt1p_over_x(x);
+      if (!(fabs(x) <= kPolyRange)) {
+        const double lsq = S.l0sq + d;
+        const double l = lsq * rsqrt_full(lsq);
+        g = d * rcp_full(fma(l, S.l0, lsq));
+      }
+      const double coef = over ? 0.0 : S.civ * g;
+      fx = fma(coef, yx, fx);
+      fy = fma(coef, yy, fy);
+      fz = fma(coef, yz, fz);
+      if (MODE != MODE_FORCE_ONLY && over && valid) {
+        cp[(k + u) * kWave] = mine;  // the bond stays broken from now on
+        ++nbroke;
+      }
+    }
+  }
+
+  node_tail<MODE>(A, i, valid, ui, G, ix, iy, iz, fx, fy, fz, nbroke, slice_ok,
+                  A.partial_base + (slice - A.slice_base), load_va(A, i, valid));
 }
 
 __device__ __forceinline__ void stage_stencil(const StepArgs& A, StencilC* s_st) {
@@ -551,6 +576,270 @@ void k_step(StepArgs A) {
   stage_stencil(A, s_st);
   const int64_t blk = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   step_body<MODE, ABS, SPB>(A, s_st, blk);
+}
+
+// ---------------------------------------------------------------------------
+// tiled bond loop: u of a tile and its halo in LDS, bond memory in class masks
+// ---------------------------------------------------------------------------
+
+// Offset, in the halo box, of the neighbour in horizon class k (lexicographic
+// (ds, dm, df) with 0 < |d|^2 <= 9) from the lane's corner cell (its own cell
+// minus kTileR on each axis); -1 past the last class.
+constexpr int tile_class_off(int k) {
+  int n = 0;
+  for (int a = -kTileR; a <= kTileR; ++a)
+    for (int b = -kTileR; b <= kTileR; ++b)
+      for (int c = -kTileR; c <= kTileR; ++c) {
+        const int d2 = a * a + b * b + c * c;
+        if (d2 == 0 || d2 > kTileR * kTileR) continue;
+        if (n == k) return ((a + kTileR) * kHM + (b + kTileR)) * kHF + (c + kTileR);
+        ++n;
+      }
+  return -1;
+}
+static_assert(tile_class_off(kTileClasses - 1) >= 0 && tile_class_off(kTileClasses) < 0,
+              "horizon factor 3 has 122 classes");
+static_assert(kMaskWords * 32 >= kTileClasses, "class mask too short");
+static_assert((kHalo + tile_class_off(kTileClasses - 1)) * sizeof(double) <= 65535,
+              "plane and class offsets must fit the LDS immediate offset");
+
+// bond tables read through the constant address space: the table of a tile is
+// the same for the whole wavefront, so these become scalar loads
+typedef const __attribute__((address_space(4))) StencilC* TileTab;
+
+// Operands of one horizon class: the neighbour's u from LDS and the class's
+// bond-law constants through scalar loads.  An opaque copy of the row address
+// keeps each class's scalar loads where they are issued instead of all 122
+// rows' being hoisted to the kernel entry.
+struct TileIn {
+  double ux, uy, uz;
+  double hx, hy, hz, thr, inv, civ;
+  const StencilC* rowp;
+};
+
+template <int K>
+__device__ __forceinline__ void tile_load(const double* L, const double* Lz, const StencilC* tabp, TileIn& in) {
+  constexpr int off = tile_class_off(K);
+  const StencilC* rowp = tabp + K;
+  asm volatile("" : "+s"(rowp));
+  const TileTab row = (TileTab)rowp;
+  in.ux = L[off];
+  in.uy = L[kHalo + off];
+  in.uz = Lz[off];
+  in.hx = row->hx;
+  in.hy = row->hy;
+  in.hz = row->hz;
+  in.thr = row->thr_d;
+  in.inv = row->inv_l0sq;
+  in.civ = row->civ;
+  in.rowp = rowp;
+}
+
+// One horizon class of the lane's node: the same arithmetic, in the same order,
+// as an entry of the slice path, so the two paths agree bitwise.  A class with
+// no bond (outside the grain, cut, or broken) adds an exact zero.  The
+// operands of class K arrived during class K - 1; once the first of them is
+// used (which waits for all of them) class K + 1's loads are issued, so that
+// they travel while class K computes.
+template <int K, bool ABS>
+__device__ __forceinline__ void tile_bond(const double* L, const double* Lz, const StencilC* tabp, TileIn& in,
+                                          const Poly10& P10, double uix, double uiy, double uiz,
+                                          double abs_ratio,
+                                          uint32_t (&mask)[kMaskWords], double& fx, double& fy, double& fz) {
+  constexpr int wd = K / 32;
+  constexpr uint32_t bit = 1u << (K % 32);
+  const double ex = in.ux - uix, ey = in.uy - uiy, ez = in.uz - uiz;
+  const double hx = in.hx, hy = in.hy, hz = in.hz;
+  const double yx = hx + ex, yy = hy + ey, yz = hz + ez;
+  const double thr = in.thr, inv = in.inv, civ = in.civ;
+  const TileTab row = (TileTab)in.rowp;
+  __builtin_amdgcn_sched_barrier(0);
+  if constexpr (K + 1 < kTileClasses) tile_load<K + 1>(L, Lz, tabp, in);
+  const double d = fma(ex, yx + hx, fma(ey, yy + hy, ez * (yz + hz)));
+  bool over = d > thr;
+  if (ABS) over = over || d < -abs_ratio * thr;
+  const double x = d * inv;
+  // the per-lane choice of the slice path (series, or the exact form past
+  // kPolyRange), the exact form computed only when some lane needs it
+  double g = x * one_minus_rsqrt1p_over_x(x, P10);
+  const bool exact = !(fabs(x) <= kPolyRange);
+  if (__any(exact)) {
+    const double lsq = row->l0sq + d;
+    const double l = lsq * rsqrt_full(lsq);
+    const double ge = d * rcp_full(fma(l, row->l0, lsq));
+    g = exact ? ge : g;
+  }
+  // a live bond within its limit adds its force, the others an exact zero (as
+  // in the slice path); a bond past its limit stays broken from now on
+  const bool live = (mask[wd] & bit) != 0u;
+  const double coef = (over || !live) ? 0.0 : civ * g;
+  fx = fma(coef, yx, fx);
+  fy = fma(coef, yy, fy);
+  fz = fma(coef, yz, fz);
+  mask[wd] = over ? (mask[wd] & ~bit) : mask[wd];
+  // materialise the running sums here: left alone, the compiler sinks every
+  // class's accumulation to the end and keeps all 122 classes' terms live
+  asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(mask[wd]));
+}
+
+template <bool ABS, int... K>
+__device__ __forceinline__ void tile_bonds(std::integer_sequence<int, K...>, const double* L, const double* Lz,
+                                           const StencilC* tab, const Poly10& P10, double uix,
+                                           double uiy, double uiz, double abs_ratio, uint32_t (&mask)[kMaskWords],
+                                           double& fx, double& fy, double& fz) {
+  TileIn in;
+  tile_load<0>(L, Lz, tab, in);
+  (tile_bond<K, ABS>(L, Lz, tab, in, P10, uix, uiy, uiz, abs_ratio, mask, fx, fy, fz), ...);
+}
+
+__device__ __forceinline__ int64_t tile_cell(const TileGrain& TG, int s, int m, int f) {
+  return TG.map_off + ((int64_t)s * TG.em + m) * TG.ef + f;
+}
+
+// One workgroup per tile: stage u of the tile and its halo (cells outside the
+// grain hold zeros and have no bonds), evaluate the 122 horizon classes of each
+// lane's cell from LDS, then the node tail of the slice path.  Lane l of
+// wavefront w owns cell (s0 + w, m0 + l / 16, f0 + l % 16).
+template <bool ABS>
+__global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
+  // x, y and z planes of the halo box
+  __shared__ double s_u[3 * kHalo];
+  constexpr int kNT = kTS * kWave;
+  constexpr int kFill = (kHalo + kNT - 1) / kNT;  // halo cells per thread
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t t = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int4 T = A.tiles[t];
+  const TileGrain TG = A.tgrain[T.x];
+  // the lane's own cell, then the halo: every map read is issued before the
+  // first wait and every u read before the second, so the fill costs two
+  // memory round trips rather than two per cell
+  const int lm = lane / kTF, lf = lane % kTF;
+  const int cs = T.y + wid, cm = T.z + lm, cf = T.w + lf;
+  const bool own_in = cs < TG.es && cm < TG.em && cf < TG.ef;
+  int64_t i = own_in ? (int64_t)A.tmap[tile_cell(TG, cs, cm, cf)] : -1;
+  int j[kFill];
+#pragma unroll
+  for (int r = 0; r < kFill; ++r) {
+    const int c = tid + r * kNT;
+    const int hs = c / (kHM * kHF), rr = c - hs * (kHM * kHF);
+    const int hm = rr / kHF, hf = rr - hm * kHF;
+    const int ps = T.y - kTileR + hs, pm = T.z - kTileR + hm, pf = T.w - kTileR + hf;
+    j[r] = -1;
+    if (c < kHalo && ps >= 0 && ps < TG.es && pm >= 0 && pm < TG.em && pf >= 0 && pf < TG.ef)
+      j[r] = A.tmap[tile_cell(TG, ps, pm, pf)];
+  }
+  const bool valid = i >= 0;
+  double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
+  uint32_t mask[kMaskWords] = {0u, 0u, 0u, 0u};
+  if (valid) {
+    ui = A.ucur[i];
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) mask[w] = A.mask[(int64_t)w * A.n + i];
+  }
+  double hx_[kFill], hy_[kFill], hz_[kFill];
+#pragma unroll
+  for (int r = 0; r < kFill; ++r) {
+    hx_[r] = hy_[r] = hz_[r] = 0.0;
+    if (j[r] >= 0) {
+      const double4 u = A.ucur[j[r]];
+      hx_[r] = u.x;
+      hy_[r] = u.y;
+      hz_[r] = u.z;
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < kFill; ++r) {
+    const int c = tid + r * kNT;
+    if (c < kHalo) {
+      s_u[c] = hx_[r];
+      s_u[kHalo + c] = hy_[r];
+      s_u[2 * kHalo + c] = hz_[r];
+    }
+  }
+  const GrainC* G = A.grains + T.x;
+  const int pi = packed_ijk(ui.w);
+  __syncthreads();
+
+  const double* L = s_u + (wid * kHM + lm) * kHF + lf;
+  const double* Lz = L + 2 * kHalo;  // own base: plane and class offsets must fit the 16-bit immediate
+  double fx = 0.0, fy = 0.0, fz = 0.0;
+  const StencilC* tab = A.ttab + (int64_t)TG.table * kTileClasses;
+  const Poly10 P10 = poly10_in_registers();
+  int nbroke = 0;
+#pragma unroll
+  for (int w = 0; w < kMaskWords; ++w) nbroke += __popc(mask[w]);
+  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, P10, ui.x, ui.y, ui.z,
+                  G->abs_ratio, mask, fx, fy, fz);
+#pragma unroll
+  for (int w = 0; w < kMaskWords; ++w) nbroke -= __popc(mask[w]);  // bonds broken in this step
+  if (valid && nbroke) {
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = mask[w];
+  }
+  node_tail<MODE_STEP>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke, true,
+                       (int64_t)kTS * t + wid, load_va(A, i, valid));
+}
+
+// the six orders of the lattice axes (slowest first)
+__device__ __constant__ int kAxisPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
+
+__device__ __forceinline__ void tile_coords(const TileGrain& TG, int p, int& s, int& m, int& f) {
+  const int q[3] = {unpack_x(p), unpack_y(p), unpack_z(p)};
+  s = q[kAxisPerm[TG.perm][0]] - TG.lo_s;
+  m = q[kAxisPerm[TG.perm][1]] - TG.lo_m;
+  f = q[kAxisPerm[TG.perm][2]] - TG.lo_f;
+}
+
+__global__ void k_tile_map_fill(StepArgs A) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const double w = A.ucur[i].w;
+  const TileGrain TG = A.tgrain[packed_grain(w)];
+  int s, m, f;
+  tile_coords(TG, packed_ijk(w), s, m, f);
+  const_cast<int32_t*>(A.tmap)[tile_cell(TG, s, m, f)] = (int32_t)i;
+}
+
+// node i's slice-path entries: bit ctob[perm][class] of the mask is set for
+// every built bond whose live column word is still the built one
+__global__ void k_cols_to_mask(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int64_t sl = i / kWave, lane = i % kWave;
+  const int64_t off = A.slice_off[sl];
+  const int W = (int)((A.slice_off[sl + 1] - off) / kWave);
+  const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
+  uint32_t m[kMaskWords] = {0u, 0u, 0u, 0u};
+  for (int e = 0; e < W; ++e) {
+    const int64_t at = off + (int64_t)e * kWave + lane;
+    const uint32_t wo = colOrig[at];
+    const int cls = (int)(wo >> A.node_bits);
+    if (cls >= A.n_stencil || A.colE[at] != wo) continue;
+    const int b = ctob[perm * A.n_stencil + cls];
+    m[b >> 5] |= 1u << (b & 31);
+  }
+  for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = m[w];
+}
+
+// the inverse: an entry whose class bit is clear becomes a broken column word
+__global__ void k_mask_to_cols(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const int64_t sl = i / kWave, lane = i % kWave;
+  const int64_t off = A.slice_off[sl];
+  const int W = (int)((A.slice_off[sl + 1] - off) / kWave);
+  const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
+  uint32_t m[kMaskWords];
+  for (int w = 0; w < kMaskWords; ++w) m[w] = A.mask[(int64_t)w * A.n + i];
+  for (int e = 0; e < W; ++e) {
+    const int64_t at = off + (int64_t)e * kWave + lane;
+    const uint32_t wo = colOrig[at];
+    const int cls = (int)(wo >> A.node_bits);
+    if (cls >= A.n_stencil) continue;
+    const int b = ctob[perm * A.n_stencil + cls];
+    A.colE[at] = ((m[b >> 5] >> (b & 31)) & 1u) ? wo : ((uint32_t)i | A.sentinel_hi);
+  }
 }
 
 // Wall reactions are reduced in a fixed order in two levels, the same in every
@@ -1309,6 +1598,31 @@ hipError_t launch_energy(const StepArgs& a, double* partial4, int32_t nblocks, h
 hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double* out4,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_reduce_energy, dim3(1), dim3(64), 0, s, partial4, nblocks, out4);
+  return hipGetLastError();
+}
+
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+  if (a.n_tiles == 0) return hipSuccess;
+  if (a.abs_stretch) hipLaunchKernelGGL(k_step_tile<true>, dim3((unsigned)a.n_tiles), dim3(kTS * kWave), 0, s, a);
+  else hipLaunchKernelGGL(k_step_tile<false>, dim3((unsigned)a.n_tiles), dim3(kTS * kWave), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_map_fill(const StepArgs& a, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_tile_map_fill, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_cols_to_mask(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cols_to_mask, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, ctob, colOrig);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask_to_cols(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig, hipStream_t s) {
+  if (a.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_mask_to_cols, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, ctob, colOrig);
   return hipGetLastError();
 }
 

@@ -66,12 +66,14 @@ class pd_wall(C.Structure):
 
 class pd_launch(C.Structure):
     _fields_ = [("loop", C.c_int32), ("slices_per_block", C.c_int32), ("xcd_remap", C.c_int32),
-                ("persistent_blocks", C.c_int32)]
+                ("persistent_blocks", C.c_int32), ("bond_path", C.c_int32)]
 
 
 LOOP_GRAPH, LOOP_DIRECT, LOOP_PERSISTENT, LOOP_PER_GRAIN = 0, 1, 2, 3
 LOOP_NAMES = {LOOP_GRAPH: "graph", LOOP_DIRECT: "direct", LOOP_PERSISTENT: "persistent",
               LOOP_PER_GRAIN: "per_grain"}
+BONDS_SLICES, BONDS_TILES = 0, 1
+BOND_PATH_NAMES = {BONDS_SLICES: "slices", BONDS_TILES: "tiles"}
 
 
 class pd_cut(C.Structure):
@@ -301,15 +303,16 @@ class Sim:
                     step=int(o[4]))
 
     def set_launch(self, loop: int = LOOP_GRAPH, slices_per_block: int = 4, xcd_remap: int = 1,
-                   persistent_blocks: int = 0):
-        cfg = pd_launch(int(loop), int(slices_per_block), int(xcd_remap), int(persistent_blocks))
+                   persistent_blocks: int = 0, bond_path: int = BONDS_SLICES):
+        cfg = pd_launch(int(loop), int(slices_per_block), int(xcd_remap), int(persistent_blocks),
+                        int(bond_path))
         self._check(lib().pd_set_launch(self.h, C.byref(cfg)))
 
     def get_launch(self) -> dict:
         cfg = pd_launch()
         self._check(lib().pd_get_launch(self.h, C.byref(cfg)))
         return dict(loop=cfg.loop, slices_per_block=cfg.slices_per_block, xcd_remap=cfg.xcd_remap,
-                    persistent_blocks=cfg.persistent_blocks)
+                    persistent_blocks=cfg.persistent_blocks, bond_path=cfg.bond_path)
 
     def set_timing(self, enable: bool):
         self._check(lib().pd_set_timing(self.h, 1 if enable else 0))
