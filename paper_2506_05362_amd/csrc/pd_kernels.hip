@@ -239,30 +239,32 @@ __device__ __forceinline__ double wave_sum(double x) {
 #define PD_STEP_WAVES_PER_EU 1
 #endif
 
-// 1 - (1 + x)^(-1/2) = x * sum_k (-1)^k a_{k+1} x^k with a_k = C(2k, k) / 4^k.
-// Ten terms give the sum to better than 2e-16 relative for |x| <= kPolyRange.
+// 1 - (1 + x)^(-1/2) = x q(x).  For |x| <= kPolyRange q is a degree-8
+// polynomial: the interpolant of q at the nine Chebyshev nodes of the interval
+// (coefficients from csrc/bond_series.py), constant term exactly 1/2, relative
+// error about 1e-18 with its coefficients in double.
 constexpr double kPolyRange = 0.02;
-// The ten-term series.  Its nine non-trivial coefficients may be held in
-// registers (Poly10), with the same arithmetic either way: as literals the
-// compiler rebuilds each 64-bit constant with two moves per use.
-struct Poly10 {
-  double c[9];
+// The eight non-trivial coefficients, highest degree first.  They may be held
+// in registers (poly_in_registers), with the same arithmetic either way: as
+// literals the compiler rebuilds each 64-bit constant with two moves per use.
+struct PolyG {
+  double c[8];
 };
-constexpr Poly10 kPoly10{{-46189.0 / 262144.0, 12155.0 / 65536.0, -6435.0 / 32768.0, 429.0 / 2048.0,
-                          -231.0 / 1024.0, 63.0 / 256.0, -35.0 / 128.0, 5.0 / 16.0, -3.0 / 8.0}};
-__device__ __forceinline__ Poly10 poly10_in_registers() {
-  Poly10 P = kPoly10;
+constexpr PolyG kPolyG{{0x1.7c2767adf6933p-3, -0x1.92832f94213d7p-3, 0x1.acfff9e68ffc4p-3, -0x1.cdfff99c37884p-3,
+                        0x1.f80000002c6aep-3, -0x1.1800000017442p-2, 0x1.3fffffffffffdp-2, -0x1.7fffffffffffdp-2}};
+__device__ __forceinline__ PolyG poly_in_registers() {
+  PolyG P = kPolyG;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) asm volatile("" : "+v"(P.c[k]));
+  for (int k = 0; k < 8; ++k) asm volatile("" : "+v"(P.c[k]));
   return P;
 }
-__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x, const Poly10& P) {
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x, const PolyG& P) {
   double p = fma(P.c[0], x, P.c[1]);
 #pragma unroll
-  for (int k = 2; k < 9; ++k) p = fma(p, x, P.c[k]);
+  for (int k = 2; k < 8; ++k) p = fma(p, x, P.c[k]);
   return fma(p, x, 0.5);
 }
-__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) { return one_minus_rsqrt1p_over_x(x, kPoly10); }
+__device__ __forceinline__ double one_minus_rsqrt1p_over_x(double x) { return one_minus_rsqrt1p_over_x(x, kPolyG); }
 
 // The fused step of one workgroup: SPB slices (one wavefront each) starting at
 // slice slice_base + SPB * blk.  s_st holds the stencil tables in LDS.
@@ -478,7 +480,12 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   const bool valid = slice_ok && i >= A.node_lo && i < A.node_hi;
 
   double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
-  if (valid) ui = A.ucur[i];
+  uint32_t mask[kMaskWords] = {0u, 0u, 0u, 0u};
+  if (valid) {
+    ui = A.ucur[i];
+#pragma unroll
+    for (int w = 0; w < kMaskWords; ++w) mask[w] = A.mask[(int64_t)w * A.n + i];
+  }
   const int pi = packed_ijk(ui.w);
   const int gi = valid ? packed_grain(ui.w) : 0;
   const GrainC* G = A.grains + gi;
@@ -500,7 +507,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   // Bond law (Sec. 3.1): the force on i is c s V_j y/|y|, y = xi + eta, and
   //   c V s / |y| = (c V / |xi|) g,   g = 1 - |xi|/|y| = 1 - (1 + x)^(-1/2),
   //   x = (|y|^2 - |xi|^2) / |xi|^2,   |y|^2 - |xi|^2 = eta . (2 xi + eta).
-  // g comes from its ten-term power series when |x| <= kPolyRange (no square
+  // g comes from its polynomial when |x| <= kPolyRange (no square
   // root or division), else from g = (|y|^2 - |xi|^2) / (|y| (|y| + |xi|));
   // neither form subtracts nearly equal numbers.  The choice is made per lane,
   // so any grouping of bonds (the tiled path) computes the same values.
@@ -643,8 +650,7 @@ __device__ __forceinline__ void tile_load(const double* L, const double* Lz, con
 // they travel while class K computes.
 template <int K, bool ABS>
 __device__ __forceinline__ void tile_bond(const double* L, const double* Lz, const StencilC* tabp, TileIn& in,
-                                          const Poly10& P10, double uix, double uiy, double uiz,
-                                          double abs_ratio,
+                                          const PolyG& PG, double uix, double uiy, double uiz, double abs_ratio,
                                           uint32_t (&mask)[kMaskWords], double& fx, double& fy, double& fz) {
   constexpr int wd = K / 32;
   constexpr uint32_t bit = 1u << (K % 32);
@@ -661,7 +667,7 @@ __device__ __forceinline__ void tile_bond(const double* L, const double* Lz, con
   const double x = d * inv;
   // the per-lane choice of the slice path (series, or the exact form past
   // kPolyRange), the exact form computed only when some lane needs it
-  double g = x * one_minus_rsqrt1p_over_x(x, P10);
+  double g = x * one_minus_rsqrt1p_over_x(x, PG);
   const bool exact = !(fabs(x) <= kPolyRange);
   if (__any(exact)) {
     const double lsq = row->l0sq + d;
@@ -684,12 +690,12 @@ __device__ __forceinline__ void tile_bond(const double* L, const double* Lz, con
 
 template <bool ABS, int... K>
 __device__ __forceinline__ void tile_bonds(std::integer_sequence<int, K...>, const double* L, const double* Lz,
-                                           const StencilC* tab, const Poly10& P10, double uix,
-                                           double uiy, double uiz, double abs_ratio, uint32_t (&mask)[kMaskWords],
-                                           double& fx, double& fy, double& fz) {
+                                           const StencilC* tab, const PolyG& PG, double uix, double uiy, double uiz,
+                                           double abs_ratio, uint32_t (&mask)[kMaskWords], double& fx, double& fy,
+                                           double& fz) {
   TileIn in;
   tile_load<0>(L, Lz, tab, in);
-  (tile_bond<K, ABS>(L, Lz, tab, in, P10, uix, uiy, uiz, abs_ratio, mask, fx, fy, fz), ...);
+  (tile_bond<K, ABS>(L, Lz, tab, in, PG, uix, uiy, uiz, abs_ratio, mask, fx, fy, fz), ...);
 }
 
 __device__ __forceinline__ int64_t tile_cell(const TileGrain& TG, int s, int m, int f) {
@@ -765,11 +771,11 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   const double* Lz = L + 2 * kHalo;  // own base: plane and class offsets must fit the 16-bit immediate
   double fx = 0.0, fy = 0.0, fz = 0.0;
   const StencilC* tab = A.ttab + (int64_t)TG.table * kTileClasses;
-  const Poly10 P10 = poly10_in_registers();
+  const PolyG PG = poly_in_registers();
   int nbroke = 0;
 #pragma unroll
   for (int w = 0; w < kMaskWords; ++w) nbroke += __popc(mask[w]);
-  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, P10, ui.x, ui.y, ui.z,
+  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, PG, ui.x, ui.y, ui.z,
                   G->abs_ratio, mask, fx, fy, fz);
 #pragma unroll
   for (int w = 0; w < kMaskWords; ++w) nbroke -= __popc(mask[w]);  // bonds broken in this step
