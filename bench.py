@@ -25,7 +25,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_05362_amd", "csrc", "pd_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_notched_plate.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_tile_notched_plate.json")
 
 # algorithmic bytes of the fused step kernel (per launch):
 #   per directed bond : 4 B column word (it also carries the bond-broken state)

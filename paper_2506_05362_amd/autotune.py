@@ -2,9 +2,12 @@
 
 For one simulation context it times every candidate launch configuration -
 step-loop mode (captured graph, persistent cooperative kernel), 64-node slices
-per workgroup and the XCD-aware workgroup order - on the context's own state,
-keeps the fastest and restores the state it started from, so tuning changes
-nothing but speed (every configuration computes bitwise the same result).
+per workgroup, the XCD-aware workgroup order and the bond path (sliced rows or
+LDS tiles) - on the context's own state, keeps the fastest and restores the
+state it started from, so tuning changes nothing but speed (every candidate
+computes bitwise the same node state; the tile path is left out when a wall is
+servo-controlled, since its wall reactions, and through them the servo, agree
+with the slice path only to rounding).
 
 Results are cached in a JSON file keyed by the GPU architecture, the node and
 bond counts and a histogram of grain sizes (log2 bins), so a later context of
@@ -21,9 +24,11 @@ from typing import Dict, Iterable, List, Optional
 
 import numpy as np
 
+from . import inputs as I
 from . import pd
 
-DEFAULT = dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=1, persistent_blocks=0)
+DEFAULT = dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=1, persistent_blocks=0,
+               bond_path=pd.BONDS_SLICES)
 
 
 def cache_path() -> str:
@@ -41,12 +46,21 @@ def shape_key(arch: str, n_nodes: int, nnz: int, grain_sizes: Iterable[int]) -> 
     return f"{arch}|n={int(n_nodes)}|nnz={int(nnz)}|g={hist}"
 
 
-def candidates(persistent: bool = True) -> List[Dict[str, int]]:
-    out = [dict(loop=pd.LOOP_GRAPH, slices_per_block=spb, xcd_remap=x, persistent_blocks=0)
-           for spb in (1, 2, 4, 8) for x in (1, 0)]
+def candidates(persistent: bool = True, tiles: bool = True) -> List[Dict[str, int]]:
+    out = [dict(loop=pd.LOOP_GRAPH, slices_per_block=spb, xcd_remap=x, persistent_blocks=0,
+                bond_path=pd.BONDS_SLICES) for spb in (1, 2, 4, 8) for x in (1, 0)]
     if persistent:
-        out.append(dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=1, persistent_blocks=0))
+        out.append(dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=1, persistent_blocks=0,
+                        bond_path=pd.BONDS_SLICES))
+    if tiles:
+        out += [dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=x, persistent_blocks=0,
+                     bond_path=pd.BONDS_TILES) for x in (1, 0)]
     return out
+
+
+def name_of(cfg: Dict[str, int]) -> str:
+    base = f"{pd.LOOP_NAMES[cfg['loop']]}/spb{cfg['slices_per_block']}/xcd{cfg['xcd_remap']}"
+    return base + "/tiles" if cfg.get("bond_path", pd.BONDS_SLICES) == pd.BONDS_TILES else base
 
 
 def _load(path: str) -> dict:
@@ -99,10 +113,12 @@ def tune(sim: "pd.Sim", steps: Optional[int] = None, use_cache: bool = True,
         steps = graph_len * max(2, int(math.ceil(0.02 / max(_quick_step_estimate(sim), 1e-6) / graph_len)))
     start = sim.get_state()
     before = sim.get_launch()
+    tiles = not any(w.mode == I.WALL_SERVO for w in sim.wl.walls)
+    cands = candidates(persistent, tiles)
     times = {}
     try:
-        for cfg in candidates(persistent):
-            name = f"{pd.LOOP_NAMES[cfg['loop']]}/spb{cfg['slices_per_block']}/xcd{cfg['xcd_remap']}"
+        for cfg in cands:
+            name = name_of(cfg)
             try:
                 times[name] = time_config(sim, cfg, steps)
             except pd.PDError as e:
@@ -114,8 +130,7 @@ def tune(sim: "pd.Sim", steps: Optional[int] = None, use_cache: bool = True,
         sim.set_launch(**before)
         sim.set_state(start)
     best_name = min(times, key=times.get)
-    cfg = next(c for c in candidates(persistent)
-               if f"{pd.LOOP_NAMES[c['loop']]}/spb{c['slices_per_block']}/xcd{c['xcd_remap']}" == best_name)
+    cfg = next(c for c in cands if name_of(c) == best_name)
     sim.set_launch(**cfg)
     if use_cache:
         table = _load(path)

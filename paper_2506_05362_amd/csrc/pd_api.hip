@@ -316,11 +316,12 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
-  if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
+  // a single step launch records ev0/ev1 itself, tightly around the kernel
   if (c->launch.bond_path == PD_BONDS_TILES) {
     A.partial_stride = kTS * c->n_tiles;  // one wall-partial column per tile wavefront
-    HIPCHK(c, launch_step_tile(A, c->stream));
+    HIPCHK(c, launch_step_tile(A, c->stream, ev0, ev1));
   } else if (c->launch.loop == PD_LOOP_PER_GRAIN) {
+    if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
     // one launch per grain over the slices that hold its nodes; a slice shared
     // by two grains is visited by both launches, each lane working for its own
     A.partial_stride = c->pg_cols;
@@ -334,12 +335,10 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
       Ag.xcd_remap = 0;
       HIPCHK(c, launch_step_spb(Ag, kSlicesPerBlock, c->stream));
     }
-  } else if (c->launch.slices_per_block != kSlicesPerBlock) {
-    HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream));
+    if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
   } else {
-    HIPCHK(c, launch_step(A, MODE_STEP, c->stream));
+    HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream, ev0, ev1));
   }
-  if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
   HIPCHK(c, launch_wall_finalize(A, c->stream));
   return PD_OK;
 }

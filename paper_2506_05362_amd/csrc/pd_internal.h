@@ -232,8 +232,10 @@ hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s);
 hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s);
 hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s);
-// MODE_STEP with slices_per_block in {1, 2, 4, 8}
-hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s);
+// MODE_STEP with slices_per_block in {1, 2, 4, 8}; e0/e1, when given, are
+// recorded by the launch itself around the kernel
+hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s, hipEvent_t e0 = nullptr,
+                           hipEvent_t e1 = nullptr);
 // nsteps steps with no rebuild in between, one cooperative launch of nblocks
 // workgroups (4 slices each) that loop over the slices with a grid barrier
 // between steps
@@ -257,8 +259,8 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
 int32_t step_grid_blocks(int64_t nslices);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
-// tiled bond loop: MODE_STEP over all tiles
-hipError_t launch_step_tile(const StepArgs& a, hipStream_t s);
+// tiled bond loop: MODE_STEP over all tiles (events as for launch_step_spb)
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // per-node cell map of the tile grains: tmap[map_off + (s em + m) ef + f] = node
 hipError_t launch_tile_map_fill(const StepArgs& a, hipStream_t s);
 // bond state between the slice path's column words and the tile path's class

@@ -19,6 +19,8 @@
 // Sec. 3.1 eq. (peri-damage) with nodal quadrature, Sec. 6.1): no atomics, so
 // results are bitwise reproducible run to run.
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <utility>
 
@@ -1515,11 +1517,20 @@ static size_t step_lds(const StepArgs& a) {
 }
 
 template <int MODE, int SPB>
-static void launch_step_t(const StepArgs& a, hipStream_t s) {
+static void launch_step_t(const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr) {
   const int32_t nb = step_blocks_spb(a.slice_end - a.slice_base, SPB);
   if (nb == 0) return;
-  if (a.abs_stretch) hipLaunchKernelGGL((k_step<MODE, true, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
-  else hipLaunchKernelGGL((k_step<MODE, false, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
+  // with events, the launch itself records them around the kernel
+  if (e0 || e1) {
+    if (a.abs_stretch)
+      hipExtLaunchKernelGGL((k_step<MODE, true, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, e0, e1, 0, a);
+    else
+      hipExtLaunchKernelGGL((k_step<MODE, false, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, e0, e1, 0, a);
+  } else if (a.abs_stretch) {
+    hipLaunchKernelGGL((k_step<MODE, true, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
+  } else {
+    hipLaunchKernelGGL((k_step<MODE, false, SPB>), dim3(nb), dim3(SPB * kWave), step_lds(a), s, a);
+  }
 }
 
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
@@ -1529,12 +1540,12 @@ hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s) {
+hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   switch (slices_per_block) {
-    case 1: launch_step_t<MODE_STEP, 1>(a, s); break;
-    case 2: launch_step_t<MODE_STEP, 2>(a, s); break;
-    case 4: launch_step_t<MODE_STEP, 4>(a, s); break;
-    case 8: launch_step_t<MODE_STEP, 8>(a, s); break;
+    case 1: launch_step_t<MODE_STEP, 1>(a, s, e0, e1); break;
+    case 2: launch_step_t<MODE_STEP, 2>(a, s, e0, e1); break;
+    case 4: launch_step_t<MODE_STEP, 4>(a, s, e0, e1); break;
+    case 8: launch_step_t<MODE_STEP, 8>(a, s, e0, e1); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();
@@ -1607,10 +1618,17 @@ hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double*
   return hipGetLastError();
 }
 
-hipError_t launch_step_tile(const StepArgs& a, hipStream_t s) {
+hipError_t launch_step_tile(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (a.n_tiles == 0) return hipSuccess;
-  if (a.abs_stretch) hipLaunchKernelGGL(k_step_tile<true>, dim3((unsigned)a.n_tiles), dim3(kTS * kWave), 0, s, a);
-  else hipLaunchKernelGGL(k_step_tile<false>, dim3((unsigned)a.n_tiles), dim3(kTS * kWave), 0, s, a);
+  const dim3 grid((unsigned)a.n_tiles), block(kTS * kWave);
+  if (e0 || e1) {
+    if (a.abs_stretch) hipExtLaunchKernelGGL(k_step_tile<true>, grid, block, 0, s, e0, e1, 0, a);
+    else hipExtLaunchKernelGGL(k_step_tile<false>, grid, block, 0, s, e0, e1, 0, a);
+  } else if (a.abs_stretch) {
+    hipLaunchKernelGGL(k_step_tile<true>, grid, block, 0, s, a);
+  } else {
+    hipLaunchKernelGGL(k_step_tile<false>, grid, block, 0, s, a);
+  }
   return hipGetLastError();
 }
 
