@@ -511,6 +511,111 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
     return wl
 
 
+def _sequential_spheres(rng: np.random.Generator, radii: np.ndarray, L: float, frac: float) -> np.ndarray:
+    """Centres in [0, L]^3 for spheres of radii frac * radii, placed largest first
+    by random sequential addition without overlap (a hashed grid keeps each
+    placement test local)."""
+    from scipy.spatial import cKDTree
+    order = np.argsort(-radii)
+    r = frac * radii
+    rmax = r.max()
+    pts = np.zeros((len(radii), 3))
+    placed = []
+    tree = None
+    since = 0
+    for k in order:
+        for _ in range(100000):
+            c = rng.uniform(r[k], L - r[k], size=3)
+            ok = True
+            if tree is not None:
+                near = tree.query_ball_point(c, r[k] + rmax)
+                ok = all(np.sum((pts[j] - c) ** 2) >= (r[j] + r[k]) ** 2 for j in (placed[q] for q in near))
+            if ok:
+                for j in placed[len(placed) - since:]:
+                    if np.sum((pts[j] - c) ** 2) < (r[j] + r[k]) ** 2:
+                        ok = False
+                        break
+            if ok:
+                break
+        else:
+            raise RuntimeError("sphere placement did not converge; lower frac")
+        pts[k] = c
+        placed.append(k)
+        since += 1
+        if since >= 64:  # rebuild the tree over everything placed so far
+            tree = cKDTree(pts[placed])
+            since = 0
+    return pts
+
+
+def large_aggregate(seed: int = 0, n_grains: int = 1000, mean_radius: float = 0.5e-3, sigma: float = 0.3,
+                    h: float = 4.1e-5, dt: float = 4.0e-9, platen_speed: float = 10.0, axial_strain: float = 0.05,
+                    material: Material = SAND, rebuild_every: int = 20, min_grain_nodes: int = 20) -> Workload:
+    """A dense aggregate of n_grains grains with log-normal sizes confined by six walls.
+
+    Radii r ~ LogNormal(ln(mean_radius) - sigma^2/2, sigma) (mean mean_radius);
+    the box holds their total volume.  Seeds are spread by random sequential
+    addition of spheres of 0.6 r, and every node centre (i + 1/2) h of the box
+    joins the seed of least power distance |x - c|^2 - r^2 (a Laguerre
+    tessellation), so cell volumes follow the radii and neighbouring grains
+    touch face to face without pressing.  Walls one spacing beyond the nodes:
+    floor fixed (normal +z), platen moving down at platen_speed, four fixed
+    lateral walls; steps cover axial_strain of the box height.
+    """
+    rng = np.random.default_rng(seed)
+    from scipy.spatial import cKDTree
+    params = default_params(h, dt, rebuild_every=rebuild_every)
+    radii = rng.lognormal(math.log(mean_radius) - 0.5 * sigma * sigma, sigma, size=n_grains)
+    L = float(np.sum(4.0 / 3.0 * math.pi * radii ** 3)) ** (1.0 / 3.0)
+    n_side = int(round(L / h))
+    L = n_side * h
+    seeds = _sequential_spheres(rng, radii, L, 0.6)
+    # grains in a coarse space-filling order so neighbours stay close in memory
+    cell = np.floor(seeds / (L / 8.0)).clip(0, 7).astype(np.int64)
+    perm = np.lexsort((seeds[:, 0], cell[:, 0], cell[:, 1], cell[:, 2]))
+    seeds, radii = seeds[perm], radii[perm]
+    r = np.arange(n_side)
+    tree = cKDTree(seeds)
+    kq = min(16, n_grains)
+    gid = np.empty(n_side ** 3, dtype=np.int64)
+    for i0 in range(0, n_side, 16):  # slabs of the lattice keep the query's memory small
+        I, J, K = np.meshgrid(r[i0:i0 + 16], r, r, indexing="ij")
+        x = (np.stack([I.ravel(), J.ravel(), K.ravel()], axis=1) + 0.5) * h
+        d, idx = tree.query(x, k=kq)
+        power = d * d - radii[idx] ** 2
+        gid[i0 * n_side * n_side:(i0 + I.shape[0]) * n_side * n_side] = idx[np.arange(len(idx)), np.argmin(power, axis=1)]
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    lat = np.stack([I.ravel(), J.ravel(), K.ravel()]).astype(np.int64)
+    order = np.argsort(gid, kind="stable")
+    bounds = np.searchsorted(gid[order], np.arange(n_grains + 1))
+    blocks = []
+    for gr in range(n_grains):
+        sel = order[bounds[gr]:bounds[gr + 1]]
+        if sel.size < min_grain_nodes:
+            continue
+        ijk, origin = _grain_block(lat[:, sel], np.full(3, 0.5 * h), h)
+        blocks.append((ijk, origin, h, 0))
+    wl = _assemble("large_aggregate", blocks, [material], params, [], [], 1,
+                   info={"seed": seed, "n_grains": len(blocks), "box": L})
+    lo = wl.X.min(axis=1) - h
+    hi = wl.X.max(axis=1) + h
+    span = hi - lo
+    area = [span[1] * span[2], span[0] * span[2], span[0] * span[1]]
+    wl.walls = [
+        Wall(normal=(0.0, 0.0, 1.0), offset=lo[2], mode=WALL_FIXED, area=area[2]),
+        Wall(normal=(0.0, 0.0, -1.0), offset=-hi[2], mode=WALL_VELOCITY, velocity=platen_speed, area=area[2]),
+    ]
+    for ax in (0, 1):
+        for sgn in (1.0, -1.0):
+            nrm = [0.0, 0.0, 0.0]
+            nrm[ax] = sgn
+            wl.walls.append(Wall(normal=tuple(nrm), offset=lo[ax] if sgn > 0 else -hi[ax], mode=WALL_FIXED,
+                                 area=area[ax]))
+    wl.steps = int(math.ceil(axial_strain * span[2] / (platen_speed * dt)))
+    wl.info.update({"span0": span.tolist(), "platen_speed": platen_speed, "radii_mean": float(radii.mean())})
+    return wl
+
+
 # ----------------------------------------------------------------------------
 # named workloads with the sizes of the paper-scale experiments
 # ----------------------------------------------------------------------------
@@ -527,4 +632,6 @@ def workload(name: str, **kw) -> Workload:
         return grain_aggregate(**kw)
     if name == "rve_aggregate":
         return rve_aggregate(**kw)
+    if name == "large_aggregate":
+        return large_aggregate(**kw)
     raise KeyError(name)

@@ -1,0 +1,127 @@
+"""Large-aggregate run: about 1e7 nodes and 1e9 bonds on one GPU.
+
+A dense aggregate of 1000 grains with log-normal sizes (inputs.large_aggregate)
+in a box closed by six walls, compressed by the top platen.  The script times
+the step loop with both bond paths from the same state (and checks that they
+reach bitwise the same state), then runs the confined compression from the
+start, logging the platen stress, the mean damage and the kinetic energy every
+100 steps, until the requested axial strain or the time budget.  Prints JSON.
+
+    python -m paper_2506_05362_amd.scale_bench [--steps 200] [--strain 0.05] [--budget 120]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import time
+
+import numpy as np
+
+from . import inputs as I
+from . import pd
+
+
+def time_path(sim, bond_path, start, steps):
+    sim.set_state(start)
+    sim.set_launch(bond_path=bond_path)
+    sim.step(20)  # graph capture and caches
+    t0 = time.perf_counter()
+    sim.step(steps)
+    wall = (time.perf_counter() - t0) / steps
+    sim.set_timing(True)
+    sim.step(min(steps, 100))
+    n, ms = sim.timing()
+    sim.set_timing(False)
+    return wall, ms / max(n, 1), sim.get("displacement")
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--strain", type=float, default=0.05)
+    ap.add_argument("--budget", type=float, default=120.0, help="seconds for the compression run")
+    ap.add_argument("--log-every", type=int, default=100)
+    ap.add_argument("--seed", type=int, default=0)
+    ap.add_argument("--damping", type=float, default=2.4e23,
+                    help="normal contact damping beta_d (Sec. 3.4); the representative volume's "
+                         "2.8e22 at h = 70 um scaled by h^-4 to h = 41 um")
+    ap.add_argument("--rebuild-every", type=int, default=5)
+    ap.add_argument("--skin", type=float, default=0.5, help="Verlet skin in lattice spacings")
+    ap.add_argument("--capacity", type=int, default=32, help="contact candidates per node")
+    a = ap.parse_args(argv)
+    import torch
+
+    t0 = time.perf_counter()
+    wl = I.large_aggregate(seed=a.seed, axial_strain=a.strain, rebuild_every=a.rebuild_every)
+    wl.params.contact_damping = a.damping
+    wl.params.skin = a.skin * wl.grain_h[0]
+    gen_s = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    sim = pd.Sim(wl, candidate_capacity_per_node=a.capacity)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    info = sim.info()
+    sizes = np.diff(wl.grain_begin)
+    out = {"workload": "large_aggregate", "grains": int(wl.n_grains), "nodes": info["n_nodes"],
+           "bonds": info["nnz"], "padded_slots": info["padded"],
+           "grain_nodes_min": int(sizes.min()), "grain_nodes_max": int(sizes.max()),
+           "generate_s": round(gen_s, 1), "build_s": round(build_s, 2),
+           "contact_damping": a.damping, "rebuild_every": a.rebuild_every, "skin_h": a.skin, "candidate_capacity_per_node": a.capacity, "dt": wl.params.dt,
+           "platen_speed": wl.walls[1].velocity,
+           "device_bytes": int(torch.cuda.memory_allocated())}
+    print(json.dumps(out), flush=True)
+
+    start = sim.get_state()
+    paths = {}
+    ref = None
+    for name, bp in (("slices", pd.BONDS_SLICES), ("tiles", pd.BONDS_TILES)):
+        try:
+            wall, kern_ms, u = time_path(sim, bp, start, a.steps)
+        except pd.PDError as e:
+            paths[name] = {"error": str(e)}
+            continue
+        same = None if ref is None else bool(np.array_equal(u, ref))
+        ref = u if ref is None else ref
+        paths[name] = {"ms_per_step": wall * 1e3, "step_kernel_ms": kern_ms,
+                       "bond_updates_per_s": info["nnz"] / wall, "bitwise_equal_to_slices": same}
+        print(name, json.dumps(paths[name]), flush=True)
+    out["paths"] = paths
+    best = min((p for p in paths if "ms_per_step" in paths[p]), key=lambda p: paths[p]["ms_per_step"])
+    out["bond_path"] = best
+
+    # confined compression from the start with the faster path
+    sim.set_state(start)
+    sim.set_launch(bond_path=pd.BONDS_TILES if best == "tiles" else pd.BONDS_SLICES)
+    span_z = wl.info["span0"][2]
+    area = wl.walls[1].area
+    log = []
+    done = 0
+    t0 = time.perf_counter()
+    status = "complete"
+    while done < wl.steps:
+        n = min(a.log_every, wl.steps - done)
+        st = sim.step_status(n)
+        if st != pd.PD_OK:
+            status = "stopped: " + pd.lib().pd_last_error(sim.h).decode()
+            break
+        done += n
+        f = sim.get("wall_force")
+        v = sim.get("velocity")
+        dmg = sim.get("damage")
+        mass = I.SAND.density * wl.grain_h[0] ** 3
+        log.append({"step": done, "axial_strain": done * wl.params.dt * wl.walls[1].velocity / span_z,
+                    "platen_stress_pa": float(-(f[1] @ np.array(wl.walls[1].normal)) / area),
+                    "mean_damage": float(dmg.mean()),
+                    "kinetic_energy_j": float(0.5 * mass * np.sum(v * v))})
+        print(json.dumps(log[-1]), flush=True)
+        if time.perf_counter() - t0 > a.budget:
+            status = "time budget"
+            break
+    out["compression"] = {"steps": done, "status": status, "seconds": time.perf_counter() - t0,
+                          "ms_per_step": 1e3 * (time.perf_counter() - t0) / max(done, 1), "log": log}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    from paper_2506_05362_amd.scale_bench import main as _main
+    _main()

@@ -356,3 +356,23 @@ def test_oblique_collision_with_friction_matches_oracle(oracle_lib):
         v = ora.state()["v"]
         tang[mu] = v[1, nA:].mean() - v[1, :nA].mean()
     assert tang[0.5] < tang[0.0]
+
+
+def test_large_aggregate_small_instance_matches_oracle(oracle_lib):
+    """The large-aggregate generator's tessellation (log-normal Laguerre cells,
+    six walls) at a small size, compressed by the platen with damping: state
+    1e-9, platen force 1e-6, with both bond paths."""
+    from paper_2506_05362_amd import pd
+    wl = I.large_aggregate(seed=2, n_grains=30, h=1.6e-4, platen_speed=50.0)
+    wl.params.contact_damping = 1e21
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    ora.step(400)
+    fo, _ = ora.walls()
+    assert np.abs(fo[1]).max() > 0  # the platen is loaded
+    for bp in (pd.BONDS_SLICES, pd.BONDS_TILES):
+        sim = gpu_sim(wl)
+        sim.set_launch(bond_path=bp)
+        sim.step(400)
+        assert_state_close(sim, ora, what=f"bond path {bp}")
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        sim.close()
