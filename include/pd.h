@@ -87,8 +87,13 @@ typedef struct {
 
 enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 */
        PD_FLAG_ABS_STRETCH = 2,   /* break on |s| > s0 instead of s > s0 */
-       PD_FLAG_NO_GRAPH = 4       /* launch every step's kernels directly instead of replaying
-                                     a captured HIP graph of rebuild_every steps */ };
+       PD_FLAG_NO_GRAPH = 4,      /* launch every step's kernels directly instead of replaying
+                                     a captured HIP graph of rebuild_every steps */
+       PD_FLAG_CONIC = 8          /* conic micromodulus c0 (1 - |xi|/delta) (the table's second row,
+                                     Sec. 3.1.1): c0 = 90K/(pi delta^4), s0 = sqrt(2 G_c/(3 K delta)),
+                                     the values for which a uniform stretch has energy 9Ks^2/2 and
+                                     breaking the bonds across a unit area costs G_c; with
+                                     PD_FLAG_TABLE_LITERAL the printed row */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with

@@ -7,7 +7,8 @@
  * the plainest order; see pdref.h for the list of sections it follows.
  *
  * Readings of points the paper leaves open (each is also listed in the design notes):
- *   R1 constant micromodulus c = 18K/(pi delta^4) and s0 = sqrt(5 Gc/(9 K delta)):
+ *   R1 constant micromodulus c = 18K/(pi delta^4) and s0 = sqrt(5 Gc/(9 K delta))
+ *      (conic, PDREF_CONIC: c0 = 90K/(pi delta^4), s0 = sqrt(2 Gc/(3 K delta))):
  *      the values for which a uniform small strain reproduces the strain-energy
  *      density 9Ks^2/2 and breaking every bond across a unit area costs G_c
  *      (Sec. 3.1.1 states both calibrations; the 3-D row of its table carries a
@@ -103,17 +104,37 @@ struct pdref {
 /* constants                                                                 */
 /* ------------------------------------------------------------------------- */
 
+/* Sec. 3.1.1 and its table.  Calibrated (R1): the strain-energy density of a
+ * uniform stretch s, (1/2) int_H (1/2) c w(r) s^2 r dV = 9 K s^2 / 2, and the
+ * energy of all bonds across a unit area at s0 equal to G_c:
+ *   constant w = 1:          pi c delta^4 / 4  = 9K/2,  pi c s0^2 delta^5 / 10 = G_c;
+ *   conic    w = 1 - r/delta: pi c delta^4 / 20 = 9K/2,  pi c s0^2 delta^5 / 60 = G_c.
+ * PDREF_TABLE_LITERAL takes the printed 3-D rows instead (nu = 1/4, E = 3K(1-2nu)). */
 void pdref_constants(double K, double Gc, double delta, int32_t flags, double* c, double* s0) {
+  const int conic = (flags & PDREF_CONIC) != 0;
   if (flags & PDREF_TABLE_LITERAL) {
-    /* the table's 3-D constant row with nu = 1/4 and E = 3K(1-2nu) */
     double nu = 0.25;
     double E = 3.0 * K * (1.0 - 2.0 * nu);
-    *c = 12.0 * E / (PI * pow(delta, 4) * (1.0 - nu));
-    *s0 = sqrt(5.0 * PI * Gc / (12.0 * E * delta));
+    if (conic) {
+      /* 60 E (delta - r) / (pi delta^5 (1 - nu)) = c0 (1 - r/delta) */
+      *c = 60.0 * E / (PI * pow(delta, 4) * (1.0 - nu));
+      *s0 = sqrt(7.0 * PI * Gc / (12.0 * E * delta));
+    } else {
+      *c = 12.0 * E / (PI * pow(delta, 4) * (1.0 - nu));
+      *s0 = sqrt(5.0 * PI * Gc / (12.0 * E * delta));
+    }
+  } else if (conic) {
+    *c = 90.0 * K / (PI * pow(delta, 4));
+    *s0 = sqrt(2.0 * Gc / (3.0 * K * delta));
   } else {
     *c = 18.0 * K / (PI * pow(delta, 4));
     *s0 = sqrt(5.0 * Gc / (9.0 * K * delta));
   }
+}
+
+/* micromodulus weight w(|xi|) of a bond in grain g */
+static double bond_weight(const pdref* s, int32_t g, double l0) {
+  return (s->flags & PDREF_CONIC) ? 1.0 - l0 / (s->m * s->gh[g]) : 1.0;
 }
 
 double pdref_contact_stiffness(double k_a, double k_b, double eps) {
@@ -526,7 +547,7 @@ static int eval_force(pdref* s) {
       }
       double r = fabs(st / s0 - 1.0);
       if (r < margin) margin = r;
-      double coef = c * st * Vj / l;
+      double coef = c * bond_weight(s, g, l0) * st * Vj / l;
       for (int q = 0; q < 3; ++q) Fi[q] += coef * y[q];
     }
     /* repulsive contact with nodes of other grains, Sec. 3.2 */
@@ -777,7 +798,7 @@ void pdref_energy_density(const pdref* s, double* W) {
       double l = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
       double st = stretch(xi, eta, l0, l);
       /* micropotential 1/2 c s^2 |xi| per unit volume squared */
-      acc += 0.5 * s->gc[g] * st * st * l0 * s->gV[s->grain_of[j]];
+      acc += 0.5 * s->gc[g] * bond_weight(s, g, l0) * st * st * l0 * s->gV[s->grain_of[j]];
     }
     W[i] = 0.5 * acc;
   }

@@ -37,6 +37,7 @@ extern "C" {
 #define PDREF_TABLE_LITERAL 1 /* 3-D constants exactly as printed in the paper's table */
 #define PDREF_ABS_STRETCH 2   /* break when |s| > s0 (the paper's prose) instead of s > s0 */
 #define PDREF_CELL_LIST 4     /* contact candidates from a cell list instead of an O(N^2) scan */
+#define PDREF_CONIC 8         /* conic micromodulus c0 (1 - |xi|/delta) instead of a constant one */
 
 /* packed wall record (15 doubles):
  *   nx ny nz offset velocity lox loy loz hix hiy hiz mode target_stress servo_gain area */
@@ -49,7 +50,7 @@ extern "C" {
 
 typedef struct pdref pdref;
 
-/* constants of the constant-micromodulus 3-D row: c [N/m^6] and s0 */
+/* 3-D micromodulus constants: c [N/m^6] (c0 of the conic form with PDREF_CONIC) and s0 */
 void pdref_constants(double K, double Gc, double delta, int32_t flags, double* c, double* s0);
 /* K_n = 18 k_eff / (pi eps^5), k_eff = 2 k_a k_b / (k_a + k_b) */
 double pdref_contact_stiffness(double k_a, double k_b, double eps);

@@ -18,6 +18,7 @@ LIB = os.path.join(HERE, "libpdref.so")
 TABLE_LITERAL = 1
 ABS_STRETCH = 2
 CELL_LIST = 4
+CONIC = 8
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC",
           "-shared", "-Wall"]
@@ -119,6 +120,8 @@ class Oracle:
 
     def __init__(self, wl, flags: int = 0, threads: int = 1, build_now: bool = True):
         L = lib()
+        if getattr(wl.params, "micromodulus", "constant") == "conic":
+            flags |= CONIC
         self.wl = wl
         self.n = wl.n_nodes
         p = wl.params

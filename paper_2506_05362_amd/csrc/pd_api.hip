@@ -172,14 +172,22 @@ pd_status alloc_n(pd_ctx* c, T** out, int64_t count, const char* what) {
     if (s_ != PD_OK) return s_;   \
   } while (0)
 
+// 3-D micromodulus constants (Sec. 3.1.1 and its table): c, or c0 of the conic
+// form c0 (1 - |xi|/delta), and the critical stretch s0.
 void micro_constants(double K, double Gc, double delta, int flags, double* c, double* s0) {
+  const bool conic = (flags & PD_FLAG_CONIC) != 0;
+  const double d4 = delta * delta * delta * delta;
   if (flags & PD_FLAG_TABLE_LITERAL) {
     const double nu = 0.25, E = 3.0 * K * (1.0 - 2.0 * nu);
-    *c = 12.0 * E / (kPi * delta * delta * delta * delta * (1.0 - nu));
-    *s0 = sqrt(5.0 * kPi * Gc / (12.0 * E * delta));
+    *c = (conic ? 60.0 : 12.0) * E / (kPi * d4 * (1.0 - nu));
+    *s0 = sqrt((conic ? 7.0 : 5.0) * kPi * Gc / (12.0 * E * delta));
+  } else if (conic) {
+    // energy-consistent: pi c0 delta^4 / 20 = 9K/2 and pi c0 s0^2 delta^5 / 60 = G_c
+    *c = 90.0 * K / (kPi * d4);
+    *s0 = sqrt(2.0 * Gc / (3.0 * K * delta));
   } else {
-    // energy-consistent 3-D constants: pi c delta^4 / 4 = 9K/2 and pi c s0^2 delta^5 / 10 = G_c
-    *c = 18.0 * K / (kPi * delta * delta * delta * delta);
+    // energy-consistent: pi c delta^4 / 4 = 9K/2 and pi c s0^2 delta^5 / 10 = G_c
+    *c = 18.0 * K / (kPi * d4);
     *s0 = sqrt(5.0 * Gc / (9.0 * K * delta));
   }
 }
@@ -680,7 +688,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     return fail(c, PD_ERR_INVALID, "contact_damping must be finite and >= 0");
   if (!(P.friction >= 0) || !isfinite(P.friction))
     return fail(c, PD_ERR_INVALID, "friction must be finite and >= 0");
-  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH))
+  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH | PD_FLAG_CONIC))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
 
@@ -729,6 +737,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     GrainC& gc = c->grains_h[g];
     gc.V = h * h * h;
     gc.cVih = cc * gc.V / h;
+    gc.conic_inv_delta = (P.flags & PD_FLAG_CONIC) ? 1.0 / delta : 0.0;
     // break tests on |y|^2 - |xi|^2 against |xi|^2 ((1 +- s0)^2 - 1), |xi|^2 = h^2 |d|^2
     gc.thr = h * h * s0 * (2.0 + s0);
     gc.abs_ratio = (2.0 - s0) / (2.0 + s0);
@@ -775,8 +784,10 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     for (int32_t k = 0; k < c->n_stencil; ++k) {
       const double d2 = (double)(sd[3 * k] * sd[3 * k] + sd[3 * k + 1] * sd[3 * k + 1] + sd[3 * k + 2] * sd[3 * k + 2]);
       const double l0 = h * sqrt(d2), l0sq = h * h * d2;
+      // micromodulus weight: 1, or 1 - |xi|/delta for the conic form
+      const double w = (P.flags & PD_FLAG_CONIC) ? 1.0 - l0 / (P.horizon_factor * h) : 1.0;
       st.push_back(StencilC{h * sd[3 * k], h * sd[3 * k + 1], h * sd[3 * k + 2], l0sq * s0 * (2.0 + s0),
-                            1.0 / l0sq, cV / l0, l0, l0sq});
+                            1.0 / l0sq, cV * w / l0, l0, l0sq});
     }
     // zero-force class: xi = 0, x = 0, c V / |xi| = 0 (broken bonds, padding)
     st.push_back(StencilC{0.0, 0.0, 0.0, 1.0, 0.0, 0.0, 1.0, 1.0});

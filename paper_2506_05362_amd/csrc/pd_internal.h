@@ -27,7 +27,8 @@ constexpr int kUnroll = PD_BOND_UNROLL;  // bond entries in flight per lane; sli
 
 // per-grain constants
 struct GrainC {
-  double cVih;    // c * V / h (micromodulus times nodal volume, over the lattice spacing)
+  double cVih;    // c * V / h (micromodulus, or c0 of the conic form, times nodal volume, over h)
+  double conic_inv_delta;  // 1/delta with the conic micromodulus c0 (1 - |xi|/delta), else 0
   double thr;     // h^2 s0 (2 + s0): bond breaks when |y|^2 - |xi|^2 > thr * |d|^2  (s > s0)
   double abs_ratio;  // (2 - s0) / (2 + s0): with the |s| reading a bond also breaks when
                      // |y|^2 - |xi|^2 < -abs_ratio * thr * |d|^2  (s < -s0)

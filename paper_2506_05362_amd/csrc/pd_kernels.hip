@@ -1080,7 +1080,8 @@ __global__ __launch_bounds__(kBlock) void k_energy(StepArgs A, double* partial4)
       const double l0 = sqrt(xx * xx + xy * xy + xz * xz), l = sqrt(yx * yx + yy * yy + yz * yz);
       const double dd = ex * (2.0 * xx + ex) + ey * (2.0 * xy + ey) + ez * (2.0 * xz + ez);
       const double st = dd / (l0 * (l + l0));
-      w += 0.5 * (G->cVih * G->h) * st * st * l0;  // micropotential times V_j
+      // micropotential 1/2 c w(|xi|) s^2 |xi| times V_j
+      w += 0.5 * (G->cVih * G->h) * (1.0 - l0 * G->conic_inv_delta) * st * st * l0;
     }
     e[1] = 0.5 * V * w;
     if (A.cand_ptr != nullptr) {

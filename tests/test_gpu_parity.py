@@ -376,3 +376,26 @@ def test_large_aggregate_small_instance_matches_oracle(oracle_lib):
         assert_state_close(sim, ora, what=f"bond path {bp}")
         assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
         sim.close()
+
+
+def test_conic_micromodulus_matches_oracle(oracle_lib):
+    """Fracturing sphere collision with the conic micromodulus (Sec. 3.1.1, second
+    row of the table): state 1e-9, broken-bond set and stored energy equal, with
+    both bond paths."""
+    from paper_2506_05362_amd import pd
+    wl = I.two_spheres(radius_cells=6, speed=50.0, gap=0.0, rebuild_every=7)
+    wl.params.micromodulus = "conic"
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    ora.step(80)
+    eo = ora.energy()
+    for bp in (pd.BONDS_SLICES, pd.BONDS_TILES):
+        sim = gpu_sim(wl)
+        sim.set_launch(bond_path=bp)
+        sim.step(80)
+        assert_state_close(sim, ora, what=f"conic, bond path {bp}")
+        # broken sets bit-exact where no stretch came within 1e-9 of s0
+        assert_bonds_equal(sim, ora, broken=ora.min_margin() > 1e-9)
+        assert sim.bonds()[2].any()
+        eg = sim.get("energy")
+        assert eg[1] == pytest.approx(eo["elastic"], rel=1e-9)
+        sim.close()

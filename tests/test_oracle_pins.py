@@ -528,3 +528,66 @@ def test_contact_friction_slip_stick_and_momentum(oracle_lib):
         v = o.state()["v"]
         assert np.all(np.abs(v[:, 0] + v[:, 1]) <= 1e-12 * p0 / (I.SAND.density * h ** 3))
     assert v[1, 0] - v[1, 1] < 2.0  # the relative sliding slowed down
+
+
+# ---------------------------------------------------------------------------
+# conic micromodulus c0 (1 - |xi|/delta) (the table's second row, Sec. 3.1.1)
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("m", [3, 6, 10])
+def test_conic_uniform_strain_energy_converges_to_continuum(oracle_lib, m):
+    """u = s X: energy density over 9Ks^2/2 equals the lattice quadrature of the
+    weighted shell, 5 sum |d| (1 - |d|/m) / (pi m^4), which tends to 1 (the
+    continuum integral pi c0 s^2 delta^4 / 20 = 9K s^2/2 fixes c0 = 90K/(pi delta^4))."""
+    s = 1e-4
+    wl = ball_workload(m, m, u0_fn=lambda X: s * X)
+    wl.params.micromodulus = "conic"
+    W = oracle_lib.Oracle(wl).energy_density()
+    centre = np.where((wl.ijk == m).all(axis=0))[0][0]
+    ratio = W[centre] / (9.0 * wl.materials[0].bulk_modulus * s * s / 2.0)
+    dl = lattice_shell(m)[3]
+    assert ratio == pytest.approx(5.0 * float((dl * (1.0 - dl / m)).sum()) / (math.pi * m ** 4), rel=1e-9)
+    if m >= 6:
+        assert abs(ratio - 1.0) < 2e-3
+
+
+@pytest.mark.parametrize("m", [6, 10, 20])
+def test_conic_fracture_energy_calibration(oracle_lib, m):
+    """Energy to break every bond across a unit area with the conic weight,
+    1/2 c0 s0^2 h^5 sum_{dz>0} dz |d| (1 - |d|/m), tends to G_c (continuum
+    pi c0 s0^2 delta^5 / 60 = G_c)."""
+    K, Gc, h = 14.9e9, 10.0, 1e-4
+    c0, s0 = oracle_lib.constants(K, Gc, m * h, oracle_lib.CONIC)
+    _, _, dz, dl = lattice_shell(m)
+    S = float((np.where(dz > 0, dz, 0) * dl * (1.0 - dl / m)).sum())
+    G_lat = 0.5 * c0 * s0 * s0 * h ** 5 * S
+    assert abs(G_lat / Gc - 1.0) < (0.012 if m == 6 else 0.005)
+
+
+def test_conic_printed_row_carries_the_same_extra_factor(oracle_lib):
+    """Without its (1-nu) factor the printed conic row, 60E(delta - r)/(pi delta^5),
+    is the calibrated c0 (1 - r/delta); with it, 4/3 times that, as in the constant row."""
+    K, Gc, delta = 14.9e9, 10.0, 3e-4
+    c0, _ = oracle_lib.constants(K, Gc, delta, oracle_lib.CONIC)
+    cl, _ = oracle_lib.constants(K, Gc, delta, oracle_lib.CONIC | oracle_lib.TABLE_LITERAL)
+    E = 1.5 * K  # nu = 1/4
+    assert c0 == pytest.approx(60.0 * E / (math.pi * delta ** 4), rel=1e-12)
+    assert cl / c0 == pytest.approx(4.0 / 3.0, rel=1e-12)
+
+
+def test_conic_two_node_bond_force(oracle_lib):
+    """One bond of length |d| h: force c0 (1 - |d|/m) s V along the bond, for each
+    shell radius |d| = 1, 2, 3 (the constant micromodulus gives c s V)."""
+    h = 1e-4
+    for cells in (1, 2, 3):
+        st = 2e-4
+        wl = two_node(stretch=st, along=1, dist_cells=cells)
+        wl.params.micromodulus = "conic"
+        F = oracle_lib.Oracle(wl).state()["F"]
+        K = wl.materials[0].bulk_modulus
+        c0 = 90 * K / (math.pi * (3 * h) ** 4)
+        expect = c0 * (1.0 - cells / 3.0) * st * h ** 3
+        if cells < 3:
+            assert F[1, 0] == pytest.approx(expect, rel=1e-9)
+        else:
+            assert F[1, 0] == 0.0  # the weight vanishes at the horizon
