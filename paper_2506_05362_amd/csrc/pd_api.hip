@@ -1267,6 +1267,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
     case PD_ACCEL: return soa_from_dev(c->a);
     case PD_FORCE_DENSITY: {
       if (!c->F) TRY(alloc_n(c, &c->F, 3 * N, "force output"));
+      TRY(sync_columns(c));  // the force-only pass reads the bond memory from the column words
       StepArgs A = step_args(c);
       HIPCHK(c, launch_step(A, MODE_FORCE_ONLY, s));
       return soa_from_dev(c->F);

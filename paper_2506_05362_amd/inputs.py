@@ -618,6 +618,104 @@ def large_aggregate(seed: int = 0, n_grains: int = 1000, mean_radius: float = 0.
 
 
 # ----------------------------------------------------------------------------
+# shape study: 125 grains of one shape on a cubic grid, compressed by the lid
+# ----------------------------------------------------------------------------
+
+SHAPES = ("sphere", "shell", "jack")
+
+
+def _rotation(rng: np.random.Generator) -> np.ndarray:
+    """A uniformly distributed rotation (normalised Gaussian quaternion)."""
+    q = rng.normal(size=4)
+    w, x, y, z = q / np.linalg.norm(q)
+    return np.array([[1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y)],
+                     [2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x)],
+                     [2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)]])
+
+
+def shape_grain(rng: np.random.Generator, shape: str, radius: float, h: float,
+                arm_half_width: float = 0.25, cavity: float = 0.5):
+    """Lattice points of one grain of the shape study, all within the ball of
+    the given radius about the grain centre.
+
+    sphere: the ball; shell: the ball less a concentric cavity of cavity*radius;
+    jack: three orthogonal square bars of half-width arm_half_width*radius
+    through the centre, clipped to the ball, in a seeded random orientation.
+    Every grain gets a seeded sub-cell lattice offset.  Returns (offsets (3,n)
+    int, centre-relative lattice shift (3,), cavity radius or 0)."""
+    if shape not in SHAPES:
+        raise ValueError(f"unknown shape {shape!r}")
+    o = rng.uniform(0.0, 1.0, size=3)
+    rot = _rotation(rng) if shape == "jack" else None
+    nmax = int(math.ceil(radius / h)) + 1
+    r = np.arange(-nmax, nmax + 1)
+    I, J, K = np.meshgrid(r, r, r, indexing="ij")
+    pts = np.stack([I.ravel(), J.ravel(), K.ravel()])
+    q = (pts + o[:, None]) * h
+    d2 = np.sum(q * q, axis=0)
+    inside = d2 <= radius * radius
+    rin = 0.0
+    if shape == "shell":
+        rin = cavity * radius
+        inside &= d2 >= rin * rin
+    elif shape == "jack":
+        a = arm_half_width * radius
+        body = np.abs(rot.T @ q) <= a  # coordinates in the jack's own frame
+        inside &= np.sum(body, axis=0) >= 2  # inside at least one bar
+    return pts[:, inside], o, rin
+
+
+def shape_study(shape: str = "sphere", seed: int = 0, grid: int = 5, radius: float = 1e-3,
+                h: float = 1e-4, gap: float = 1.0, lid_speed: float = 10.0, dt: float = 1e-8,
+                duration: float = 5e-4, material: Material = SAND, rebuild_every: int = 5,
+                arm_half_width: float = 0.25, cavity: float = 0.5) -> Workload:
+    """grid^3 grains of one shape (Sec. 7.6: 125 grains of radius 1 mm on a
+    cubic grid, solid spheres, hollow spheres or jacks) in a box of rigid walls
+    whose lid moves down at lid_speed (10 m/s in the paper).
+
+    Grid pitch 2*radius + gap*h; the floor and the four side walls sit R_c
+    beyond the outermost nodes, the lid R_c above the highest node, so no node
+    touches a wall at t = 0.  Shell cavities are cut with the chord rule.
+    steps cover duration (the paper plots 100 x 5 us)."""
+    rng = np.random.default_rng(seed)
+    params = default_params(h, dt, rebuild_every=rebuild_every)
+    pitch = 2.0 * radius + gap * h
+    blocks, cuts = [], []
+    for g in range(grid ** 3):
+        a, b, c = g % grid, (g // grid) % grid, g // (grid * grid)
+        centre = np.array([a, b, c], dtype=np.float64) * pitch
+        off, o, rin = shape_grain(rng, shape, radius, h, arm_half_width, cavity)
+        ijk, origin = _grain_block(off, centre + o * h, h)
+        blocks.append((ijk, origin, h, 0))
+        if rin > 0:
+            ijk_c = (centre - origin) / h
+            cen_half = np.rint(2.0 * ijk_c).astype(np.int64)
+            r_half = 2.0 * rin / h - 1.0  # stays inside the unmeshed cavity after rounding
+            cuts.append(Cut(kind=CUT_CAVITY_CHORD, grain=g, center=tuple(int(v) for v in cen_half),
+                            radius2=int(math.floor(r_half * r_half))))
+    steps = int(math.ceil(duration / dt))
+    wl = _assemble(f"shape_study_{shape}", blocks, [material], params, [], cuts, steps,
+                   info={"seed": seed, "shape": shape, "grid": grid, "radius": radius, "pitch": pitch})
+    Rc = params.contact_radius
+    lo = wl.X.min(axis=1) - Rc
+    hi = wl.X.max(axis=1) + Rc
+    span = hi - lo
+    area = [span[1] * span[2], span[0] * span[2], span[0] * span[1]]
+    wl.walls = [
+        Wall(normal=(0.0, 0.0, 1.0), offset=lo[2], mode=WALL_FIXED, area=area[2]),
+        Wall(normal=(0.0, 0.0, -1.0), offset=-hi[2], mode=WALL_VELOCITY, velocity=lid_speed, area=area[2]),
+    ]
+    for ax in (0, 1):
+        for sgn in (1.0, -1.0):
+            nrm = [0.0, 0.0, 0.0]
+            nrm[ax] = sgn
+            wl.walls.append(Wall(normal=tuple(nrm), offset=lo[ax] if sgn > 0 else -hi[ax], mode=WALL_FIXED,
+                                 area=area[ax]))
+    wl.info.update({"span0": span.tolist(), "lid_speed": lid_speed})
+    return wl
+
+
+# ----------------------------------------------------------------------------
 # named workloads with the sizes of the paper-scale experiments
 # ----------------------------------------------------------------------------
 
@@ -635,4 +733,6 @@ def workload(name: str, **kw) -> Workload:
         return rve_aggregate(**kw)
     if name == "large_aggregate":
         return large_aggregate(**kw)
+    if name == "shape_study":
+        return shape_study(**kw)
     raise KeyError(name)

@@ -399,3 +399,28 @@ def test_conic_micromodulus_matches_oracle(oracle_lib):
         eg = sim.get("energy")
         assert eg[1] == pytest.approx(eo["elastic"], rel=1e-9)
         sim.close()
+
+
+@pytest.mark.parametrize("shape", ["sphere", "shell", "jack"])
+def test_shape_study_small_instance_matches_oracle(oracle_lib, shape):
+    """Shape-study aggregate (Sec. 7.6) at 2 x 2 x 2 grains of radius 5 h, lid at
+    50 m/s so it meets the top layer and drives it into the bottom one within
+    the run: state 1e-9, wall forces 1e-6, with both bond paths (shells carry
+    friction, so the stick-slip law runs at wall and grain contacts too)."""
+    from paper_2506_05362_amd import pd
+    wl = I.shape_study(shape, seed=3, grid=2, radius=5e-4, h=1e-4, lid_speed=50.0, duration=1e-5)
+    wl.params.skin = 0.5 * wl.grain_h[0]
+    wl.params.contact_damping = 1e21
+    if shape == "shell":
+        wl.params.friction = 0.3
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    assert ora.step(wl.steps) == 0
+    fo, _ = ora.walls()
+    assert np.abs(fo[1]).max() > 0 and np.abs(fo[0]).max() > 0  # lid and floor both loaded
+    for bp in (pd.BONDS_SLICES, pd.BONDS_TILES):
+        sim = gpu_sim(wl)
+        sim.set_launch(bond_path=bp)
+        sim.step(wl.steps)
+        assert_state_close(sim, ora, what=f"{shape}, bond path {bp}")
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        sim.close()

@@ -9,7 +9,10 @@ from paper_2506_05362_amd import inputs as I
 
 pytestmark = pytest.mark.gpu
 
-NODE_FIELDS = ["displacement", "velocity", "accel", "bond_broken", "intact_count", "damage", "step"]
+# force_density comes before any field whose read hands the bond memory over to
+# the column words, so it checks that its own read does
+NODE_FIELDS = ["displacement", "velocity", "accel", "force_density", "bond_broken", "intact_count", "damage",
+               "step"]
 
 
 def cases():
