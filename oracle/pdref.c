@@ -37,6 +37,15 @@
  *      node's own tangential relative velocity w_t (the prose; the printed
  *      e_perp(y,x) would push along it).  rho is the node's density; the
  *      velocities are the mid-step ones of R15; f_r excludes the damping term.
+ *   R18 self-contact (Sec. 5, PDREF_SELF_CONTACT): every pair of nodes of one
+ *      grain with no intact bond at the evaluation (broken in this or an
+ *      earlier evaluation, removed by a cut, or never in the horizon) and
+ *      current distance d < R_c repels.  Reference length |xi| < R_c: the
+ *      repulsive-only bond K_n R_c (|xi| - d)/|xi| for d < |xi|; otherwise the
+ *      contact spring K_n (R_c - d) (c_w = K_n R_c), both times V_j, with the
+ *      damping and friction of R15/R17 on top.  The paper's assumption
+ *      eps <= R_c is not needed for this case split and is not made.  With
+ *      self-contact the skin guard applies to a single grain as well.
  */
 #include "pdref.h"
 
@@ -413,6 +422,14 @@ static void ivec_push(ivec* a, int32_t x) {
   a->v[a->len++] = x;
 }
 
+/* pairs the contact search keeps: nodes of other grains, and with self-contact
+   every other node of the same grain (whether bonded is decided at the force) */
+static int contact_kind_pair(const pdref* s, int64_t i, int64_t j) {
+  if (j == i) return 0;
+  if (s->grain_of[j] != s->grain_of[i]) return 1;
+  return (s->flags & PDREF_SELF_CONTACT) != 0;
+}
+
 static void build_candidates(pdref* s) {
   const int64_t n = s->n;
   const double cut = s->Rc + s->skin, cut2 = cut * cut;
@@ -425,7 +442,7 @@ static void build_candidates(pdref* s) {
     for (int64_t i = 0; i < n; ++i) {
       s->cand_ptr[i] = out.len;
       for (int64_t j = 0; j < n; ++j) {
-        if (s->grain_of[j] == s->grain_of[i]) continue;
+        if (!contact_kind_pair(s, i, j)) continue;
         if (pair_dist2(s, i, j, y) < cut2) ivec_push(&out, (int32_t)j);
       }
     }
@@ -468,7 +485,7 @@ static void build_candidates(pdref* s) {
             int64_t cx = cidx[3 * i] + dx, cy = cidx[3 * i + 1] + dy, cz = cidx[3 * i + 2] + dz;
             if (cx < 0 || cy < 0 || cz < 0 || cx >= dim[0] || cy >= dim[1] || cz >= dim[2]) continue;
             for (int64_t j = head[(cx * dim[1] + cy) * dim[2] + cz]; j >= 0; j = next[j]) {
-              if (s->grain_of[j] == s->grain_of[i]) continue;
+              if (!contact_kind_pair(s, i, j)) continue;
               if (pair_dist2(s, i, j, y) < cut2) ivec_push(&out, (int32_t)j);
             }
           }
@@ -516,6 +533,21 @@ static void add_friction(double mu, double fr, double rho, double dt, const doub
   }
 }
 
+/* bond memory of the pair: 1 when j is in i's bond row and that bond is intact */
+static int bond_intact(const pdref* s, int64_t i, int64_t j) {
+  for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e)
+    if (s->col[e] == j) return !s->broken[e];
+  return 0;
+}
+
+/* reference distance |X_j - X_i| */
+static double self_ref_length(const pdref* s, int64_t i, int64_t j) {
+  const int64_t n = s->n;
+  double xi[3];
+  for (int q = 0; q < 3; ++q) xi[q] = s->X[q * n + j] - s->X[q * n + i];
+  return sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
+}
+
 static int eval_force(pdref* s) {
   const int64_t n = s->n;
   const double Rc = s->Rc;
@@ -550,7 +582,8 @@ static int eval_force(pdref* s) {
       double coef = c * bond_weight(s, g, l0) * st * Vj / l;
       for (int q = 0; q < 3; ++q) Fi[q] += coef * y[q];
     }
-    /* repulsive contact with nodes of other grains, Sec. 3.2 */
+    /* repulsive contact with nodes of other grains, Sec. 3.2, and with nodes of
+       the same grain that have no intact bond to i, Sec. 5 (R18) */
     for (int64_t e = s->cand_ptr[i]; e < s->cand_ptr[i + 1]; ++e) {
       const int64_t j = s->cand[e];
       double y[3];
@@ -560,7 +593,16 @@ static int eval_force(pdref* s) {
       if (d == 0.0) continue;
       const int32_t gj = s->grain_of[j];
       double Kn = pdref_contact_stiffness(s->gK[g], s->gK[gj], s->eps);
-      double coef = -Kn * (Rc - d) * s->gV[gj] / d;
+      double fr = Kn * (Rc - d) * s->gV[gj]; /* repulsive force density, along -y/d */
+      if (gj == g) {
+        if (bond_intact(s, i, j)) continue;
+        double l0 = self_ref_length(s, i, j);
+        if (l0 < Rc) {
+          if (!(d < l0)) continue;
+          fr = Kn * Rc * (l0 - d) / l0 * s->gV[gj];
+        }
+      }
+      double coef = -fr / d;
       if (s->beta > 0.0) {
         /* normal damping, Sec. 3.4 (linear reading): -beta (w . e) e V_j with w the
            velocity of i relative to j and e = y/d pointing from i to j */
@@ -579,7 +621,7 @@ static int eval_force(pdref* s) {
           wn += w[q] * e[q];
         }
         for (int q = 0; q < 3; ++q) wt[q] = w[q] - wn * e[q];
-        add_friction(s->mu, Kn * (Rc - d) * s->gV[gj], s->grho[g], s->dt, wt, Fi);
+        add_friction(s->mu, fr, s->grho[g], s->dt, wt, Fi);
       }
     }
     for (int q = 0; q < 3; ++q) {
@@ -706,8 +748,9 @@ int32_t pdref_step(pdref* s, int64_t nsteps) {
     s->step += 1;
     advance_walls(s);
     if (s->step % s->rebuild_every == 0) {
-      /* the skin guard protects inter-grain pairs; a single grain has none to miss */
-      if (s->n_grains > 1 && skin_exceeded(s)) bad = 1;
+      /* the skin guard protects contact pairs; a single grain without
+         self-contact has none to miss */
+      if ((s->n_grains > 1 || (s->flags & PDREF_SELF_CONTACT)) && skin_exceeded(s)) bad = 1;
       build_candidates(s);
     }
     /* new accelerations at the new positions, then the velocity update; the
@@ -825,8 +868,15 @@ void pdref_energy(const pdref* s, double* out4) {
       double d = sqrt(d2);
       const int32_t gj = s->grain_of[j];
       double Kn = pdref_contact_stiffness(s->gK[g], s->gK[gj], s->eps);
-      /* pair potential 1/2 K_n (R_c - d)^2, each pair seen from both ends */
-      ct += 0.5 * V * 0.5 * Kn * (s->Rc - d) * (s->Rc - d) * s->gV[gj];
+      /* pair potential 1/2 K_n (R_c - d)^2, each pair seen from both ends; the
+         repulsive-only bond of a short same-grain pair 1/2 K_n R_c (|xi| - d)^2 / |xi| */
+      double pot = 0.5 * Kn * (s->Rc - d) * (s->Rc - d);
+      if (gj == g) {
+        if (bond_intact(s, i, j)) continue;
+        double l0 = self_ref_length(s, i, j);
+        if (l0 < s->Rc) pot = d < l0 ? 0.5 * Kn * s->Rc * (l0 - d) * (l0 - d) / l0 : 0.0;
+      }
+      ct += 0.5 * V * pot * s->gV[gj];
     }
   }
   free(W);

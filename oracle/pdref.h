@@ -15,7 +15,9 @@
  *   - damage 1 - intact/initial (Sec. 3.1.1);
  *   - repulsive contact -K_n (R_c - |p_y - p_x|) e between nodes of different
  *     grains (Sec. 3.2 eq. (repulsive-force)), K_n = 18 k / (pi eps^5) with the
- *     harmonic-mean bulk modulus;
+ *     harmonic-mean bulk modulus; with PDREF_SELF_CONTACT the same law (and a
+ *     repulsive-only bond for pairs shorter than R_c) between nodes of one grain
+ *     that have no intact bond (Sec. 5);
  *   - normal contact damping (Sec. 3.4 eq. (damping-force)) and regularised
  *     stick-slip friction (Sec. 3.3 eq. (regularized-friction)) on the mid-step
  *     velocity, between grains and against walls;
@@ -38,6 +40,7 @@ extern "C" {
 #define PDREF_ABS_STRETCH 2   /* break when |s| > s0 (the paper's prose) instead of s > s0 */
 #define PDREF_CELL_LIST 4     /* contact candidates from a cell list instead of an O(N^2) scan */
 #define PDREF_CONIC 8         /* conic micromodulus c0 (1 - |xi|/delta) instead of a constant one */
+#define PDREF_SELF_CONTACT 16 /* contact between nodes of one grain with no intact bond (Sec. 5) */
 
 /* packed wall record (15 doubles):
  *   nx ny nz offset velocity lox loy loz hix hiy hiz mode target_stress servo_gain area */

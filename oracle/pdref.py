@@ -19,6 +19,7 @@ TABLE_LITERAL = 1
 ABS_STRETCH = 2
 CELL_LIST = 4
 CONIC = 8
+SELF_CONTACT = 16
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC",
           "-shared", "-Wall"]
@@ -122,6 +123,8 @@ class Oracle:
         L = lib()
         if getattr(wl.params, "micromodulus", "constant") == "conic":
             flags |= CONIC
+        if getattr(wl.params, "self_contact", False):
+            flags |= SELF_CONTACT
         self.wl = wl
         self.n = wl.n_nodes
         p = wl.params

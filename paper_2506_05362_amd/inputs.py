@@ -76,6 +76,7 @@ class Params:
     contact_damping: float = 0.0  # beta_d of the normal damping law [N s/m^7]; 0 = none
     friction: float = 0.0  # mu of the stick-slip friction law; 0 = none
     micromodulus: str = "constant"  # "constant" or "conic" (c0 (1 - |xi|/delta))
+    self_contact: bool = False  # contact between nodes of one grain with no intact bond
 
 
 @dataclasses.dataclass

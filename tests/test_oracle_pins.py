@@ -591,3 +591,130 @@ def test_conic_two_node_bond_force(oracle_lib):
             assert F[1, 0] == pytest.approx(expect, rel=1e-9)
         else:
             assert F[1, 0] == 0.0  # the weight vanishes at the horizon
+
+
+# ---------------------------------------------------------------------------
+# self-contact inside a grain (Sec. 5)
+# ---------------------------------------------------------------------------
+
+def _self_pair(h, dist_cells, d, self_contact, same_grain=True, Rc=None, v_rel=0.0, mu=0.0, beta=0.0):
+    """Two nodes dist_cells h apart along x (one grain, or two one-node grains),
+    node 1 moved so that the pair is d apart; relative velocity v_rel along y."""
+    wl = two_node(h=h, dist_cells=dist_cells, same_grain=same_grain)
+    wl.params.self_contact = self_contact
+    wl.params.friction, wl.params.contact_damping = mu, beta
+    if Rc is not None:
+        wl.params.contact_radius = Rc
+    wl.u0[0, 1] = d - dist_cells * h
+    wl.v0[1, 0], wl.v0[1, 1] = 0.5 * v_rel, -0.5 * v_rel
+    return wl
+
+
+def test_self_contact_of_an_unbonded_pair_is_the_grain_contact_law(oracle_lib):
+    """A same-grain pair beyond the horizon (no bond) closer than R_c: without
+    self-contact no force; with it exactly the force two one-node grains in the
+    same places feel (repulsion K_n (R_c - d) V_j, damping and friction), which
+    is -K_n (R_c - d) h^3 along the pair without velocities."""
+    h = 1e-4
+    Rc = 0.95 * h
+    d = 0.6 * Rc
+    off = oracle_lib.Oracle(_self_pair(h, 4, d, False)).state()["F"]
+    assert np.all(off == 0.0)
+    on = oracle_lib.Oracle(_self_pair(h, 4, d, True)).state()["F"]
+    K = I.SAND.bulk_modulus
+    Kn = 18 * K / (math.pi * (3 * h) ** 5)
+    assert on[0, 0] == pytest.approx(-Kn * (Rc - d) * h ** 3, rel=1e-12)
+    assert on[0, 1] == pytest.approx(Kn * (Rc - d) * h ** 3, rel=1e-12)
+    kw = dict(v_rel=3.0, mu=0.4, beta=1e21)
+    on = oracle_lib.Oracle(_self_pair(h, 4, d, True, **kw)).state()["F"]
+    two = oracle_lib.Oracle(_self_pair(h, 4, d, False, same_grain=False, **kw)).state()["F"]
+    assert np.abs(two[1]).max() > 0  # friction acts
+    assert np.allclose(on, two, rtol=1e-14, atol=0.0)
+
+
+def test_self_contact_of_a_broken_bond(oracle_lib):
+    """A bonded pair one spacing apart: pulled past s0 its bond breaks; pushed
+    back to d < R_c it then repels with the contact law (|xi| = h > R_c).  An
+    intact bond pushed to the same distance feels its bond force only."""
+    h = 1e-4
+    Rc = 0.95 * h
+    d = 0.7 * Rc
+    for sc in (False, True):
+        wl = _self_pair(h, 1, 1.5 * h, sc)  # stretch 0.5: far past s0
+        o = oracle_lib.Oracle(wl)
+        rp, col, br = o.bonds()
+        assert br.all()
+        u = o.state()["u"]
+        u[0, 1] = d - h
+        o.set_u(u)
+        o.step(1)  # a = 0 after the break, so u stays; the force is evaluated at d
+        F = o.state()["F"]
+        if not sc:
+            assert np.all(F == 0.0)
+        else:
+            Kn = 18 * I.SAND.bulk_modulus / (math.pi * (3 * h) ** 5)
+            assert F[0, 0] == pytest.approx(-Kn * (Rc - d) * h ** 3, rel=1e-12)
+    # intact bond compressed to d: self-contact adds nothing
+    Fs = []
+    for sc in (False, True):
+        o = oracle_lib.Oracle(_self_pair(h, 1, h, sc))
+        u = o.state()["u"]
+        u[0, 1] = d - h
+        o.set_u(u)
+        o.step(1)
+        assert not o.bonds()[2].any()
+        Fs.append(o.state()["F"])
+    assert np.array_equal(Fs[0], Fs[1]) and Fs[0][0, 0] < 0
+
+
+def test_self_contact_short_pair_is_a_repulsive_only_bond(oracle_lib):
+    """With R_c = 1.5 h a broken bond of length h is shorter than R_c: it repels
+    as a compression-only bond K_n R_c (|xi| - d)/|xi| V_j for d < |xi| and not
+    at all for |xi| <= d < R_c, where the contact spring would still push."""
+    h = 1e-4
+    Rc = 1.5 * h
+    Kn = 18 * I.SAND.bulk_modulus / (math.pi * (3 * h) ** 5)
+    for d, expect in ((0.8 * h, Kn * Rc * (h - 0.8 * h) / h * h ** 3), (1.2 * h, 0.0)):
+        o = oracle_lib.Oracle(_self_pair(h, 1, 1.5 * h, True, Rc=Rc))
+        assert o.bonds()[2].all()
+        u = o.state()["u"]
+        u[0, 1] = d - h
+        o.set_u(u)
+        o.step(1)
+        F = o.state()["F"]
+        assert F[0, 0] == pytest.approx(-expect, rel=1e-12, abs=0.0)
+        assert F[0, 1] == pytest.approx(expect, rel=1e-12, abs=0.0)
+    # the contact spring at d = 1.2 h (two grains) does push
+    o = oracle_lib.Oracle(_self_pair(h, 1, 1.2 * h, False, same_grain=False, Rc=Rc))
+    assert o.state()["F"][0, 0] == pytest.approx(-Kn * (Rc - 1.2 * h) * h ** 3, rel=1e-12)
+
+
+def test_self_contact_conserves_momentum_in_a_shattered_grain(oracle_lib):
+    """A ball whose bonds a large random displacement field has broken (in
+    tension and, with |s| > s0, in compression, so that broken pairs sit closer
+    than R_c), with random velocities, damping and friction: self-contact forces
+    act (the force field differs from the one without them) and are equal and
+    opposite, so sum V F = 0 and the total momentum stays constant over steps."""
+    h = 1e-4
+    rng = np.random.default_rng(11)
+    fields = {}
+    for sc in (False, True):
+        wl = ball_workload(4, 3, h=h)
+        wl.u0[:] = rng.uniform(-0.35 * h, 0.35 * h, size=wl.u0.shape) if not fields else fields["u0"]
+        wl.v0[:] = rng.uniform(-1.0, 1.0, size=wl.v0.shape) if not fields else fields["v0"]
+        fields.setdefault("u0", wl.u0.copy())
+        fields.setdefault("v0", wl.v0.copy())
+        wl.params.self_contact = sc
+        wl.params.friction, wl.params.contact_damping = 0.3, 1e21
+        wl.params.skin = 2 * h
+        o = oracle_lib.Oracle(wl, flags=oracle_lib.ABS_STRETCH)
+        F = o.state()["F"]
+        fields[sc] = F
+        if sc:
+            scale = np.abs(F).sum(axis=1).max()
+            assert np.abs(F.sum(axis=1)).max() <= 1e-12 * scale
+            p0 = wl.v0.sum(axis=1)
+            o.step(40)
+            assert o.step_count == 40
+            assert np.abs(o.state()["v"].sum(axis=1) - p0).max() <= 1e-10 * np.abs(wl.v0).sum()
+    assert np.abs(fields[True] - fields[False]).max() > 1e-3 * np.abs(fields[True]).max()
