@@ -89,11 +89,19 @@ enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 
        PD_FLAG_ABS_STRETCH = 2,   /* break on |s| > s0 instead of s > s0 */
        PD_FLAG_NO_GRAPH = 4,      /* launch every step's kernels directly instead of replaying
                                      a captured HIP graph of rebuild_every steps */
-       PD_FLAG_CONIC = 8          /* conic micromodulus c0 (1 - |xi|/delta) (the table's second row,
+       PD_FLAG_CONIC = 8,         /* conic micromodulus c0 (1 - |xi|/delta) (the table's second row,
                                      Sec. 3.1.1): c0 = 90K/(pi delta^4), s0 = sqrt(2 G_c/(3 K delta)),
                                      the values for which a uniform stretch has energy 9Ks^2/2 and
                                      breaking the bonds across a unit area costs G_c; with
-                                     PD_FLAG_TABLE_LITERAL the printed row */ };
+                                     PD_FLAG_TABLE_LITERAL the printed row */
+       PD_FLAG_SELF_CONTACT = 16  /* self-contact (Sec. 5): nodes of one grain with no intact bond
+                                     repel as nodes of different grains do (K_n (R_c - d) V_j with
+                                     damping and friction).  Pairs whose bond has broken are taken
+                                     from the bond memory at every evaluation; pairs never bonded
+                                     (outside the horizon or cut) join the contact candidates.
+                                     Requires contact_radius below every grain's lattice spacing
+                                     (so no pair is shorter than R_c), else PD_ERR_INVALID; the
+                                     skin guard then applies to a single grain too */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with

@@ -106,6 +106,9 @@ struct pd_ctx {
   int32_t* tmap = nullptr;
   StencilC* ttab = nullptr;
   int16_t* ctob = nullptr;  // [6][n_stencil]: slice-path class -> mask bit per axis order
+  // bond cuts, kept after the build for the self-contact search
+  CutDev* cuts = nullptr;
+  int32_t* cut_begin = nullptr;
   uint32_t* mask = nullptr;  // [kMaskWords][N]
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
@@ -220,6 +223,12 @@ pd_status check_wall(pd_ctx* c, const pd_wall& w, int k) {
   return PD_OK;
 }
 
+// the skin guard protects contact pairs; a single grain without self-contact
+// has none to miss
+int skin_guard(const pd_ctx* c) {
+  return (c->n_grains > 1 || (c->flags & PD_FLAG_SELF_CONTACT)) ? 1 : 0;
+}
+
 StepArgs step_args(pd_ctx* c) {
   StepArgs A{};
   A.ucur = c->u4[c->cur];
@@ -249,6 +258,9 @@ StepArgs step_args(pd_ctx* c) {
   A.colE = c->colE;
   A.sentinel_hi = c->sentinel_hi;
   A.intact = c->intact;
+  A.self_contact = (c->flags & PD_FLAG_SELF_CONTACT) ? 1 : 0;
+  A.colOrig = c->colOrig;
+  A.ctob = c->ctob;
   A.cand_ptr = c->cand_ptr;
   A.cand = c->cand;
   A.cand_capacity = c->capacity;
@@ -310,6 +322,10 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.inv_cell = 1.0 / (cut * 1.01);
   C.cut2 = cut * cut;
   C.skin_half2 = 0.25 * c->skin * c->skin;
+  C.self_contact = (c->flags & PD_FLAG_SELF_CONTACT) ? 1 : 0;
+  C.m2 = c->m * c->m;
+  C.cuts = c->cuts;
+  C.cut_begin = c->cut_begin;
   return C;
 }
 
@@ -319,8 +335,7 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
     ContactArgs C = contact_args(c, nxt);
-    // the skin guard protects inter-grain pairs; with one grain there are none to miss
-    HIPCHK(c, launch_contact_rebuild(C, c->n_grains > 1 ? 1 : 0, c->stream));
+    HIPCHK(c, launch_contact_rebuild(C, skin_guard(c), c->stream));
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
@@ -360,7 +375,7 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
   const int64_t k = std::min<int64_t>(left, (s / R + 1) * R - s);
   if (s % R == 0) {
     ContactArgs C = contact_args(c, c->cur ^ 1);
-    HIPCHK(c, launch_contact_rebuild(C, c->n_grains > 1 ? 1 : 0, c->stream));
+    HIPCHK(c, launch_contact_rebuild(C, skin_guard(c), c->stream));
   }
   if (!c->barrier) TRY(alloc_n(c, &c->barrier, 2, "grid barrier"));
   HIPCHK(c, launch_fill_i32(reinterpret_cast<int32_t*>(c->barrier), 0, 2, c->stream));
@@ -688,7 +703,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
     return fail(c, PD_ERR_INVALID, "contact_damping must be finite and >= 0");
   if (!(P.friction >= 0) || !isfinite(P.friction))
     return fail(c, PD_ERR_INVALID, "friction must be finite and >= 0");
-  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH | PD_FLAG_CONIC))
+  if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH | PD_FLAG_CONIC |
+                  PD_FLAG_SELF_CONTACT))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
 
@@ -732,6 +748,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   for (int32_t g = 0; g < G; ++g) {
     const pd_material& mt = materials[grains->material[g]];
     const double h = grains->h[g], delta = P.horizon_factor * h;
+    if ((P.flags & PD_FLAG_SELF_CONTACT) && !(P.contact_radius < h))
+      return fail(c, PD_ERR_INVALID, "grain %d: self-contact needs the contact radius below the lattice spacing", g);
     double cc, s0;
     micro_constants(mt.bulk_modulus, mt.fracture_energy, delta, P.flags, &cc, &s0);
     GrainC& gc = c->grains_h[g];
@@ -1014,9 +1032,9 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   dev_free(c, gdim_d);
   dev_free(c, glo_d);
   dev_free(c, gmap_d);
-  dev_free(c, cut_begin_d);
+  c->cut_begin = cut_begin_d;
+  c->cuts = cuts_d;
   dev_free(c, stencil_d);
-  dev_free(c, cuts_d);
   dev_free(c, scan_scratch64);
 
   // contact structures

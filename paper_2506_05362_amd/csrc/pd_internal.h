@@ -167,6 +167,12 @@ struct StepArgs {
   const int32_t* tmap;
   const StencilC* ttab;
   uint32_t* mask;
+  // self-contact inside a grain (Sec. 5): the node's broken bonds are found
+  // from the built column words (colOrig) and, on the tiled path, the class
+  // masks through ctob ([6][n_stencil] slice class -> mask bit per axis order)
+  int32_t self_contact;
+  const uint32_t* colOrig;
+  const int16_t* ctob;
 };
 
 // grid barrier state of the persistent step kernel (zeroed before each launch)
@@ -225,6 +231,12 @@ struct ContactArgs {
   double inv_cell;
   double cut2;            // (R_c + skin)^2
   double skin_half2;
+  // self-contact: same-grain pairs that were never bonded (outside the horizon
+  // shell |d ijk|^2 <= m2, or removed by a cut) are candidates too
+  int32_t self_contact;
+  int32_t m2;
+  const CutDev* cuts;
+  const int32_t* cut_begin;  // [G+1]
 };
 
 // ---- launchers (pd_kernels.hip) ----

@@ -111,18 +111,22 @@ __device__ bool chord_cuts(const CutDev& c, const int64_t A[3], const int64_t B[
   return ww * dd - wd * wd < c.r2 * dd;
 }
 
-__device__ bool bond_cut(const BuildArgs& b, int g, int pi, int pj) {
-  const int c0 = b.cut_begin[g], c1 = b.cut_begin[g + 1];
+__device__ bool cut_between(const CutDev* cuts, const int32_t* cut_begin, int g, int pi, int pj) {
+  const int c0 = cut_begin[g], c1 = cut_begin[g + 1];
   if (c0 == c1) return false;
   const int64_t A[3] = {2 * (int64_t)unpack_x(pi), 2 * (int64_t)unpack_y(pi), 2 * (int64_t)unpack_z(pi)};
   const int64_t B[3] = {2 * (int64_t)unpack_x(pj), 2 * (int64_t)unpack_y(pj), 2 * (int64_t)unpack_z(pj)};
   for (int k = c0; k < c1; ++k) {
-    const CutDev& c = b.cuts[k];
+    const CutDev& c = cuts[k];
     if (c.kind == 0 && notch_cuts(c, A, B)) return true;
     if (c.kind == 1 && (sq_dist(A, c.c) < c.r2 || sq_dist(B, c.c) < c.r2)) return true;
     if (c.kind == 2 && chord_cuts(c, A, B)) return true;
   }
   return false;
+}
+
+__device__ __forceinline__ bool bond_cut(const BuildArgs& b, int g, int pi, int pj) {
+  return cut_between(b.cuts, b.cut_begin, g, pi, pj);
 }
 
 // node index at lattice point ijk + d of grain g, or -1
@@ -306,10 +310,57 @@ __device__ __forceinline__ NodeVA load_va(const StepArgs& A, int64_t i, bool val
   return r;
 }
 
+// Repulsion of node j on node i when closer than R_c (Sec. 3.2), with normal
+// damping (Sec. 3.4) and stick-slip friction (Sec. 3.3): between grains, and
+// between nodes of one grain without an intact bond (Sec. 5, where c_w / R_c
+// is the same K_n; self-contact needs R_c below the lattice spacing, so the
+// repulsive-only bond of pairs shorter than R_c never arises).
+__device__ __forceinline__ void contact_pair(const StepArgs& A, int j, double Xx, double Xy, double Xz,
+                                             const double4& ui, const double4& vhi, int mi, double rho_i,
+                                             bool damp, bool fric, double& fx, double& fy, double& fz) {
+  const double4 uj = A.ucur[j];
+  double yx, yy, yz;
+  const double d2 = contact_d2(A.X[j], Xx, uj.x, ui.x, A.X[A.n + j], Xy, uj.y, ui.y,
+                               A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
+  if (d2 < A.Rc2 && d2 > 0.0) {
+    const GrainC* Gj = A.grains + packed_grain(uj.w);
+    const double d = sqrt(d2);
+    const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
+    double coef = -rep / d;
+    double4 vhj = make_double4(0.0, 0.0, 0.0, 0.0);
+    if (damp || fric) vhj = A.vh_cur[j];
+    const double wx = vhi.x - vhj.x, wy = vhi.y - vhj.y, wz = vhi.z - vhj.z;
+    if (damp) {
+      // -beta (w . e) e V_j, w = velocity of i relative to j, e = y / d
+      const double w = wx * yx + wy * yy + wz * yz;
+      coef -= A.beta * Gj->V * w / d2;
+    }
+    fx = fma(coef, yx, fx);
+    fy = fma(coef, yy, fy);
+    fz = fma(coef, yz, fz);
+    if (fric) {
+      // tangential part of w against the repulsive force density rep
+      const double inv_d = 1.0 / d;
+      const double ex = yx * inv_d, ey = yy * inv_d, ez = yz * inv_d;
+      const double wn = wx * ex + wy * ey + wz * ez;
+      stick_slip(A.mu * rep, rho_i, A.dt, wx - wn * ex, wy - wn * ey, wz - wn * ez, fx, fy, fz);
+    }
+  }
+}
+
+// The bond memory of the lane's node after this evaluation's breaks: on the
+// tiled path its four class-mask words and the grain's axis order (perm >= 0);
+// on the slice path (perm < 0) the live column words hold it.
+struct BondMem {
+  uint32_t w0, w1, w2, w3;
+  int perm;
+};
+
 template <int MODE>
 __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool valid, const double4& ui,
                                           const GrainC* G, int ix, int iy, int iz, double fx, double fy,
-                                          double fz, int nbroke, bool col_ok, int64_t col, const NodeVA& va) {
+                                          double fz, int nbroke, bool col_ok, int64_t col, const NodeVA& va,
+                                          const BondMem& bm) {
   const int lane = threadIdx.x & 63;
   const double h = G->h;
   // mid-step velocity of this node for the normal damping (Sec. 3.4) and
@@ -319,45 +370,42 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
   if (vdep && valid) vhi = A.vh_cur[i];
   const double rho_i = G->rho;
 
-  // ---- repulsive contact with candidates of other grains (Sec. 3.2) ----
+  // ---- repulsive contact with the candidates: nodes of other grains, and with
+  // self-contact never-bonded nodes of the same grain (Secs. 3.2, 5) ----
   if (valid && A.cand_ptr != nullptr) {
     // rows past the capacity were not stored (the rebuild flagged it)
     const int32_t c0 = (int32_t)min((int64_t)A.cand_ptr[i], A.cand_capacity);
     const int32_t c1 = (int32_t)min((int64_t)A.cand_ptr[i + 1], A.cand_capacity);
     if (c1 > c0) {
       const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
-      const int mi = G->mat;
-      for (int32_t e = c0; e < c1; ++e) {
-        const int j = A.cand[e];
-        const double4 uj = A.ucur[j];
-        double yx, yy, yz;
-        const double d2 = contact_d2(A.X[j], Xx, uj.x, ui.x, A.X[A.n + j], Xy, uj.y, ui.y,
-                                     A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
-        if (d2 < A.Rc2 && d2 > 0.0) {
-          const GrainC* Gj = A.grains + packed_grain(uj.w);
-          const double d = sqrt(d2);
-          const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
-          double coef = -rep / d;
-          double4 vhj = make_double4(0.0, 0.0, 0.0, 0.0);
-          if (vdep) vhj = A.vh_cur[j];
-          const double wx = vhi.x - vhj.x, wy = vhi.y - vhj.y, wz = vhi.z - vhj.z;
-          if (damp) {
-            // -beta (w . e) e V_j, w = velocity of i relative to j, e = y / d
-            const double w = wx * yx + wy * yy + wz * yz;
-            coef -= A.beta * Gj->V * w / d2;
-          }
-          fx = fma(coef, yx, fx);
-          fy = fma(coef, yy, fy);
-          fz = fma(coef, yz, fz);
-          if (fric) {
-            // tangential part of w against the repulsive force density rep
-            const double inv_d = 1.0 / d;
-            const double ex = yx * inv_d, ey = yy * inv_d, ez = yz * inv_d;
-            const double wn = wx * ex + wy * ey + wz * ez;
-            stick_slip(A.mu * rep, rho_i, A.dt, wx - wn * ex, wy - wn * ey, wz - wn * ez, fx, fy, fz);
-          }
-        }
+      for (int32_t e = c0; e < c1; ++e)
+        contact_pair(A, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, fx, fy, fz);
+    }
+  }
+
+  // ---- self-contact across broken bonds (Sec. 5): only nodes that have lost a
+  // bond walk their built entries; the bond memory is the one after this
+  // evaluation's breaks ----
+  if (A.self_contact && valid && A.intact[i] - nbroke < A.rowlen[i]) {
+    const int64_t sl = i >> 6, ln = i & 63;
+    const int64_t off = A.slice_off[sl];
+    const int W = (int)((A.slice_off[sl + 1] - off) >> 6);
+    const uint32_t node_mask = (1u << A.node_bits) - 1u;
+    const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
+    for (int e = 0; e < W; ++e) {
+      const int64_t at = off + ((int64_t)e << 6) + ln;
+      const uint32_t wo = A.colOrig[at];
+      const int cls = (int)(wo >> A.node_bits);
+      if (cls >= A.n_stencil) continue;  // padding
+      bool live;
+      if (bm.perm >= 0) {
+        const int b = A.ctob[bm.perm * A.n_stencil + cls];
+        const uint32_t w = b < 32 ? bm.w0 : b < 64 ? bm.w1 : b < 96 ? bm.w2 : bm.w3;
+        live = ((w >> (b & 31)) & 1u) != 0u;
+      } else {
+        live = A.colE[at] == wo;
       }
+      if (!live) contact_pair(A, (int)(wo & node_mask), Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, fx, fy, fz);
     }
   }
 
@@ -482,12 +530,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   const bool valid = slice_ok && i >= A.node_lo && i < A.node_hi;
 
   double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
-  uint32_t mask[kMaskWords] = {0u, 0u, 0u, 0u};
-  if (valid) {
-    ui = A.ucur[i];
-#pragma unroll
-    for (int w = 0; w < kMaskWords; ++w) mask[w] = A.mask[(int64_t)w * A.n + i];
-  }
+  if (valid) ui = A.ucur[i];
   const int pi = packed_ijk(ui.w);
   const int gi = valid ? packed_grain(ui.w) : 0;
   const GrainC* G = A.grains + gi;
@@ -569,7 +612,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   }
 
   node_tail<MODE>(A, i, valid, ui, G, ix, iy, iz, fx, fy, fz, nbroke, slice_ok,
-                  A.partial_base + (slice - A.slice_base), load_va(A, i, valid));
+                  A.partial_base + (slice - A.slice_base), load_va(A, i, valid), BondMem{0u, 0u, 0u, 0u, -1});
 }
 
 __device__ __forceinline__ void stage_stencil(const StepArgs& A, StencilC* s_st) {
@@ -786,7 +829,8 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
     for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = mask[w];
   }
   node_tail<MODE_STEP>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke, true,
-                       (int64_t)kTS * t + wid, load_va(A, i, valid));
+                       (int64_t)kTS * t + wid, load_va(A, i, valid),
+                       BondMem{mask[0], mask[1], mask[2], mask[3], TG.perm});
 }
 
 // the six orders of the lattice axes (slowest first)
@@ -1239,7 +1283,8 @@ __global__ void k_active(ContactArgs c, double cut) {
   const double4 u = c.u[i];
   const int g = packed_grain(u.w);
   const double p[3] = {c.X[i] + u.x, c.X[c.n + i] + u.y, c.X[2 * c.n + i] + u.z};
-  uint8_t act = 0;
+  // with self-contact every node can meet a node of its own grain
+  uint8_t act = c.self_contact ? 1 : 0;
   for (int e = c.gpair_count[g]; e < c.gpair_count[g + 1] && !act; ++e) {
     const int b = c.gpair[e];
     bool in = true;
@@ -1286,6 +1331,7 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
   const int64_t i = me.x;
   const int gi = me.y;
   const double4 ui = c.u[i];
+  const int pi = packed_ijk(ui.w);
   const long long key = ((long long)me.w << 32) | (long long)(uint32_t)me.z;
   const int cx = (int)((key >> 42) & 0x1fffff) - (1 << 20);
   const int cy = (int)((key >> 21) & 0x1fffff) - (1 << 20);
@@ -1301,9 +1347,18 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
     const int e1 = c.bucket_start[hsh + 1];
     for (int e = c.bucket_start[hsh]; e < e1; ++e) {
       const int4 r = c.srec[e];
-      if (r.z != klo || r.w != khi || r.y == gi) continue;
+      if (r.z != klo || r.w != khi || (r.y == gi && !c.self_contact)) continue;
       const int j = r.x;
       const double4 uj = c.u[j];
+      if (r.y == gi) {
+        // same grain: only pairs that were never bonded (their broken bonds
+        // are found from the bond memory at every evaluation)
+        if (j == i) continue;
+        const int pj = packed_ijk(uj.w);
+        const int ax = unpack_x(pj) - unpack_x(pi), ay = unpack_y(pj) - unpack_y(pi),
+                  az = unpack_z(pj) - unpack_z(pi);
+        if (ax * ax + ay * ay + az * az <= c.m2 && !cut_between(c.cuts, c.cut_begin, gi, pi, pj)) continue;
+      }
       double yx, yy, yz;
       const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y,
                                    c.X[2 * c.n + j], Xz, uj.z, ui.z, yx, yy, yz);

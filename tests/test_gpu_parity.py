@@ -424,3 +424,94 @@ def test_shape_study_small_instance_matches_oracle(oracle_lib, shape):
         assert_state_close(sim, ora, what=f"{shape}, bond path {bp}")
         assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
         sim.close()
+
+
+def _notched_ball(self_contact=True, seed=7, h=1e-4):
+    """A ball of radius 5 h with a notch plane through half of it, shaken by a
+    random displacement field of 0.3 h and random velocities: with |s| > s0 most
+    bonds break, broken pairs and pairs across the notch sit closer than R_c."""
+    off = I.sphere_offsets(5)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, 1e-9, rebuild_every=5)
+    params.self_contact = self_contact
+    params.friction, params.contact_damping = 0.3, 1e21
+    params.skin = 2 * h
+    hu = I.HALF_UNBOUNDED
+    cut = I.Cut(kind=I.CUT_NOTCH, grain=0, plane=(1, 0, 0, -11), lo=(-hu, -hu, -hu), hi=(hu, 10, hu))
+    wl = I.assemble("ball_notch", [(ijk, origin, h, 0)], [I.SAND], params, [], [cut], 30)
+    rng = np.random.default_rng(seed)
+    wl.u0[:] = rng.uniform(-0.3 * h, 0.3 * h, size=wl.u0.shape)
+    wl.v0[:] = rng.uniform(-1.0, 1.0, size=wl.v0.shape)
+    return wl
+
+
+def test_self_contact_candidates_are_the_never_bonded_pairs(oracle_lib):
+    """Self-contact (Sec. 5): the GPU's candidate rows hold exactly the oracle's
+    same-grain candidates that were never bonded (cut or outside the horizon);
+    the bonded ones are handled from the bond memory instead."""
+    from paper_2506_05362_amd import pd
+    wl = _notched_ball()
+    sim = gpu_sim(wl, candidate_capacity_per_node=64)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST | oracle_lib.ABS_STRETCH)
+    rpo, colo = ora.candidates()
+    brp, bcol, _ = ora.bonds()
+    rows = []
+    for i in range(wl.n_nodes):
+        bonded = set(bcol[brp[i]:brp[i + 1]].tolist())
+        rows.append([j for j in colo[rpo[i]:rpo[i + 1]] if j not in bonded])
+    rp, col = sim.candidates()
+    assert sum(map(len, rows)) > 100
+    for i in range(wl.n_nodes):
+        assert col[rp[i]:rp[i + 1]].tolist() == rows[i], i
+    sim.close()
+
+
+@pytest.mark.parametrize("bond_path", [0, 1])
+def test_self_contact_matches_oracle(oracle_lib, bond_path):
+    """Self-contact with damping and friction across broken bonds and across a
+    notch (never bonded), 30 steps: state 1e-9 and broken sets equal, through
+    either bond path; without self-contact the forces differ."""
+    from paper_2506_05362_amd import pd
+    wl = _notched_ball()
+    flags = oracle_lib.CELL_LIST | oracle_lib.ABS_STRETCH
+    ora = oracle_lib.Oracle(wl, flags=flags)
+    assert ora.step(30) == 0
+    sim = gpu_sim(wl, flags=pd.FLAG_ABS_STRETCH, candidate_capacity_per_node=64)
+    sim.set_launch(bond_path=bond_path)
+    sim.step(30)
+    assert_state_close(sim, ora, what=f"self-contact, bond path {bond_path}")
+    assert np.array_equal(sim.bonds()[2], ora.bonds()[2])
+    sim.close()
+    off = oracle_lib.Oracle(_notched_ball(self_contact=False), flags=flags)
+    off.step(30)
+    assert rel_inf(off.state()["F"], ora.state()["F"]) > 1e-3
+
+
+def test_self_contact_rejects_a_contact_radius_at_the_spacing():
+    from paper_2506_05362_amd import pd
+    wl = _notched_ball()
+    wl.params.contact_radius = wl.grain_h[0]
+    with pytest.raises(pd.PDError, match="self-contact"):
+        gpu_sim(wl)
+
+
+@pytest.mark.parametrize("shape", ["shell", "jack"])
+def test_shape_study_with_self_contact_matches_oracle(oracle_lib, shape):
+    """The crushed shape-study instance with self-contact on: state 1e-9 and wall
+    forces 1e-6 through both bond paths, and self-contact changed the result."""
+    from paper_2506_05362_amd import pd
+    wl = I.shape_study(shape, seed=3, grid=2, radius=5e-4, h=1e-4, lid_speed=50.0, duration=1e-5)
+    wl.params.skin = 0.5 * wl.grain_h[0]
+    wl.params.contact_damping = 1e21
+    wl.params.friction = 0.3
+    wl.params.self_contact = True
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    assert ora.step(wl.steps) == 0
+    fo, _ = ora.walls()
+    for bp in (pd.BONDS_SLICES, pd.BONDS_TILES):
+        sim = gpu_sim(wl)
+        sim.set_launch(bond_path=bp)
+        sim.step(wl.steps)
+        assert_state_close(sim, ora, what=f"{shape} self-contact, bond path {bp}")
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        sim.close()
