@@ -96,12 +96,12 @@ enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 
                                      PD_FLAG_TABLE_LITERAL the printed row */
        PD_FLAG_SELF_CONTACT = 16  /* self-contact (Sec. 5): nodes of one grain with no intact bond
                                      repel as nodes of different grains do (K_n (R_c - d) V_j with
-                                     damping and friction).  Pairs whose bond has broken are taken
-                                     from the bond memory at every evaluation; pairs never bonded
-                                     (outside the horizon or cut) join the contact candidates.
-                                     Requires contact_radius below every grain's lattice spacing
-                                     (so no pair is shorter than R_c), else PD_ERR_INVALID; the
-                                     skin guard then applies to a single grain too */ };
+                                     damping and friction).  The contact candidates then include the
+                                     node's own grain; a pair whose bond is intact at the evaluation
+                                     is skipped.  Requires contact_radius below every grain's
+                                     lattice spacing (so no pair is shorter than R_c), else
+                                     PD_ERR_INVALID; the skin guard then applies to a single grain
+                                     too */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with
@@ -109,11 +109,13 @@ typedef struct {
   int32_t flags;           /* PD_FLAG_* */
   double contact_radius;   /* R_c [m] (Sec. 3.2) */
   double contact_horizon;  /* eps in K_n = 18 k / (pi eps^5) [m] */
-  double skin;             /* Verlet skin [m]: candidates are other-grain nodes within R_c + skin */
+  double skin;             /* Verlet skin [m]: candidates are other-grain nodes (with
+                              PD_FLAG_SELF_CONTACT also same-grain nodes) within R_c + skin */
   int32_t rebuild_every;   /* candidate rebuild cadence in steps (>= 1) */
   int32_t candidate_capacity_per_node; /* candidate list capacity: N times this in total and
-                                          twice this for any one node (0 = 16); exceeding
-                                          either raises PD_ERR_UNSTABLE */
+                                          twice this for any one node (0 = 16, or 48 with
+                                          PD_FLAG_SELF_CONTACT); exceeding either raises
+                                          PD_ERR_UNSTABLE */
   double dt;               /* time step [s] */
   double gravity[3];       /* body force per unit mass [m/s^2] */
   double contact_damping;  /* beta_d of the normal damping law (Sec. 3.4) [N s/m^7], >= 0;

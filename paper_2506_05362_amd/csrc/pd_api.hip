@@ -106,9 +106,6 @@ struct pd_ctx {
   int32_t* tmap = nullptr;
   StencilC* ttab = nullptr;
   int16_t* ctob = nullptr;  // [6][n_stencil]: slice-path class -> mask bit per axis order
-  // bond cuts, kept after the build for the self-contact search
-  CutDev* cuts = nullptr;
-  int32_t* cut_begin = nullptr;
   uint32_t* mask = nullptr;  // [kMaskWords][N]
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
@@ -323,9 +320,6 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.cut2 = cut * cut;
   C.skin_half2 = 0.25 * c->skin * c->skin;
   C.self_contact = (c->flags & PD_FLAG_SELF_CONTACT) ? 1 : 0;
-  C.m2 = c->m * c->m;
-  C.cuts = c->cuts;
-  C.cut_begin = c->cut_begin;
   return C;
 }
 
@@ -724,7 +718,8 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   c->use_graph = (P.flags & PD_FLAG_NO_GRAPH) ? 0 : 1;
   if (!c->use_graph) c->launch.loop = PD_LOOP_DIRECT;
   c->graph_len = (P.rebuild_every % 2 == 0) ? P.rebuild_every : 2 * (int64_t)P.rebuild_every;
-  c->cap_per_node = P.candidate_capacity_per_node > 0 ? P.candidate_capacity_per_node : 16;
+  c->cap_per_node = P.candidate_capacity_per_node > 0 ? P.candidate_capacity_per_node
+                                                      : ((P.flags & PD_FLAG_SELF_CONTACT) ? 48 : 16);
   for (int q = 0; q < 3; ++q) c->g[q] = P.gravity[q];
   c->grain_begin.assign(grains->node_begin, grains->node_begin + G + 1);
 
@@ -1032,9 +1027,9 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   dev_free(c, gdim_d);
   dev_free(c, glo_d);
   dev_free(c, gmap_d);
-  c->cut_begin = cut_begin_d;
-  c->cuts = cuts_d;
+  dev_free(c, cut_begin_d);
   dev_free(c, stencil_d);
+  dev_free(c, cuts_d);
   dev_free(c, scan_scratch64);
 
   // contact structures

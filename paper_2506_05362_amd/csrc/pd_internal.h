@@ -167,9 +167,10 @@ struct StepArgs {
   const int32_t* tmap;
   const StencilC* ttab;
   uint32_t* mask;
-  // self-contact inside a grain (Sec. 5): the node's broken bonds are found
-  // from the built column words (colOrig) and, on the tiled path, the class
-  // masks through ctob ([6][n_stencil] slice class -> mask bit per axis order)
+  // self-contact inside a grain (Sec. 5): a same-grain candidate pair is
+  // skipped while its bond is intact, found in the built column words (rows
+  // sorted by neighbour) and, on the tiled path, the class masks through ctob
+  // ([6][n_stencil] slice class -> mask bit per axis order)
   int32_t self_contact;
   const uint32_t* colOrig;
   const int16_t* ctob;
@@ -231,12 +232,8 @@ struct ContactArgs {
   double inv_cell;
   double cut2;            // (R_c + skin)^2
   double skin_half2;
-  // self-contact: same-grain pairs that were never bonded (outside the horizon
-  // shell |d ijk|^2 <= m2, or removed by a cut) are candidates too
+  // self-contact: nodes of the node's own grain are candidates too
   int32_t self_contact;
-  int32_t m2;
-  const CutDev* cuts;
-  const int32_t* cut_begin;  // [G+1]
 };
 
 // ---- launchers (pd_kernels.hip) ----

@@ -310,19 +310,57 @@ __device__ __forceinline__ NodeVA load_va(const StepArgs& A, int64_t i, bool val
   return r;
 }
 
+// The bond memory of the lane's node after this evaluation's breaks: on the
+// tiled path its four class-mask words and the grain's axis order (perm >= 0);
+// on the slice path (perm < 0) the live column words hold it.
+struct BondMem {
+  uint32_t w0, w1, w2, w3;
+  int perm;
+};
+
+// Is the bond from node i to node j (same grain) intact after this evaluation's
+// breaks?  The node's built entries are sorted by neighbour index, so a binary
+// search finds j's entry; a pair with no entry (outside the horizon, or cut)
+// has no bond.
+__device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j, const BondMem& bm) {
+  const uint32_t node_mask = (1u << A.node_bits) - 1u;
+  const int64_t base = A.slice_off[i >> 6] + (i & 63);
+  int lo = 0, hi = A.rowlen[i] - 1;
+  while (lo <= hi) {
+    const int mid = (lo + hi) >> 1;
+    const int64_t at = base + ((int64_t)mid << 6);
+    const uint32_t wo = A.colOrig[at];
+    const int jm = (int)(wo & node_mask);
+    if (jm < j) {
+      lo = mid + 1;
+    } else if (jm > j) {
+      hi = mid - 1;
+    } else {
+      if (bm.perm < 0) return A.colE[at] == wo;
+      const int b = A.ctob[bm.perm * A.n_stencil + (int)(wo >> A.node_bits)];
+      const uint32_t w = b < 32 ? bm.w0 : b < 64 ? bm.w1 : b < 96 ? bm.w2 : bm.w3;
+      return ((w >> (b & 31)) & 1u) != 0u;
+    }
+  }
+  return false;
+}
+
 // Repulsion of node j on node i when closer than R_c (Sec. 3.2), with normal
 // damping (Sec. 3.4) and stick-slip friction (Sec. 3.3): between grains, and
 // between nodes of one grain without an intact bond (Sec. 5, where c_w / R_c
 // is the same K_n; self-contact needs R_c below the lattice spacing, so the
 // repulsive-only bond of pairs shorter than R_c never arises).
-__device__ __forceinline__ void contact_pair(const StepArgs& A, int j, double Xx, double Xy, double Xz,
+__device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j, double Xx, double Xy, double Xz,
                                              const double4& ui, const double4& vhi, int mi, double rho_i,
-                                             bool damp, bool fric, double& fx, double& fy, double& fz) {
+                                             bool damp, bool fric, const BondMem& bm, double& fx, double& fy,
+                                             double& fz) {
   const double4 uj = A.ucur[j];
   double yx, yy, yz;
   const double d2 = contact_d2(A.X[j], Xx, uj.x, ui.x, A.X[A.n + j], Xy, uj.y, ui.y,
                                A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
   if (d2 < A.Rc2 && d2 > 0.0) {
+    // a node of the same grain repels only while no intact bond joins the two
+    if (A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, bm)) return;
     const GrainC* Gj = A.grains + packed_grain(uj.w);
     const double d = sqrt(d2);
     const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
@@ -348,14 +386,6 @@ __device__ __forceinline__ void contact_pair(const StepArgs& A, int j, double Xx
   }
 }
 
-// The bond memory of the lane's node after this evaluation's breaks: on the
-// tiled path its four class-mask words and the grain's axis order (perm >= 0);
-// on the slice path (perm < 0) the live column words hold it.
-struct BondMem {
-  uint32_t w0, w1, w2, w3;
-  int perm;
-};
-
 template <int MODE>
 __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool valid, const double4& ui,
                                           const GrainC* G, int ix, int iy, int iz, double fx, double fy,
@@ -370,8 +400,8 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
   if (vdep && valid) vhi = A.vh_cur[i];
   const double rho_i = G->rho;
 
-  // ---- repulsive contact with the candidates: nodes of other grains, and with
-  // self-contact never-bonded nodes of the same grain (Secs. 3.2, 5) ----
+  // ---- repulsive contact with the candidates: nodes of other grains and, with
+  // self-contact, of the same grain (Secs. 3.2, 5) ----
   if (valid && A.cand_ptr != nullptr) {
     // rows past the capacity were not stored (the rebuild flagged it)
     const int32_t c0 = (int32_t)min((int64_t)A.cand_ptr[i], A.cand_capacity);
@@ -379,33 +409,7 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
     if (c1 > c0) {
       const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
       for (int32_t e = c0; e < c1; ++e)
-        contact_pair(A, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, fx, fy, fz);
-    }
-  }
-
-  // ---- self-contact across broken bonds (Sec. 5): only nodes that have lost a
-  // bond walk their built entries; the bond memory is the one after this
-  // evaluation's breaks ----
-  if (A.self_contact && valid && A.intact[i] - nbroke < A.rowlen[i]) {
-    const int64_t sl = i >> 6, ln = i & 63;
-    const int64_t off = A.slice_off[sl];
-    const int W = (int)((A.slice_off[sl + 1] - off) >> 6);
-    const uint32_t node_mask = (1u << A.node_bits) - 1u;
-    const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
-    for (int e = 0; e < W; ++e) {
-      const int64_t at = off + ((int64_t)e << 6) + ln;
-      const uint32_t wo = A.colOrig[at];
-      const int cls = (int)(wo >> A.node_bits);
-      if (cls >= A.n_stencil) continue;  // padding
-      bool live;
-      if (bm.perm >= 0) {
-        const int b = A.ctob[bm.perm * A.n_stencil + cls];
-        const uint32_t w = b < 32 ? bm.w0 : b < 64 ? bm.w1 : b < 96 ? bm.w2 : bm.w3;
-        live = ((w >> (b & 31)) & 1u) != 0u;
-      } else {
-        live = A.colE[at] == wo;
-      }
-      if (!live) contact_pair(A, (int)(wo & node_mask), Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, fx, fy, fz);
+        contact_pair(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, bm, fx, fy, fz);
     }
   }
 
@@ -1331,7 +1335,6 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
   const int64_t i = me.x;
   const int gi = me.y;
   const double4 ui = c.u[i];
-  const int pi = packed_ijk(ui.w);
   const long long key = ((long long)me.w << 32) | (long long)(uint32_t)me.z;
   const int cx = (int)((key >> 42) & 0x1fffff) - (1 << 20);
   const int cy = (int)((key >> 21) & 0x1fffff) - (1 << 20);
@@ -1347,18 +1350,11 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
     const int e1 = c.bucket_start[hsh + 1];
     for (int e = c.bucket_start[hsh]; e < e1; ++e) {
       const int4 r = c.srec[e];
-      if (r.z != klo || r.w != khi || (r.y == gi && !c.self_contact)) continue;
+      // with self-contact the node's own grain counts too (whether a pair is
+      // bonded is decided at the force, from the bond memory)
+      if (r.z != klo || r.w != khi || (r.y == gi && (!c.self_contact || r.x == i))) continue;
       const int j = r.x;
       const double4 uj = c.u[j];
-      if (r.y == gi) {
-        // same grain: only pairs that were never bonded (their broken bonds
-        // are found from the bond memory at every evaluation)
-        if (j == i) continue;
-        const int pj = packed_ijk(uj.w);
-        const int ax = unpack_x(pj) - unpack_x(pi), ay = unpack_y(pj) - unpack_y(pi),
-                  az = unpack_z(pj) - unpack_z(pi);
-        if (ax * ax + ay * ay + az * az <= c.m2 && !cut_between(c.cuts, c.cut_begin, gi, pi, pj)) continue;
-      }
       double yx, yy, yz;
       const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y,
                                    c.X[2 * c.n + j], Xz, uj.z, ui.z, yx, yy, yz);

@@ -93,8 +93,11 @@ def main(argv=None):
                     help="normal contact damping beta_d (Sec. 3.4); the representative volume's "
                          "2.8e22 at h = 70 um scaled by h^-4 to h = 100 um")
     ap.add_argument("--rebuild-every", type=int, default=5)
-    ap.add_argument("--skin", type=float, default=0.5, help="Verlet skin in lattice spacings")
-    ap.add_argument("--capacity", type=int, default=32, help="contact candidates per node")
+    ap.add_argument("--skin", type=float, default=0.4,
+                    help="Verlet skin in lattice spacings (below sqrt(2) - 0.95, so the own-grain "
+                         "candidates of self-contact are the six face neighbours until a grain deforms)")
+    ap.add_argument("--capacity", type=int, default=48,
+                    help="contact candidates per node (own-grain neighbours count with self-contact)")
     ap.add_argument("--self-contact", type=int, default=1, choices=(0, 1),
                     help="contact between fragments of one grain (Sec. 5)")
     ap.add_argument("--out", default=None, help="write every shape's full log to this JSON file")
