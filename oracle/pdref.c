@@ -46,6 +46,14 @@
  *      damping and friction of R15/R17 on top.  The paper's assumption
  *      eps <= R_c is not needed for this case split and is not made.  With
  *      self-contact the skin guard applies to a single grain as well.
+ *   R19 several walls (Sec. 4.1.1, PDREF_WALL_CORNERS): inclusion-exclusion
+ *      over the walls a node touches, pairs counted once (the printed sum over
+ *      i != j would count each twice) and the triple term without the stray
+ *      factor V_x; the intersection volumes and centroids, which the paper does
+ *      not give, are integrated over slices of the ball.  Only mutually
+ *      orthogonal walls (a box) form pairs and triples.  The damping and
+ *      friction of each wall stay per wall.  Each wall's reaction takes the
+ *      corrections' components along its normal.
  */
 #include "pdref.h"
 
@@ -155,6 +163,132 @@ void pdref_wall_cap(double Rc, double d, double* volume, double* centroid) {
   /* cap of the ball B_Rc(p) on the far side of a plane at signed distance d */
   *volume = PI / 3.0 * (Rc - d) * (Rc - d) * (2.0 * Rc + d);
   *centroid = (PI / 4.0) * (Rc * Rc - d * d) * (Rc * Rc - d * d) / *volume;
+}
+
+/* ------------------------------------------------------------------------- */
+/* several walls at a corner (Sec. 4.1.1, R19)                               */
+/* ------------------------------------------------------------------------- */
+
+/* Area and first moments of the plane region {v > b, w > c, v^2 + w^2 < r^2}
+   (c = -INFINITY: the circular segment v > b), integrated over v in closed
+   form.  For a given v the region spans w in (max(c, -s), s), s = sqrt(r^2 - v^2). */
+static double seg_S0(double r, double x) { /* int sqrt(r^2 - v^2) dv */
+  const double sx = sqrt(fmax(r * r - x * x, 0.0));
+  return 0.5 * (x * sx + r * r * asin(fmax(-1.0, fmin(1.0, x / r))));
+}
+static double seg_S1(double r, double x) { /* int v sqrt(r^2 - v^2) dv */
+  const double q = fmax(r * r - x * x, 0.0);
+  return -q * sqrt(q) / 3.0;
+}
+static double seg_S2(double r, double x) { /* int (r^2 - v^2) dv */
+  return r * r * x - x * x * x / 3.0;
+}
+static void region2d(double r, double b, double c, double out[3]) {
+  out[0] = out[1] = out[2] = 0.0;
+  if (!(r > 0.0) || b >= r || c >= r) return;
+  const double v0 = fmax(b, -r);
+  /* pieces of the v axis: |v| < e where the lower bound is c (s > -c), and
+     e <= |v| < r where it is -s; with c >= 0 only |v| < e is non-empty */
+  double e = r;
+  if (c > -r) e = sqrt(r * r - c * c);
+  double lo[3] = {-r, -e, e}, hi[3] = {-e, e, r};
+  int kind[3] = {2, 1, 2}; /* 1: length s - c, 2: length 2s */
+  if (c >= 0.0) kind[0] = kind[2] = 0;
+  if (!(c > -r)) { kind[1] = 2; }
+  for (int k = 0; k < 3; ++k) {
+    if (!kind[k]) continue;
+    double x0 = fmax(lo[k], v0), x1 = hi[k];
+    if (!(x1 > x0)) continue;
+    if (kind[k] == 1) {
+      out[0] += seg_S0(r, x1) - seg_S0(r, x0) - c * (x1 - x0);
+      out[1] += seg_S1(r, x1) - seg_S1(r, x0) - 0.5 * c * (x1 * x1 - x0 * x0);
+      out[2] += 0.5 * (seg_S2(r, x1) - seg_S2(r, x0) - c * c * (x1 - x0));
+    } else {
+      out[0] += 2.0 * (seg_S0(r, x1) - seg_S0(r, x0));
+      out[1] += 2.0 * (seg_S1(r, x1) - seg_S1(r, x0));
+    }
+  }
+}
+
+/* integrand over u: [A, u A, M_v, M_w] of the slice of the ball at height u */
+static void corner_slice(double R, double b, double c, double u, double f[4]) {
+  double m[3];
+  region2d(sqrt(fmax(R * R - u * u, 0.0)), b, c, m);
+  f[0] = m[0];
+  f[1] = u * m[0];
+  f[2] = m[1];
+  f[3] = m[2];
+}
+
+/* tanh-sinh (double-exponential) quadrature of the four integrands on
+   [x0, x1] (Takahasi and Mori): x = mid + half tanh((pi/2) sinh t) on a step
+   of t halved until two levels agree; it is exact to rounding for integrands
+   that are smooth inside the interval, whatever their behaviour at its ends. */
+static void tanh_sinh4(double R, double b, double c, double x0, double x1, double out[4]) {
+  const double mid = 0.5 * (x0 + x1), half = 0.5 * (x1 - x0);
+  double prev[4] = {0.0, 0.0, 0.0, 0.0}, sum[4] = {0.0, 0.0, 0.0, 0.0};
+  double step = 0.5;
+  /* level 0: t = k step for |t| <= 4, then odd multiples of each halved step */
+  for (int level = 0; level < 9; ++level) {
+    const int stride = level == 0 ? 1 : 2;
+    const int first = level == 0 ? 0 : 1;
+    for (int k = first; k * step <= 4.0; k += stride) {
+      const double t = k * step;
+      const double sh = (PI / 2.0) * sinh(t), ch = cosh(sh);
+      const double w = (PI / 2.0) * cosh(t) / (ch * ch);
+      const double x = tanh(sh);
+      double f[4];
+      corner_slice(R, b, c, mid + half * x, f);
+      for (int q = 0; q < 4; ++q) sum[q] += w * f[q];
+      if (k > 0) {
+        corner_slice(R, b, c, mid - half * x, f);
+        for (int q = 0; q < 4; ++q) sum[q] += w * f[q];
+      }
+    }
+    double est[4], diff = 0.0, scale = 0.0;
+    for (int q = 0; q < 4; ++q) {
+      est[q] = half * step * sum[q];
+      diff = fmax(diff, fabs(est[q] - prev[q]));
+      scale = fmax(scale, fabs(est[q]));
+      prev[q] = est[q];
+    }
+    if (level >= 3 && diff <= 1e-15 * scale) break;
+    step *= 0.5;
+  }
+  for (int q = 0; q < 4; ++q) out[q] += prev[q];
+}
+
+/* Volume and centroid of {x : |x| < R, x_u > a, x_v > b, x_w > c} (c = -INFINITY
+   for two planes): V = int A(u) du over the slices u = const, each a disk of
+   radius sqrt(R^2 - u^2) cut by the other planes.  The u axis is split where a
+   slice changes shape, and each piece is integrated by tanh-sinh quadrature. */
+void pdref_corner_region(double R, double a, double b, double c, double* volume, double centroid[3]) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const double u0 = fmax(a, -R);
+  double cuts[8]; /* u0, R and up to two points for each of three radii */
+  int nc = 0;
+  cuts[nc++] = u0;
+  const double rr[3] = {fabs(b), fabs(c), sqrt(b * b + c * c)};
+  for (int k = 0; k < 3; ++k)
+    if (rr[k] < R && isfinite(rr[k])) {
+      const double uk = sqrt(R * R - rr[k] * rr[k]);
+      if (uk > u0 && uk < R) cuts[nc++] = uk;
+      if (-uk > u0 && -uk < R) cuts[nc++] = -uk;
+    }
+  cuts[nc++] = R;
+  for (int i = 1; i < nc; ++i) /* sort the break points */
+    for (int j = i; j > 0 && cuts[j] < cuts[j - 1]; --j) {
+      const double t = cuts[j];
+      cuts[j] = cuts[j - 1];
+      cuts[j - 1] = t;
+    }
+  for (int k = 0; k + 1 < nc; ++k) {
+    const double x0 = cuts[k], x1 = cuts[k + 1];
+    if (!(x1 > x0)) continue;
+    tanh_sinh4(R, b, c, x0, x1, acc);
+  }
+  *volume = acc[0];
+  for (int q = 0; q < 3; ++q) centroid[q] = acc[0] > 0.0 ? acc[q + 1] / acc[0] : 0.0;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -533,6 +667,70 @@ static void add_friction(double mu, double fr, double rho, double dt, const doub
   }
 }
 
+/* Inclusion-exclusion over the walls node i touches (Sec. 4.1.1): the force
+   sum_l F_l - sum_{pairs} F_{l l'} + F_{l l' l''} of terms
+   -K_n (R_c - |c_S - p|) |S| e_S, e_S = (c_S - p)/|c_S - p|, S the part of the
+   contact ball beyond every wall of the term.  Pairs and triples are those of
+   mutually orthogonal walls (the corners of a box; the regions of other pairs
+   have no closed description here and their terms are left out).  Wall l takes
+   the component of each correction along its normal, so the corrections land
+   in the per-wall magnitudes: corr[l][i] += (sign F_S) . n_l. */
+static void wall_corners(const pdref* s, int64_t i, double* corr) {
+  const int64_t n = s->n;
+  const double Rc = s->Rc;
+  int hit[3], nh = 0;
+  double dl[3];
+  double p[3];
+  for (int q = 0; q < 3; ++q) p[q] = s->X[q * n + i] + s->u[q * n + i];
+  for (int32_t w = 0; w < s->n_walls && nh < 3; ++w) {
+    const wall_t* W = &s->walls[w];
+    int in = 1;
+    for (int q = 0; q < 3; ++q)
+      if (p[q] < W->lo[q] || p[q] > W->hi[q]) in = 0;
+    if (!in) continue;
+    double d = (W->n[0] * p[0] + W->n[1] * p[1]) + W->n[2] * p[2] - W->offset;
+    if (!(d < Rc) || d <= -Rc) continue;
+    hit[nh] = w;
+    dl[nh] = d;
+    ++nh;
+  }
+  if (nh < 2) return;
+  const int32_t g = s->grain_of[i];
+  const double Kn = pdref_contact_stiffness(s->gK[g], s->gK[g], s->eps);
+  int orth[3][3];
+  for (int x = 0; x < nh; ++x)
+    for (int y = 0; y < nh; ++y) {
+      const double* a = s->walls[hit[x]].n;
+      const double* b = s->walls[hit[y]].n;
+      orth[x][y] = fabs((a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]) < 1e-12;
+    }
+  /* terms: the pairs (minus) and the triple (plus) */
+  for (int x = 0; x < nh; ++x)
+    for (int y = x + 1; y < nh; ++y)
+      for (int z = y + 1; z <= nh; ++z) {
+        const int triple = z < nh;
+        if (!orth[x][y] || (triple && (!orth[x][z] || !orth[y][z]))) continue;
+        if (!triple && z != nh) continue;
+        const int m[3] = {x, y, triple ? z : -1};
+        double vol, cen[3];
+        pdref_corner_region(Rc, dl[x], dl[y], triple ? dl[z] : -INFINITY, &vol, cen);
+        if (!(vol > 0.0)) continue;
+        /* c - p along the outward directions t_l = -n_l */
+        double cp[3] = {0.0, 0.0, 0.0};
+        for (int k = 0; k < (triple ? 3 : 2); ++k)
+          for (int q = 0; q < 3; ++q) cp[q] -= cen[k] * s->walls[hit[m[k]]].n[q];
+        const double ell = sqrt((cp[0] * cp[0] + cp[1] * cp[1]) + cp[2] * cp[2]);
+        if (!(ell > 0.0)) continue;
+        const double sign = triple ? 1.0 : -1.0;
+        for (int k = 0; k < (triple ? 3 : 2); ++k) {
+          const double* nl = s->walls[hit[m[k]]].n;
+          /* F_S . n_l with F_S = -K_n (R_c - ell) vol cp / ell */
+          const double fn = -Kn * (Rc - ell) * vol * ((cp[0] * nl[0] + cp[1] * nl[1]) + cp[2] * nl[2]) / ell;
+          corr[hit[m[k]] * n + i] += sign * fn;
+        }
+      }
+}
+
 /* bond memory of the pair: 1 when j is in i's bond row and that bond is intact */
 static int bond_intact(const pdref* s, int64_t i, int64_t j) {
   for (int64_t e = s->row_ptr[i]; e < s->row_ptr[i + 1]; ++e)
@@ -630,6 +828,13 @@ static int eval_force(pdref* s) {
     }
   }
   if (margin < s->min_margin) s->min_margin = margin;
+  /* several walls at a corner (Sec. 4.1.1, R19): corrections of the normal
+     magnitude each wall applies to each node */
+  double* corr = NULL;
+  if ((s->flags & PDREF_WALL_CORNERS) && s->n_walls > 1) {
+    corr = (double*)calloc((size_t)(s->n_walls * n), sizeof(double));
+    for (int64_t i = 0; i < n; ++i) wall_corners(s, i, corr);
+  }
   /* rigid walls, Sec. 4.1 (sequential pass so the reaction sum runs in ascending i) */
   for (int32_t w = 0; w < s->n_walls; ++w) {
     wall_t* W = &s->walls[w];
@@ -653,6 +858,7 @@ static int eval_force(pdref* s) {
       pdref_wall_cap(Rc, d, &vol, &ell);
       /* -K_n (R_c - |c_l - p|) |S_l| e_l with e_l = -n (towards the wall) */
       double mag = Kn * (Rc - ell) * vol;
+      if (corr) mag += corr[w * n + i];
       if (s->beta > 0.0) {
         /* damping against the wall (Sec. 4.1 with V_y -> |S_l|): the relative
            normal velocity is v . n minus the wall's own rate along n */
@@ -678,6 +884,7 @@ static int eval_force(pdref* s) {
       }
     }
   }
+  free(corr);
   return bad;
 }
 

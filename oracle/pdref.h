@@ -41,6 +41,7 @@ extern "C" {
 #define PDREF_CELL_LIST 4     /* contact candidates from a cell list instead of an O(N^2) scan */
 #define PDREF_CONIC 8         /* conic micromodulus c0 (1 - |xi|/delta) instead of a constant one */
 #define PDREF_SELF_CONTACT 16 /* contact between nodes of one grain with no intact bond (Sec. 5) */
+#define PDREF_WALL_CORNERS 32 /* inclusion-exclusion of orthogonal walls at a corner (Sec. 4.1.1) */
 
 /* packed wall record (15 doubles):
  *   nx ny nz offset velocity lox loy loz hix hiy hiz mode target_stress servo_gain area */
@@ -59,6 +60,9 @@ void pdref_constants(double K, double Gc, double delta, int32_t flags, double* c
 double pdref_contact_stiffness(double k_a, double k_b, double eps);
 /* spherical cap of B_Rc(p) beyond a plane at signed distance d: volume and centroid distance */
 void pdref_wall_cap(double Rc, double d, double* volume, double* centroid);
+/* volume and centroid (coordinates along the three plane normals) of the part
+   of the ball |x| < R with x_u > a, x_v > b and x_w > c (c = -INFINITY: two planes) */
+void pdref_corner_region(double R, double a, double b, double c, double* volume, double centroid[3]);
 
 pdref* pdref_create(int64_t n, const double* X, const int32_t* ijk, const double* u0,
                     const double* v0, const uint8_t* fixed, int32_t n_grains,

@@ -20,6 +20,7 @@ ABS_STRETCH = 2
 CELL_LIST = 4
 CONIC = 8
 SELF_CONTACT = 16
+WALL_CORNERS = 32
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC",
           "-shared", "-Wall"]
@@ -77,6 +78,8 @@ def lib():
         L.pdref_contact_stiffness.restype = C.c_double
         L.pdref_wall_cap.argtypes = [C.c_double, C.c_double, C.POINTER(C.c_double),
                                      C.POINTER(C.c_double)]
+        L.pdref_corner_region.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                          C.POINTER(C.c_double), C.POINTER(C.c_double)]
         _lib = L
     return _lib
 
@@ -99,6 +102,14 @@ def wall_cap(Rc, d):
     v, l = C.c_double(), C.c_double()
     lib().pdref_wall_cap(Rc, d, C.byref(v), C.byref(l))
     return v.value, l.value
+
+
+def corner_region(R, a, b, c=-np.inf):
+    """Volume and centroid of {|x| < R, x_u > a, x_v > b, x_w > c}."""
+    v = C.c_double()
+    cen = (C.c_double * 3)()
+    lib().pdref_corner_region(R, a, b, c, C.byref(v), cen)
+    return v.value, np.array(cen[:])
 
 
 def pack_walls(walls):
@@ -125,6 +136,8 @@ class Oracle:
             flags |= CONIC
         if getattr(wl.params, "self_contact", False):
             flags |= SELF_CONTACT
+        if getattr(wl.params, "wall_corners", False):
+            flags |= WALL_CORNERS
         self.wl = wl
         self.n = wl.n_nodes
         p = wl.params

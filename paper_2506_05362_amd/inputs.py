@@ -77,6 +77,7 @@ class Params:
     friction: float = 0.0  # mu of the stick-slip friction law; 0 = none
     micromodulus: str = "constant"  # "constant" or "conic" (c0 (1 - |xi|/delta))
     self_contact: bool = False  # contact between nodes of one grain with no intact bond
+    wall_corners: bool = False  # inclusion-exclusion of orthogonal walls at box corners
 
 
 @dataclasses.dataclass

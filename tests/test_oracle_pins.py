@@ -718,3 +718,105 @@ def test_self_contact_conserves_momentum_in_a_shattered_grain(oracle_lib):
             assert o.step_count == 40
             assert np.abs(o.state()["v"].sum(axis=1) - p0).max() <= 1e-10 * np.abs(wl.v0).sum()
     assert np.abs(fields[True] - fields[False]).max() > 1e-3 * np.abs(fields[True]).max()
+
+
+# ---------------------------------------------------------------------------
+# several walls at a corner (Sec. 4.1.1)
+# ---------------------------------------------------------------------------
+
+def test_corner_regions_special_cases(oracle_lib):
+    """Ball parts beyond two or three planes: through the centre a quarter ball
+    (pi R^3/3) and an octant (pi R^3/6), centroid 3R/8 along each cut normal;
+    a plane at -R leaves the single-wall cap; swapping planes swaps axes; an
+    empty corner has no volume."""
+    R = 0.7
+    v, c = oracle_lib.corner_region(R, 0.0, 0.0)
+    assert v == pytest.approx(math.pi * R ** 3 / 3, rel=1e-13)
+    assert c == pytest.approx([3 * R / 8, 3 * R / 8, 0.0], rel=1e-12, abs=1e-15)
+    v, c = oracle_lib.corner_region(R, 0.0, 0.0, 0.0)
+    assert v == pytest.approx(math.pi * R ** 3 / 6, rel=1e-13)
+    assert c == pytest.approx([3 * R / 8] * 3, rel=1e-12)
+    for a in (-0.6 * R, 0.0, 0.45 * R):
+        v, c = oracle_lib.corner_region(R, a, -R)
+        vc, lc = oracle_lib.wall_cap(R, a)
+        assert v == pytest.approx(vc, rel=1e-13) and c[0] == pytest.approx(lc, rel=1e-12)
+        assert abs(c[1]) <= 1e-13 * R
+    v1, c1 = oracle_lib.corner_region(R, 0.2 * R, -0.3 * R, 0.1 * R)
+    v2, c2 = oracle_lib.corner_region(R, 0.1 * R, 0.2 * R, -0.3 * R)
+    assert v1 == pytest.approx(v2, rel=1e-13) and c1 == pytest.approx(c2[[1, 2, 0]], rel=1e-12)
+    assert oracle_lib.corner_region(R, 0.8 * R, 0.7 * R)[0] == 0.0
+
+
+@pytest.mark.parametrize("abc", [(0.3, -0.2, None), (-0.5, 0.1, None), (0.3, -0.2, 0.1), (-0.4, -0.6, 0.2)])
+def test_corner_regions_monte_carlo(oracle_lib, abc):
+    """Volume and centroid of ball parts beyond two or three orthogonal planes
+    against Monte Carlo sampling of the ball (4e6 points)."""
+    a, b, c = abc
+    rng = np.random.default_rng(3)
+    x = rng.uniform(-1.0, 1.0, size=(4_000_000, 3))
+    x = x[np.einsum("ij,ij->i", x, x) < 1.0]
+    m = (x[:, 0] > a) & (x[:, 1] > b)
+    if c is not None:
+        m &= x[:, 2] > c
+    v_mc = 8.0 * m.sum() / 4_000_000
+    c_mc = x[m].mean(axis=0)
+    v, cen = oracle_lib.corner_region(1.0, a, b, -np.inf if c is None else c)
+    sig = math.sqrt(v_mc * (8 - v_mc) / 4_000_000)
+    assert abs(v - v_mc) < 5 * sig
+    assert np.abs(cen - c_mc).max() < 5e-3
+
+
+def _corner_node(h, d, walls_n, corners=True):
+    """One node at distance d from each of the given axis walls (normals into the
+    box), at rest."""
+    off = np.zeros((3, 1), dtype=np.int64)
+    ijk, origin = I.grain_block(off, np.zeros(3), h)
+    params = I.default_params(h, 1e-9)
+    params.wall_corners = corners
+    walls = []
+    for ax in range(walls_n):
+        nrm = [0.0, 0.0, 0.0]
+        nrm[ax] = 1.0
+        walls.append(I.Wall(normal=tuple(nrm), offset=-d, mode=I.WALL_FIXED, area=1.0))
+    return I.assemble("corner", [(ijk, origin, h, 0)], [I.SAND], params, walls, [], 1)
+
+
+@pytest.mark.parametrize("walls_n", [2, 3])
+def test_corner_inclusion_exclusion_closed_form(oracle_lib, walls_n):
+    """A node on a box edge (two walls) or in a corner (three) with d = 0: the
+    force is sum F_l - sum F_ll' (+ F_ll'l'') with each term
+    -K_n (R_c - |c - p|) |S| e_S, here from the closed forms of the half ball
+    (2 pi R^3/3, 3R/8), the quarter ball (pi R^3/3, 3 sqrt2 R/8) and the octant
+    (pi R^3/6, 3 sqrt3 R/8).  Without corners the single terms are summed; the
+    walls' reactions add up to minus the node's force times V."""
+    h = 1e-4
+    wl = _corner_node(h, 0.0, walls_n)
+    Rc = wl.params.contact_radius
+    Kn = 18 * I.SAND.bulk_modulus / (math.pi * (3 * h) ** 5)
+    single = Kn * (Rc - 3 * Rc / 8) * 2 * math.pi * Rc ** 3 / 3  # along each normal
+    pair = Kn * (Rc - 3 * math.sqrt(2) * Rc / 8) * math.pi * Rc ** 3 / 3 / math.sqrt(2)
+    triple = Kn * (Rc - 3 * math.sqrt(3) * Rc / 8) * math.pi * Rc ** 3 / 6 / math.sqrt(3)
+    if walls_n == 2:
+        expect = single - pair  # per component along each of the two normals
+    else:
+        expect = single - 2 * pair + triple
+    o = oracle_lib.Oracle(wl)
+    F = o.state()["F"][:, 0]
+    for ax in range(walls_n):
+        assert F[ax] == pytest.approx(expect, rel=1e-12)
+    fo, _ = o.walls()
+    assert np.allclose(fo.sum(axis=0), -h ** 3 * F, rtol=1e-12, atol=0.0)
+    F_sum = oracle_lib.Oracle(_corner_node(h, 0.0, walls_n, corners=False)).state()["F"][:, 0]
+    assert F_sum[:walls_n] == pytest.approx([single] * walls_n, rel=1e-12)
+
+
+def test_corner_terms_need_orthogonal_walls(oracle_lib):
+    """Two walls at 45 degrees give the plain sum with or without corners."""
+    h = 1e-4
+    wl = _corner_node(h, 0.0, 1)
+    s = 1 / math.sqrt(2)
+    wl.walls.append(I.Wall(normal=(s, s, 0.0), offset=-0.2 * h, mode=I.WALL_FIXED, area=1.0))
+    a = oracle_lib.Oracle(wl).state()["F"]
+    wl.params.wall_corners = False
+    b = oracle_lib.Oracle(wl).state()["F"]
+    assert np.array_equal(a, b) and np.abs(a).max() > 0
