@@ -94,14 +94,23 @@ enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 
                                      the values for which a uniform stretch has energy 9Ks^2/2 and
                                      breaking the bonds across a unit area costs G_c; with
                                      PD_FLAG_TABLE_LITERAL the printed row */
-       PD_FLAG_SELF_CONTACT = 16  /* self-contact (Sec. 5): nodes of one grain with no intact bond
+       PD_FLAG_SELF_CONTACT = 16, /* self-contact (Sec. 5): nodes of one grain with no intact bond
                                      repel as nodes of different grains do (K_n (R_c - d) V_j with
                                      damping and friction).  The contact candidates then include the
                                      node's own grain; a pair whose bond is intact at the evaluation
                                      is skipped.  Requires contact_radius below every grain's
                                      lattice spacing (so no pair is shorter than R_c), else
                                      PD_ERR_INVALID; the skin guard then applies to a single grain
-                                     too */ };
+                                     too */
+       PD_FLAG_WALL_CORNERS = 32  /* several walls (Sec. 4.1.1): a node touching two or three mutually
+                                     orthogonal walls (a box edge or corner) gets the inclusion-exclusion
+                                     sum F_l + F_l' - F_ll' (+ ...) of terms -K_n (R_c - |c_S - p|) |S| e_S
+                                     over the parts S of its contact ball beyond the walls, volumes and
+                                     centroids integrated numerically; each wall's reaction takes the
+                                     corrections' components along its normal.  Damping and friction stay
+                                     per wall; walls that are not orthogonal are summed.  A small pass
+                                     before each evaluation finds the corner nodes; PD_LOOP_PERSISTENT
+                                     is then refused (PD_ERR_UNSUPPORTED) */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with

@@ -106,6 +106,9 @@ struct pd_ctx {
   int32_t* tmap = nullptr;
   StencilC* ttab = nullptr;
   int16_t* ctob = nullptr;  // [6][n_stencil]: slice-path class -> mask bit per axis order
+  double* corner_gl = nullptr;  // Gauss-Legendre nodes and weights on [0, pi] (wall corners)
+  uint32_t* corner_w = nullptr;  // [N]
+  double* corner_c = nullptr;    // [3N]
   uint32_t* mask = nullptr;  // [kMaskWords][N]
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
@@ -220,6 +223,30 @@ pd_status check_wall(pd_ctx* c, const pd_wall& w, int k) {
   return PD_OK;
 }
 
+// Gauss-Legendre rule of n points mapped to [0, pi]: nodes then weights.  The
+// roots of P_n by Newton's method from the usual cosine guesses.
+std::vector<double> gauss_legendre_0_pi(int n) {
+  std::vector<double> out((size_t)2 * n);
+  for (int i = 0; i < n; ++i) {
+    double x = cos(M_PI * (i + 0.75) / (n + 0.5)), dp = 1.0;
+    for (int it = 0; it < 100; ++it) {
+      double p0 = 1.0, p1 = x;
+      for (int k = 2; k <= n; ++k) {
+        const double p2 = ((2.0 * k - 1.0) * x * p1 - (k - 1.0) * p0) / k;
+        p0 = p1;
+        p1 = p2;
+      }
+      dp = n * (x * p1 - p0) / (x * x - 1.0);
+      const double dx = p1 / dp;
+      x -= dx;
+      if (fabs(dx) < 1e-16) break;
+    }
+    out[(size_t)i] = 0.5 * M_PI * (x + 1.0);
+    out[(size_t)(n + i)] = 0.5 * M_PI * 2.0 / ((1.0 - x * x) * dp * dp);
+  }
+  return out;
+}
+
 // the skin guard protects contact pairs; a single grain without self-contact
 // has none to miss
 int skin_guard(const pd_ctx* c) {
@@ -258,6 +285,11 @@ StepArgs step_args(pd_ctx* c) {
   A.self_contact = (c->flags & PD_FLAG_SELF_CONTACT) ? 1 : 0;
   A.colOrig = c->colOrig;
   A.ctob = c->ctob;
+  A.wall_corners = (c->flags & PD_FLAG_WALL_CORNERS) && c->n_walls > 1 ? 1 : 0;
+  A.corner_gl = c->corner_gl;
+  A.corner_ngl = kCornerGL;
+  A.corner_w = c->corner_w;
+  A.corner_c = c->corner_c;
   A.cand_ptr = c->cand_ptr;
   A.cand = c->cand;
   A.cand_capacity = c->capacity;
@@ -333,6 +365,7 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
+  HIPCHK(c, launch_wall_corners(A, 0, c->stream));
   // a single step launch records ev0/ev1 itself, tightly around the kernel
   if (c->launch.bond_path == PD_BONDS_TILES) {
     A.partial_stride = kTS * c->n_tiles;  // one wall-partial column per tile wavefront
@@ -698,7 +731,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (!(P.friction >= 0) || !isfinite(P.friction))
     return fail(c, PD_ERR_INVALID, "friction must be finite and >= 0");
   if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH | PD_FLAG_CONIC |
-                  PD_FLAG_SELF_CONTACT))
+                  PD_FLAG_SELF_CONTACT | PD_FLAG_WALL_CORNERS))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
 
@@ -827,6 +860,14 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->stencil, (int64_t)st.size(), "stencil tables"));
   TRY(alloc_n(c, &c->Kn, (int64_t)n_mat * n_mat, "K_n"));
   TRY(alloc_n(c, &c->walls, kMaxWalls, "walls"));
+  if (P.flags & PD_FLAG_WALL_CORNERS) {
+    const std::vector<double> gl = gauss_legendre_0_pi(kCornerGL);
+    TRY(alloc_n(c, &c->corner_gl, (int64_t)gl.size(), "corner quadrature"));
+    TRY(alloc_n(c, &c->corner_w, std::max<int64_t>(N, 1), "corner walls"));
+    TRY(alloc_n(c, &c->corner_c, std::max<int64_t>(3 * N, 1), "corner corrections"));
+    HIPCHK(c, hipMemcpyAsync(c->corner_gl, gl.data(), sizeof(double) * gl.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+  }
   TRY(alloc_n(c, &c->step_d, 1, "step"));
   TRY(alloc_n(c, &c->status, 1, "status"));
   TRY(alloc_n(c, &c->fin_counter, 1, "finalize counter"));
@@ -1091,6 +1132,7 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   HIPCHK(c, launch_contact_rebuild(C, 0, s));
   StepArgs A = step_args(c);
   A.advance = 0;
+  HIPCHK(c, launch_wall_corners(A, 0, s));
   HIPCHK(c, launch_step(A, MODE_FIRST, s));
   HIPCHK(c, launch_wall_finalize(A, s));
   c->built = 1;
@@ -1133,6 +1175,8 @@ pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
   if (!c || !l) return PD_ERR_INVALID;
   if (l->loop < PD_LOOP_GRAPH || l->loop > PD_LOOP_PER_GRAIN)
     return fail(c, PD_ERR_INVALID, "unknown step loop %d", l->loop);
+  if (l->loop == PD_LOOP_PERSISTENT && (c->flags & PD_FLAG_WALL_CORNERS))
+    return fail(c, PD_ERR_UNSUPPORTED, "wall corners need the per-evaluation corner pass: no persistent loop");
   const int spb = l->slices_per_block;
   if (!(spb == 1 || spb == 2 || spb == 4 || spb == 8))
     return fail(c, PD_ERR_INVALID, "slices_per_block must be 1, 2, 4 or 8");
@@ -1282,6 +1326,7 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
       if (!c->F) TRY(alloc_n(c, &c->F, 3 * N, "force output"));
       TRY(sync_columns(c));  // the force-only pass reads the bond memory from the column words
       StepArgs A = step_args(c);
+      HIPCHK(c, launch_wall_corners(A, 1, s));
       HIPCHK(c, launch_step(A, MODE_FORCE_ONLY, s));
       return soa_from_dev(c->F);
     }

@@ -54,6 +54,7 @@ struct StencilC {
 };
 constexpr int kMaxLdsTables = 48 * 1024;  // bytes of stencil tables a workgroup may stage
 constexpr int kMaxStencil = 1024;
+constexpr int kCornerGL = 32;  // Gauss-Legendre points per piece of a wall-corner region integral
 
 // ---- tiled bond loop (horizon factor 3): a workgroup owns a tile of
 // kTS x kTM x kTF lattice cells of one grain, in the grain's node-ordering axes
@@ -174,6 +175,13 @@ struct StepArgs {
   int32_t self_contact;
   const uint32_t* colOrig;
   const int16_t* ctob;
+  // inclusion-exclusion of orthogonal walls at a corner (Sec. 4.1.1):
+  // Gauss-Legendre nodes and weights on [0, pi] for the region integrals
+  int32_t wall_corners;
+  const double* corner_gl;  // [2][corner_ngl]
+  int32_t corner_ngl;
+  uint32_t* corner_w;       // [n] walls touched: count | indices << 8 (k + 1), 0 below two
+  double* corner_c;         // [n][3] corrections of those walls' normal magnitudes
 };
 
 // grid barrier state of the persistent step kernel (zeroed before each launch)
@@ -242,6 +250,8 @@ hipError_t launch_bond_count(const BuildArgs& b, hipStream_t s);
 hipError_t launch_slice_width(const BuildArgs& b, hipStream_t s);
 hipError_t launch_bond_fill(const BuildArgs& b, hipStream_t s);
 hipError_t launch_step(const StepArgs& a, int mode, hipStream_t s);
+// corner corrections of this evaluation (before the step kernel)
+hipError_t launch_wall_corners(const StepArgs& a, int force_only, hipStream_t s);
 // MODE_STEP with slices_per_block in {1, 2, 4, 8}; e0/e1, when given, are
 // recorded by the launch itself around the kernel
 hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s, hipEvent_t e0 = nullptr,

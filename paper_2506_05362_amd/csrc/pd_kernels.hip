@@ -288,6 +288,186 @@ __device__ __forceinline__ void stick_slip(double mu_fr, double rho, double dt, 
   fz = fma(-k, tz, fz);
 }
 
+// ---- several walls at a corner (Sec. 4.1.1) ----
+// Area and first moments (v, w) of {v > b, w > c, v^2 + w^2 < r^2}: for a
+// given v the region spans w in (max(c, -s), s), s = sqrt(r^2 - v^2), which
+// integrates in closed form over the pieces of the v axis where the lower end
+// is c (|v| < e = sqrt(r^2 - c^2)) or -s.  Differences of squares are taken
+// as (r - x)(r + x): with a fused multiply-add r*r - x*x at x = r leaves the
+// rounding error of x*x, whose square root would enter at 1e-8 relative.
+__device__ __forceinline__ double disk_f0(double r, double x) {
+  const double q = fmax((r - x) * (r + x), 0.0);
+  return 0.5 * (x * sqrt(q) + r * r * asin(fmin(1.0, fmax(-1.0, x / r))));
+}
+__device__ __forceinline__ double disk_f1(double r, double x) {
+  const double q = fmax((r - x) * (r + x), 0.0);
+  return -q * sqrt(q) * (1.0 / 3.0);
+}
+__device__ void disk_cut(double r, double b, double c, double& A, double& Mv, double& Mw) {
+  A = Mv = Mw = 0.0;
+  if (!(r > 0.0) || b >= r || c >= r) return;
+  const double v0 = fmax(b, -r);
+  const bool lower_c = c > -r;  // the bound w > c cuts the disk
+  const double e = lower_c ? sqrt(fmax((r - c) * (r + c), 0.0)) : r;
+  // piece |v| < e with lower end c (when the bound cuts), pieces e <= |v| < r with -s
+  for (int k = 0; k < 3; ++k) {
+    double x0, x1;
+    bool with_c;
+    if (!lower_c) {
+      if (k != 1) continue;
+      x0 = -r, x1 = r, with_c = false;
+    } else if (k == 1) {
+      x0 = -e, x1 = e, with_c = true;
+    } else {
+      if (c >= 0.0) continue;  // there -s > c: nothing outside |v| < e
+      x0 = k == 0 ? -r : e, x1 = k == 0 ? -e : r, with_c = false;
+    }
+    x0 = fmax(x0, v0);
+    if (!(x1 > x0)) continue;
+    const double dA = disk_f0(r, x1) - disk_f0(r, x0), dM = disk_f1(r, x1) - disk_f1(r, x0);
+    if (with_c) {
+      A += dA - c * (x1 - x0);
+      Mv += dM - 0.5 * c * ((x1 - x0) * (x1 + x0));
+      Mw += 0.5 * ((r - c) * (r + c) * (x1 - x0) - (x1 * x1 * x1 - x0 * x0 * x0) * (1.0 / 3.0));
+    } else {
+      A += 2.0 * dA;
+      Mv += 2.0 * dM;
+    }
+  }
+}
+
+// Volume and centroid (along u, v, w) of {|x| < R, u > a, v > b, w > c}
+// (c = -inf: two planes).  Slices u = R cos(phi) are integrated over phi, split
+// where a slice changes shape, each piece by Gauss-Legendre on a cosine map of
+// the piece (gl: nodes and weights on [0, pi]), which makes the end-point
+// power laws of the slice area smooth.
+__device__ void corner_region(const double* gl, int ngl, double R, double a, double b, double c, double& V,
+                              double& cu, double& cv, double& cw) {
+  double acc0 = 0.0, acc1 = 0.0, acc2 = 0.0, acc3 = 0.0;
+  const double u0 = fmax(a, -R);
+  double cuts[8];
+  int nc = 0;
+  cuts[nc++] = u0;
+  const double rr[3] = {fabs(b), fabs(c), sqrt(b * b + c * c)};
+  for (int k = 0; k < 3; ++k) {
+    if (!(rr[k] < R)) continue;
+    const double uk = sqrt((R - rr[k]) * (R + rr[k]));
+    if (uk > u0 && uk < R) cuts[nc++] = uk;
+    if (-uk > u0 && -uk < R) cuts[nc++] = -uk;
+  }
+  cuts[nc++] = R;
+  for (int i = 1; i < nc; ++i)
+    for (int j = i; j > 0 && cuts[j] < cuts[j - 1]; --j) {
+      const double t = cuts[j];
+      cuts[j] = cuts[j - 1];
+      cuts[j - 1] = t;
+    }
+  for (int k = 0; k + 1 < nc; ++k) {
+    if (!(cuts[k + 1] > cuts[k])) continue;
+    const double p0 = acos(fmin(1.0, fmax(-1.0, cuts[k + 1] / R)));
+    const double p1 = acos(fmin(1.0, fmax(-1.0, cuts[k] / R)));
+    const double mid = 0.5 * (p0 + p1), half = 0.5 * (p1 - p0);
+    for (int q = 0; q < ngl; ++q) {
+      const double th = gl[q], w = gl[ngl + q];
+      const double ph = mid - half * cos(th);
+      const double sp = sin(ph), u = R * cos(ph);
+      const double jw = w * half * sin(th) * R * sp;
+      double A, Mv, Mw;
+      disk_cut(R * sp, b, c, A, Mv, Mw);
+      acc0 += jw * A;
+      acc1 += jw * u * A;
+      acc2 += jw * Mv;
+      acc3 += jw * Mw;
+    }
+  }
+  V = acc0;
+  const double inv = acc0 > 0.0 ? 1.0 / acc0 : 0.0;
+  cu = acc1 * inv;
+  cv = acc2 * inv;
+  cw = acc3 * inv;
+}
+
+// Inclusion-exclusion over the walls the node touches (at most three taken,
+// in wall order): pairs of orthogonal walls subtract, an orthogonal triple
+// adds, each term -K_n (R_c - |c - p|) |S| (c - p)/|c - p| over the part S of
+// the contact ball beyond all of its walls.  Wall l takes each term's
+// component along its normal: corr[k] for the wall index hw[k].
+__device__ void wall_corner_terms(const StepArgs& A, double Kn, const double* hd, const int* hw, int nh,
+                                  double* corr) {
+  bool orth[3][3];
+  for (int x = 0; x < nh; ++x)
+    for (int y = 0; y < nh; ++y) {
+      const double* na = A.walls[hw[x]].n;
+      const double* nb = A.walls[hw[y]].n;
+      orth[x][y] = fabs(na[0] * nb[0] + na[1] * nb[1] + na[2] * nb[2]) < 1e-12;
+    }
+  // the three pairs (x, y) and, with three walls, the triple
+  const int terms = nh == 3 ? 4 : 1;
+  for (int t = 0; t < terms; ++t) {
+    int m[3] = {0, 1, -1};
+    if (t == 1) m[0] = 0, m[1] = 2;
+    if (t == 2) m[0] = 1, m[1] = 2;
+    if (t == 3) m[2] = 2;
+    const bool triple = m[2] >= 0;
+    if (!orth[m[0]][m[1]] || (triple && (!orth[m[0]][2] || !orth[m[1]][2]))) continue;
+    double V, cu, cv, cw;
+    corner_region(A.corner_gl, A.corner_ngl, A.Rc, hd[m[0]], hd[m[1]], triple ? hd[2] : -INFINITY, V, cu, cv, cw);
+    if (!(V > 0.0)) continue;
+    const double cen[3] = {cu, cv, cw};
+    double cp[3] = {0.0, 0.0, 0.0};  // c - p along the outward directions -n_l
+    for (int k = 0; k < (triple ? 3 : 2); ++k)
+      for (int q = 0; q < 3; ++q) cp[q] -= cen[k] * A.walls[hw[m[k]]].n[q];
+    const double ell = sqrt(cp[0] * cp[0] + cp[1] * cp[1] + cp[2] * cp[2]);
+    if (!(ell > 0.0)) continue;
+    const double f = (triple ? 1.0 : -1.0) * -Kn * (A.Rc - ell) * V / ell;
+    for (int k = 0; k < (triple ? 3 : 2); ++k) {
+      const double* nl = A.walls[hw[m[k]]].n;
+      corr[m[k]] += f * (cp[0] * nl[0] + cp[1] * nl[1] + cp[2] * nl[2]);
+    }
+  }
+}
+
+// Corner corrections of every node for this evaluation: nodes touching two or
+// three walls get corner_w = count | wall indices << 8 (k + 1) and their
+// corrections in corner_c; the others 0.  force_only: walls at the offsets of
+// the last evaluation.
+__global__ void k_wall_corners(StepArgs A, int force_only) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= A.n) return;
+  const double4 ui = A.ucur[i];
+  const GrainC* G = A.grains + packed_grain(ui.w);
+  const int p = packed_ijk(ui.w);
+  const double px = lattice_pos(G->origin[0], G->h, unpack_x(p)) + ui.x;
+  const double py = lattice_pos(G->origin[1], G->h, unpack_y(p)) + ui.y;
+  const double pz = lattice_pos(G->origin[2], G->h, unpack_z(p)) + ui.z;
+  int hw[3];
+  double hd[3];
+  int nh = 0;
+  for (int w = 0; w < A.n_walls && nh < 3; ++w) {
+    const WallDev* Wd = A.walls + w;
+    const bool in = px >= Wd->lo[0] && px <= Wd->hi[0] && py >= Wd->lo[1] && py <= Wd->hi[1] &&
+                    pz >= Wd->lo[2] && pz <= Wd->hi[2];
+    const double o = force_only ? Wd->off_used : Wd->off;
+    const double d = Wd->n[0] * px + Wd->n[1] * py + Wd->n[2] * pz - o;
+    if (in && d < A.Rc && d > -A.Rc) {
+      hw[nh] = w;
+      hd[nh] = d;
+      ++nh;
+    }
+  }
+  uint32_t pw = 0u;
+  if (nh >= 2) {
+    double corr[3] = {0.0, 0.0, 0.0};
+    wall_corner_terms(A, A.Kn[G->mat * A.n_mat + G->mat], hd, hw, nh, corr);
+    pw = (uint32_t)nh;
+    for (int k = 0; k < nh; ++k) {
+      pw |= (uint32_t)hw[k] << (8 * (k + 1));
+      A.corner_c[3 * i + k] = corr[k];
+    }
+  }
+  A.corner_w[i] = pw;
+}
+
 // Everything after the bond sum for the node of this lane: contact with other
 // grains, damping and friction (Secs. 3.2-3.4), rigid walls (Sec. 4.1) with the
 // wavefront's reaction partial in wall_partial column col (written when col_ok),
@@ -310,19 +490,13 @@ __device__ __forceinline__ NodeVA load_va(const StepArgs& A, int64_t i, bool val
   return r;
 }
 
-// The bond memory of the lane's node after this evaluation's breaks: on the
-// tiled path its four class-mask words and the grain's axis order (perm >= 0);
-// on the slice path (perm < 0) the live column words hold it.
-struct BondMem {
-  uint32_t w0, w1, w2, w3;
-  int perm;
-};
-
 // Is the bond from node i to node j (same grain) intact after this evaluation's
 // breaks?  The node's built entries are sorted by neighbour index, so a binary
 // search finds j's entry; a pair with no entry (outside the horizon, or cut)
-// has no bond.
-__device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j, const BondMem& bm) {
+// has no bond.  The bond memory is the live column word on the slice path
+// (perm < 0) and, on the tiled path, the class-mask bit of the grain's axis
+// order perm (the tile kernel stores a node's masks before its tail).
+__device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j, int perm) {
   const uint32_t node_mask = (1u << A.node_bits) - 1u;
   const int64_t base = A.slice_off[i >> 6] + (i & 63);
   int lo = 0, hi = A.rowlen[i] - 1;
@@ -336,10 +510,9 @@ __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j,
     } else if (jm > j) {
       hi = mid - 1;
     } else {
-      if (bm.perm < 0) return A.colE[at] == wo;
-      const int b = A.ctob[bm.perm * A.n_stencil + (int)(wo >> A.node_bits)];
-      const uint32_t w = b < 32 ? bm.w0 : b < 64 ? bm.w1 : b < 96 ? bm.w2 : bm.w3;
-      return ((w >> (b & 31)) & 1u) != 0u;
+      if (perm < 0) return A.colE[at] == wo;
+      const int b = A.ctob[perm * A.n_stencil + (int)(wo >> A.node_bits)];
+      return ((A.mask[(int64_t)(b >> 5) * A.n + i] >> (b & 31)) & 1u) != 0u;
     }
   }
   return false;
@@ -352,7 +525,7 @@ __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j,
 // repulsive-only bond of pairs shorter than R_c never arises).
 __device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j, double Xx, double Xy, double Xz,
                                              const double4& ui, const double4& vhi, int mi, double rho_i,
-                                             bool damp, bool fric, const BondMem& bm, double& fx, double& fy,
+                                             bool damp, bool fric, int perm, double& fx, double& fy,
                                              double& fz) {
   const double4 uj = A.ucur[j];
   double yx, yy, yz;
@@ -360,7 +533,7 @@ __device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j
                                A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
   if (d2 < A.Rc2 && d2 > 0.0) {
     // a node of the same grain repels only while no intact bond joins the two
-    if (A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, bm)) return;
+    if (A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, perm)) return;
     const GrainC* Gj = A.grains + packed_grain(uj.w);
     const double d = sqrt(d2);
     const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
@@ -390,7 +563,7 @@ template <int MODE>
 __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool valid, const double4& ui,
                                           const GrainC* G, int ix, int iy, int iz, double fx, double fy,
                                           double fz, int nbroke, bool col_ok, int64_t col, const NodeVA& va,
-                                          const BondMem& bm) {
+                                          int perm) {
   const int lane = threadIdx.x & 63;
   const double h = G->h;
   // mid-step velocity of this node for the normal damping (Sec. 3.4) and
@@ -409,9 +582,13 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
     if (c1 > c0) {
       const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
       for (int32_t e = c0; e < c1; ++e)
-        contact_pair(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, bm, fx, fy, fz);
+        contact_pair(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, perm, fx, fy, fz);
     }
   }
+
+  // ---- several walls at a corner (Sec. 4.1.1): the corrections of the normal
+  // magnitudes that k_wall_corners left for this node (at most three walls) ----
+  const uint32_t corner_pw = (A.wall_corners && valid) ? A.corner_w[i] : 0u;
 
   // ---- rigid walls: spherical-cap law (Sec. 4.1), walls summed ----
   for (int w = 0; w < A.n_walls; ++w) {
@@ -437,6 +614,10 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
           const double ell = 0.75 * (A.Rc + d) * (A.Rc + d) / q;
           const double rep = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
           mag = rep;
+#pragma unroll
+          for (int k = 0; k < 3; ++k)
+            if ((int)(corner_pw & 3u) > k && (int)((corner_pw >> (8 * (k + 1))) & 255u) == w)
+              mag += A.corner_c[3 * i + k];
           const double rate = MODE == MODE_FORCE_ONLY ? Wd->rate_used : Wd->rate;
           if (damp) {
             // damping against the wall: relative normal velocity v . n - wall rate
@@ -616,7 +797,7 @@ __device__ __forceinline__ void step_body(const StepArgs& A, const StencilC* s_s
   }
 
   node_tail<MODE>(A, i, valid, ui, G, ix, iy, iz, fx, fy, fz, nbroke, slice_ok,
-                  A.partial_base + (slice - A.slice_base), load_va(A, i, valid), BondMem{0u, 0u, 0u, 0u, -1});
+                  A.partial_base + (slice - A.slice_base), load_va(A, i, valid), -1);
 }
 
 __device__ __forceinline__ void stage_stencil(const StepArgs& A, StencilC* s_st) {
@@ -833,8 +1014,7 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
     for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = mask[w];
   }
   node_tail<MODE_STEP>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke, true,
-                       (int64_t)kTS * t + wid, load_va(A, i, valid),
-                       BondMem{mask[0], mask[1], mask[2], mask[3], TG.perm});
+                       (int64_t)kTS * t + wid, load_va(A, i, valid), TG.perm);
 }
 
 // the six orders of the lattice axes (slowest first)
@@ -1699,6 +1879,12 @@ hipError_t launch_cols_to_mask(const StepArgs& a, const int16_t* ctob, const uin
 hipError_t launch_mask_to_cols(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
   hipLaunchKernelGGL(k_mask_to_cols, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, ctob, colOrig);
+  return hipGetLastError();
+}
+
+hipError_t launch_wall_corners(const StepArgs& a, int force_only, hipStream_t s) {
+  if (a.n == 0 || !a.wall_corners) return hipSuccess;
+  hipLaunchKernelGGL(k_wall_corners, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, force_only);
   return hipGetLastError();
 }
 

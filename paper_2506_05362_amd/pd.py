@@ -20,6 +20,7 @@ _LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libpd_mi35
 PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_OOM, PD_ERR_HIP, PD_ERR_UNSTABLE = 0, -1, -2, -3, -4, -5
 PD_ERR_UNSUPPORTED, PD_ERR_CORRUPT = -6, -7
 FLAG_TABLE_LITERAL, FLAG_ABS_STRETCH, FLAG_NO_GRAPH, FLAG_CONIC, FLAG_SELF_CONTACT = 1, 2, 4, 8, 16
+FLAG_WALL_CORNERS = 32
 
 FIELDS = dict(displacement=0, velocity=1, accel=2, force_density=3, damage=4, intact_count=5,
               initial_count=6, bond_rowptr=7, bond_col=8, bond_broken=9, contact_rowptr=10,
@@ -236,6 +237,8 @@ class Sim:
         prm.flags = flags | (FLAG_CONIC if getattr(p, "micromodulus", "constant") == "conic" else 0)
         if getattr(p, "self_contact", False):
             prm.flags |= FLAG_SELF_CONTACT
+        if getattr(p, "wall_corners", False):
+            prm.flags |= FLAG_WALL_CORNERS
         prm.contact_radius = p.contact_radius
         prm.contact_horizon = p.contact_horizon
         prm.skin = p.skin
