@@ -10,7 +10,8 @@ point opposite ways along z, so the difference of the z components the paper
 calls bulk strength is the sum of the magnitudes), the mean damage and the
 kinetic energy.  Prints JSON lines.
 
-    python -m paper_2506_05362_amd.shape_study [--shapes sphere,shell,jack] [--duration 5e-4] [--self-contact 1]
+    python -m paper_2506_05362_amd.shape_study [--shapes sphere,shell,jack] [--duration 5e-4]
+        [--self-contact 1] [--wall-corners 1]
 """
 from __future__ import annotations
 
@@ -33,12 +34,14 @@ def run_shape(shape, a):
     wl.params.contact_damping = a.damping
     wl.params.skin = a.skin * wl.grain_h[0]
     wl.params.self_contact = bool(a.self_contact)
+    wl.params.wall_corners = bool(a.wall_corners)
     sim = pd.Sim(wl, candidate_capacity_per_node=a.capacity)
     torch.cuda.synchronize()
     info = sim.info()
     out = {"workload": wl.name, "grains": int(wl.n_grains), "nodes": info["n_nodes"], "bonds": info["nnz"],
            "setup_s": round(time.perf_counter() - t0, 2), "dt": wl.params.dt, "steps": wl.steps,
            "contact_damping": a.damping, "self_contact": bool(a.self_contact),
+           "wall_corners": bool(a.wall_corners),
            "rebuild_every": a.rebuild_every, "skin_h": a.skin,
            "lid_speed": wl.walls[1].velocity}
     print(json.dumps(out), flush=True)
@@ -100,6 +103,8 @@ def main(argv=None):
                     help="contact candidates per node (own-grain neighbours count with self-contact)")
     ap.add_argument("--self-contact", type=int, default=1, choices=(0, 1),
                     help="contact between fragments of one grain (Sec. 5)")
+    ap.add_argument("--wall-corners", type=int, default=1, choices=(0, 1),
+                    help="inclusion-exclusion of the box's walls at its edges and corners (Sec. 4.1.1)")
     ap.add_argument("--out", default=None, help="write every shape's full log to this JSON file")
     a = ap.parse_args(argv)
     results = []
