@@ -242,7 +242,7 @@ __device__ __forceinline__ double wave_sum(double x) {
 }
 
 #ifndef PD_STEP_WAVES_PER_EU
-#define PD_STEP_WAVES_PER_EU 1
+#define PD_STEP_WAVES_PER_EU 4
 #endif
 
 // 1 - (1 + x)^(-1/2) = x q(x).  For |x| <= kPolyRange q is a degree-8
@@ -523,6 +523,7 @@ __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j,
 // between nodes of one grain without an intact bond (Sec. 5, where c_w / R_c
 // is the same K_n; self-contact needs R_c below the lattice spacing, so the
 // repulsive-only bond of pairs shorter than R_c never arises).
+template <bool EXTRA>
 __device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j, double Xx, double Xy, double Xz,
                                              const double4& ui, const double4& vhi, int mi, double rho_i,
                                              bool damp, bool fric, int perm, double& fx, double& fy,
@@ -533,7 +534,8 @@ __device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j
                                A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
   if (d2 < A.Rc2 && d2 > 0.0) {
     // a node of the same grain repels only while no intact bond joins the two
-    if (A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, perm)) return;
+    if (EXTRA && A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, perm))
+      return;
     const GrainC* Gj = A.grains + packed_grain(uj.w);
     const double d = sqrt(d2);
     const double rep = A.Kn[mi * A.n_mat + Gj->mat] * (A.Rc - d) * Gj->V;
@@ -559,7 +561,9 @@ __device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j
   }
 }
 
-template <int MODE>
+// EXTRA = false compiles out self-contact and the wall-corner corrections (the
+// tiled kernel's variant for runs with neither).
+template <int MODE, bool EXTRA = true>
 __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool valid, const double4& ui,
                                           const GrainC* G, int ix, int iy, int iz, double fx, double fy,
                                           double fz, int nbroke, bool col_ok, int64_t col, const NodeVA& va,
@@ -582,13 +586,13 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
     if (c1 > c0) {
       const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
       for (int32_t e = c0; e < c1; ++e)
-        contact_pair(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, perm, fx, fy, fz);
+        contact_pair<EXTRA>(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, perm, fx, fy, fz);
     }
   }
 
   // ---- several walls at a corner (Sec. 4.1.1): the corrections of the normal
   // magnitudes that k_wall_corners left for this node (at most three walls) ----
-  const uint32_t corner_pw = (A.wall_corners && valid) ? A.corner_w[i] : 0u;
+  const uint32_t corner_pw = (EXTRA && A.wall_corners && valid) ? A.corner_w[i] : 0u;
 
   // ---- rigid walls: spherical-cap law (Sec. 4.1), walls summed ----
   for (int w = 0; w < A.n_walls; ++w) {
@@ -614,10 +618,12 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
           const double ell = 0.75 * (A.Rc + d) * (A.Rc + d) / q;
           const double rep = A.Kn[G->mat * A.n_mat + G->mat] * (A.Rc - ell) * vol;
           mag = rep;
+          if (EXTRA) {
 #pragma unroll
-          for (int k = 0; k < 3; ++k)
-            if ((int)(corner_pw & 3u) > k && (int)((corner_pw >> (8 * (k + 1))) & 255u) == w)
-              mag += A.corner_c[3 * i + k];
+            for (int k = 0; k < 3; ++k)
+              if ((int)(corner_pw & 3u) > k && (int)((corner_pw >> (8 * (k + 1))) & 255u) == w)
+                mag += A.corner_c[3 * i + k];
+          }
           const double rate = MODE == MODE_FORCE_ONLY ? Wd->rate_used : Wd->rate;
           if (damp) {
             // damping against the wall: relative normal velocity v . n - wall rate
@@ -936,7 +942,7 @@ __device__ __forceinline__ int64_t tile_cell(const TileGrain& TG, int s, int m, 
 // grain hold zeros and have no bonds), evaluate the 122 horizon classes of each
 // lane's cell from LDS, then the node tail of the slice path.  Lane l of
 // wavefront w owns cell (s0 + w, m0 + l / 16, f0 + l % 16).
-template <bool ABS>
+template <bool ABS, bool EXTRA>
 __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   // x, y and z planes of the halo box
   __shared__ double s_u[3 * kHalo];
@@ -1013,7 +1019,8 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
 #pragma unroll
     for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = mask[w];
   }
-  node_tail<MODE_STEP>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke, true,
+  node_tail<MODE_STEP, EXTRA>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke,
+                              true,
                        (int64_t)kTS * t + wid, load_va(A, i, valid), TG.perm);
 }
 
@@ -1850,16 +1857,23 @@ hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double*
   return hipGetLastError();
 }
 
+template <bool ABS, bool EXTRA>
+void launch_tile_variant(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
+  const dim3 grid((unsigned)a.n_tiles), block(kTS * kWave);
+  void (*kern)(StepArgs) = k_step_tile<ABS, EXTRA>;
+  if (e0 || e1) hipExtLaunchKernelGGL(kern, grid, block, 0, s, e0, e1, 0, a);
+  else hipLaunchKernelGGL(kern, grid, block, 0, s, a);
+}
+
 hipError_t launch_step_tile(const StepArgs& a, hipStream_t s, hipEvent_t e0, hipEvent_t e1) {
   if (a.n_tiles == 0) return hipSuccess;
-  const dim3 grid((unsigned)a.n_tiles), block(kTS * kWave);
-  if (e0 || e1) {
-    if (a.abs_stretch) hipExtLaunchKernelGGL(k_step_tile<true>, grid, block, 0, s, e0, e1, 0, a);
-    else hipExtLaunchKernelGGL(k_step_tile<false>, grid, block, 0, s, e0, e1, 0, a);
-  } else if (a.abs_stretch) {
-    hipLaunchKernelGGL(k_step_tile<true>, grid, block, 0, s, a);
+  const bool extra = a.self_contact || a.wall_corners;
+  if (a.abs_stretch) {
+    if (extra) launch_tile_variant<true, true>(a, s, e0, e1);
+    else launch_tile_variant<true, false>(a, s, e0, e1);
   } else {
-    hipLaunchKernelGGL(k_step_tile<false>, grid, block, 0, s, a);
+    if (extra) launch_tile_variant<false, true>(a, s, e0, e1);
+    else launch_tile_variant<false, false>(a, s, e0, e1);
   }
   return hipGetLastError();
 }

@@ -8,6 +8,7 @@ start, logging the platen stress, the mean damage and the kinetic energy every
 100 steps, until the requested axial strain or the time budget.  Prints JSON.
 
     python -m paper_2506_05362_amd.scale_bench [--steps 200] [--strain 0.05] [--budget 120]
+        [--self-contact 0] [--wall-corners 0]
 """
 from __future__ import annotations
 
@@ -48,6 +49,10 @@ def main(argv=None):
     ap.add_argument("--rebuild-every", type=int, default=5)
     ap.add_argument("--skin", type=float, default=0.5, help="Verlet skin in lattice spacings")
     ap.add_argument("--capacity", type=int, default=32, help="contact candidates per node")
+    ap.add_argument("--self-contact", type=int, default=0, choices=(0, 1),
+                    help="contact between fragments of one grain (Sec. 5)")
+    ap.add_argument("--wall-corners", type=int, default=0, choices=(0, 1),
+                    help="inclusion-exclusion of the box's walls at its edges and corners (Sec. 4.1.1)")
     a = ap.parse_args(argv)
     import torch
 
@@ -55,6 +60,8 @@ def main(argv=None):
     wl = I.large_aggregate(seed=a.seed, axial_strain=a.strain, rebuild_every=a.rebuild_every)
     wl.params.contact_damping = a.damping
     wl.params.skin = a.skin * wl.grain_h[0]
+    wl.params.self_contact = bool(a.self_contact)
+    wl.params.wall_corners = bool(a.wall_corners)
     gen_s = time.perf_counter() - t0
     t0 = time.perf_counter()
     sim = pd.Sim(wl, candidate_capacity_per_node=a.capacity)
@@ -66,7 +73,9 @@ def main(argv=None):
            "bonds": info["nnz"], "padded_slots": info["padded"],
            "grain_nodes_min": int(sizes.min()), "grain_nodes_max": int(sizes.max()),
            "generate_s": round(gen_s, 1), "build_s": round(build_s, 2),
-           "contact_damping": a.damping, "rebuild_every": a.rebuild_every, "skin_h": a.skin, "candidate_capacity_per_node": a.capacity, "dt": wl.params.dt,
+           "contact_damping": a.damping, "rebuild_every": a.rebuild_every, "skin_h": a.skin,
+           "candidate_capacity_per_node": a.capacity, "dt": wl.params.dt,
+           "self_contact": bool(a.self_contact), "wall_corners": bool(a.wall_corners),
            "platen_speed": wl.walls[1].velocity,
            "device_bytes": int(torch.cuda.memory_allocated())}
     print(json.dumps(out), flush=True)
