@@ -101,8 +101,12 @@ def tune(sim: "pd.Sim", steps: Optional[int] = None, use_cache: bool = True,
     path = path or cache_path()
     info = sim.info()
     key = shape_key(_arch(), info["n_nodes"], info["nnz"], np.diff(sim.wl.grain_begin))
+    # the wall-corner pass runs before every evaluation, which one persistent
+    # launch of several steps cannot host
+    if getattr(sim.wl.params, "wall_corners", False):
+        persistent = False
     table = _load(path) if use_cache else {}
-    if use_cache and key in table:
+    if use_cache and key in table and (persistent or table[key]["config"]["loop"] != pd.LOOP_PERSISTENT):
         cfg = table[key]["config"]
         sim.set_launch(**cfg)
         return {"config": cfg, "key": key, "cached": True, "times": table[key].get("times", {})}
