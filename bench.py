@@ -99,8 +99,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path "
-              "(the sharding design is described in DESIGN.md)", file=sys.stderr)
+        print("bench.py measures one GPU: the library runs on a single device (a multi-GPU run "
+              "would shard grains by spatial bisection and exchange surface-node halos)", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -51,7 +51,7 @@ enum {
   PD_ERR_HIP = -4,         /* a HIP runtime call failed */
   PD_ERR_UNSTABLE = -5,    /* NaN/Inf force, wall penetration (d <= -R_c), Verlet skin
                               exceeded, or contact-candidate capacity exceeded */
-  PD_ERR_UNSUPPORTED = -6, /* valid request this build does not implement */
+  PD_ERR_UNSUPPORTED = -6, /* valid request the library does not implement */
   PD_ERR_CORRUPT = -7      /* checkpoint blob failed its size/magic/CRC check */
 };
 
