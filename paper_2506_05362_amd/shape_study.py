@@ -30,7 +30,8 @@ def run_shape(shape, a):
     import torch
 
     t0 = time.perf_counter()
-    wl = I.shape_study(shape, seed=a.seed, duration=a.duration, rebuild_every=a.rebuild_every)
+    wl = I.shape_study(shape, seed=a.seed, grid=a.grid, cavity=a.cavity, h=a.h, dt=a.dt, duration=a.duration,
+                       rebuild_every=a.rebuild_every)
     wl.params.contact_damping = a.damping
     wl.params.skin = a.skin * wl.grain_h[0]
     wl.params.self_contact = bool(a.self_contact)
@@ -39,6 +40,7 @@ def run_shape(shape, a):
     torch.cuda.synchronize()
     info = sim.info()
     out = {"workload": wl.name, "grains": int(wl.n_grains), "nodes": info["n_nodes"], "bonds": info["nnz"],
+           "cavity": a.cavity if shape == "shell" else None,
            "setup_s": round(time.perf_counter() - t0, 2), "dt": wl.params.dt, "steps": wl.steps,
            "contact_damping": a.damping, "self_contact": bool(a.self_contact),
            "wall_corners": bool(a.wall_corners),
@@ -60,7 +62,7 @@ def run_shape(shape, a):
 
     sim.set_state(start)
     sim.set_launch(bond_path=pd.BONDS_TILES if best == "tiles" else pd.BONDS_SLICES)
-    unit = 500  # 5 us at dt = 10 ns
+    unit = a.log_steps
     mass = wl.materials[0].density * wl.grain_h[0] ** 3
     log, done, status = [], 0, "complete"
     t0 = time.perf_counter()
@@ -78,7 +80,7 @@ def run_shape(shape, a):
         log.append({"t_5us": round(done * wl.params.dt / 5e-6, 3), "lid_n": top, "floor_n": floor,
                     "bulk_strength_n": top + floor, "mean_damage": float(sim.get("damage").mean()),
                     "kinetic_energy_j": float(0.5 * mass * np.sum(v * v))})
-        if len(log) % 10 == 0 or done == wl.steps:
+        if len(log) % max(1, 5000 // unit) == 0 or done == wl.steps:
             print(shape, json.dumps(log[-1]), flush=True)
     out["compression"] = {"steps": done, "status": status, "seconds": time.perf_counter() - t0,
                           "ms_per_step": 1e3 * (time.perf_counter() - t0) / max(done, 1), "log": log}
@@ -89,6 +91,11 @@ def run_shape(shape, a):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--shapes", default=",".join(I.SHAPES))
+    ap.add_argument("--grid", type=int, default=5, help="grains per side (1: one grain in the box)")
+    ap.add_argument("--cavity", type=float, default=0.5, help="shell cavity radius over the outer radius")
+    ap.add_argument("--h", type=float, default=1e-4, help="lattice spacing [m] (grain radius 1 mm)")
+    ap.add_argument("--dt", type=float, default=1e-8, help="time step [s]")
+    ap.add_argument("--log-steps", type=int, default=500, help="steps between log entries (500: 5 us at 10 ns)")
     ap.add_argument("--duration", type=float, default=5e-4, help="simulated seconds (the paper plots 500 us)")
     ap.add_argument("--time-steps", type=int, default=200, help="steps timed per bond path")
     ap.add_argument("--seed", type=int, default=0)
