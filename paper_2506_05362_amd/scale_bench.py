@@ -48,12 +48,16 @@ def main(argv=None):
                          "2.8e22 at h = 70 um scaled by h^-4 to h = 41 um")
     ap.add_argument("--rebuild-every", type=int, default=5)
     ap.add_argument("--skin", type=float, default=0.5, help="Verlet skin in lattice spacings")
-    ap.add_argument("--capacity", type=int, default=32, help="contact candidates per node")
+    ap.add_argument("--capacity", type=int, default=0,
+                    help="contact candidates per node (0: 32, or 48 with self-contact, whose rows "
+                         "also hold the own grain's neighbours)")
     ap.add_argument("--self-contact", type=int, default=0, choices=(0, 1),
                     help="contact between fragments of one grain (Sec. 5)")
     ap.add_argument("--wall-corners", type=int, default=0, choices=(0, 1),
                     help="inclusion-exclusion of the box's walls at its edges and corners (Sec. 4.1.1)")
     a = ap.parse_args(argv)
+    if a.capacity <= 0:
+        a.capacity = 48 if a.self_contact else 32
     import torch
 
     t0 = time.perf_counter()
