@@ -606,3 +606,67 @@ def test_large_aggregate_with_corners_and_self_contact_matches_oracle(oracle_lib
         assert_state_close(sim, ora, what=f"bond path {bp}")
         assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
         sim.close()
+
+
+def test_notched_plate_full_size_in_the_bench_configuration(oracle_lib):
+    """The benchmark workload at full size (720,000 nodes, 80,821,072 bonds) in
+    the configuration the benchmark times (tiled bond path, graph-replayed
+    steps): after 150 steps of the impact every node's u, v, a and F within
+    1e-9 of the oracle and the projectile wall's reaction within 1e-6."""
+    from paper_2506_05362_amd import pd
+    wl = I.notched_plate()
+    sim = gpu_sim(wl)
+    sim.set_launch(loop=pd.LOOP_GRAPH, bond_path=pd.BONDS_TILES)
+    sim.step(150)
+    print("gpu done", flush=True)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
+    assert ora.step(150) == 0
+    print("oracle done", flush=True)
+    assert ora.min_margin() > 1e-9  # no stretch near s0: bond decisions are unambiguous
+    assert_state_close(sim, ora, what="full-size plate")
+    fo, _ = ora.walls()
+    assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+    assert np.array_equal(sim.bonds()[2], ora.bonds()[2])
+    sim.close()
+
+
+def test_uneven_aggregate_full_size_matches_oracle(oracle_lib):
+    """The uneven-grain aggregate at full size (100 grains of 2e3-5e4 nodes,
+    1.72 M nodes) in the batched graph-replayed launch: after 40 steps state
+    within 1e-9 of the oracle and platen forces within 1e-6."""
+    from paper_2506_05362_amd import pd
+    wl = I.grain_aggregate(seed=0, rebuild_every=20)
+    sim = gpu_sim(wl)
+    sim.set_launch(loop=pd.LOOP_GRAPH)
+    sim.step(40)
+    print("gpu done", flush=True)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
+    assert ora.step(40) == 0
+    print("oracle done", flush=True)
+    assert_state_close(sim, ora, what="full-size aggregate", a_scale=None)
+    fo, _ = ora.walls()
+    assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+    sim.close()
+
+
+def test_representative_volume_full_size_matches_oracle(oracle_lib):
+    """The representative volume at full size (200 tessellated grains, 373,248
+    nodes, six walls of which four are servo-controlled), with the surrogate's
+    servo gain and damping plus friction and the platen at 20 m/s, so that it
+    loads the aggregate within the run: after 200 steps state 1e-9, wall
+    forces and offsets 1e-6."""
+    from paper_2506_05362_amd import pd
+    wl = I.rve_aggregate(seed=0, platen_speed=20.0, contact_damping=2.8e22, servo_gain=5e-8, rebuild_every=10,
+                         friction=0.3)
+    sim = gpu_sim(wl)
+    sim.step(200)
+    print("gpu done", flush=True)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
+    assert ora.step(200) == 0
+    print("oracle done", flush=True)
+    assert_state_close(sim, ora, what="full-size volume")
+    fo, oo = ora.walls()
+    assert np.abs(fo[1]).max() > 0  # the platen carries load
+    assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+    assert rel_inf(sim.get("wall_offset"), oo) <= 1e-6
+    sim.close()
