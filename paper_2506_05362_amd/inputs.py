@@ -667,13 +667,15 @@ def shape_grain(rng: np.random.Generator, shape: str, radius: float, h: float,
     return pts[:, inside], o, rin
 
 
-def shape_study(shape: str = "sphere", seed: int = 0, grid: int = 5, radius: float = 1e-3,
+def shape_study(shape: str = "sphere", seed: int = 0, grid=5, radius: float = 1e-3,
                 h: float = 1e-4, gap: float = 1.0, lid_speed: float = 10.0, dt: float = 1e-8,
                 duration: float = 5e-4, material: Material = SAND, rebuild_every: int = 5,
                 arm_half_width: float = 0.25, cavity: float = 0.5) -> Workload:
     """grid^3 grains of one shape (Sec. 7.6: 125 grains of radius 1 mm on a
     cubic grid, solid spheres, hollow spheres or jacks) in a box of rigid walls
-    whose lid moves down at lid_speed (10 m/s in the paper).
+    whose lid moves down at lid_speed (10 m/s in the paper).  grid is the
+    number of grains per side, or (nx, ny, nz) (1, 1, 2: two stacked grains,
+    the double hollow sphere of Sec. 6).
 
     Grid pitch 2*radius + gap*h; the floor and the four side walls sit R_c
     beyond the outermost nodes, the lid R_c above the highest node, so no node
@@ -682,9 +684,10 @@ def shape_study(shape: str = "sphere", seed: int = 0, grid: int = 5, radius: flo
     rng = np.random.default_rng(seed)
     params = default_params(h, dt, rebuild_every=rebuild_every)
     pitch = 2.0 * radius + gap * h
+    gx, gy, gz = (grid, grid, grid) if isinstance(grid, int) else tuple(grid)
     blocks, cuts = [], []
-    for g in range(grid ** 3):
-        a, b, c = g % grid, (g // grid) % grid, g // (grid * grid)
+    for g in range(gx * gy * gz):
+        a, b, c = g % gx, (g // gx) % gy, g // (gx * gy)
         centre = np.array([a, b, c], dtype=np.float64) * pitch
         off, o, rin = shape_grain(rng, shape, radius, h, arm_half_width, cavity)
         ijk, origin = _grain_block(off, centre + o * h, h)

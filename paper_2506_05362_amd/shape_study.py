@@ -91,7 +91,8 @@ def run_shape(shape, a):
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--shapes", default=",".join(I.SHAPES))
-    ap.add_argument("--grid", type=int, default=5, help="grains per side (1: one grain in the box)")
+    ap.add_argument("--grid", default="5",
+                    help="grains per side, or nx,ny,nz (1: one grain in the box; 1,1,2: two stacked)")
     ap.add_argument("--cavity", type=float, default=0.5, help="shell cavity radius over the outer radius")
     ap.add_argument("--h", type=float, default=1e-4, help="lattice spacing [m] (grain radius 1 mm)")
     ap.add_argument("--dt", type=float, default=1e-8, help="time step [s]")
@@ -114,6 +115,7 @@ def main(argv=None):
                     help="inclusion-exclusion of the box's walls at its edges and corners (Sec. 4.1.1)")
     ap.add_argument("--out", default=None, help="write every shape's full log to this JSON file")
     a = ap.parse_args(argv)
+    a.grid = int(a.grid) if "," not in a.grid else tuple(int(v) for v in a.grid.split(","))
     results = []
     for shape in a.shapes.split(","):
         results.append(run_shape(shape, a))
