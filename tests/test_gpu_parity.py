@@ -670,3 +670,28 @@ def test_representative_volume_full_size_matches_oracle(oracle_lib):
     assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
     assert rel_inf(sim.get("wall_offset"), oo) <= 1e-6
     sim.close()
+
+
+def test_stacked_thin_shells_match_oracle(oracle_lib):
+    """Two stacked thin shells (cavity 3R/4, Sec. 6) under the lid with
+    self-contact, wall corners, damping and friction: state 1e-9 and wall
+    forces 1e-6 through both bond paths."""
+    from paper_2506_05362_amd import pd
+    wl = I.shape_study("shell", seed=6, grid=(1, 1, 2), radius=6e-4, h=1e-4, cavity=0.75, lid_speed=50.0,
+                       duration=1e-5)
+    wl.params.skin = 0.5 * wl.grain_h[0]
+    wl.params.contact_damping = 1e21
+    wl.params.friction = 0.3
+    wl.params.self_contact = True
+    wl.params.wall_corners = True
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    assert ora.step(wl.steps) == 0
+    fo, _ = ora.walls()
+    assert np.abs(fo[1]).max() > 0
+    for bp in (pd.BONDS_SLICES, pd.BONDS_TILES):
+        sim = gpu_sim(wl)
+        sim.set_launch(bond_path=bp)
+        sim.step(wl.steps)
+        assert_state_close(sim, ora, what=f"stacked shells, bond path {bp}")
+        assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+        sim.close()
