@@ -2,14 +2,19 @@
 
 One step = the whole hot path through the C ABI (pd_step): contact-candidate
 rebuild on its cadence, the fused bond-force / break / damage / contact / wall /
-velocity-Verlet kernel, and the wall reduction.  The workload is the
-double-notched plate (100 x 100 x 9 mm at h = 0.5 mm: 720,000 nodes, horizon 3h,
-about 81 M directed bonds) struck on its edge by a rigid projectile face at
-32 m/s; inputs are seeded, synthetic, and resident in HBM before timing starts.
+velocity-Verlet kernel, and the wall reduction.
 
-Prints one JSON line with the metric, the roofline of the fused step kernel
-(algorithmic bytes per launch over its event-timed average duration) and the
-CPU oracle timed on the host cores on a bounded sample of the same workload.
+The headline workload is the large aggregate: 999 tessellated grains with
+log-normal sizes on one lattice (h = 41 um), 9,261,000 nodes and 967,622,492
+directed bonds in a box of six walls, compressed by the platen at 10 m/s.  A
+second object in the same line times the double-notched plate (720,000 nodes)
+struck by a projectile face.  Inputs are seeded, synthetic, and resident in HBM
+before timing starts.
+
+The timed region replays the captured step loop (HIP graphs of rebuild_every
+steps) with event-record nodes around every step kernel on the library's
+stream, so the kernel's average duration (the roofline's denominator) comes
+from the same region as the step rate.  Prints one JSON line.
 """
 from __future__ import annotations
 
@@ -17,6 +22,7 @@ import argparse
 import hashlib
 import json
 import os
+import platform
 import sys
 import time
 
@@ -25,13 +31,13 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_05362_amd", "csrc", "pd_kernels.hip")
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_k_step_tile_notched_plate.json")
+PROFILES = os.path.join(ROOT, "profiles")
 
-# algorithmic bytes of the fused step kernel (per launch):
-#   per directed bond : 4 B column word (it also carries the bond-broken state)
-#   per node          : read u, v, a (72 B) + write u, v, a (72 B) + 4 B lattice/grain word
-BYTES_PER_BOND = 4.0
-BYTES_PER_NODE = 148.0
+# Algorithmic bytes of one step-kernel launch (CSR byte model):
+#   per directed bond : 4 B column word + 1 bit of bond-broken mask = 4.125 B
+#   per node          : 128 B (read u, X, v; write u, v; 8 B damage/intact)
+BYTES_PER_BOND = 4.125
+BYTES_PER_NODE = 128.0
 
 
 def kernel_hash() -> str:
@@ -41,6 +47,8 @@ def kernel_hash() -> str:
 
 def workload(name: str):
     from paper_2506_05362_amd import inputs as I
+    if name == "large_aggregate":
+        return I.large_aggregate()
     if name == "notched_plate":
         return I.notched_plate()
     if name == "two_spheres":
@@ -50,52 +58,184 @@ def workload(name: str):
     raise SystemExit(f"unknown workload {name}")
 
 
+def host_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except AttributeError:
+        usable = os.cpu_count() or 1
+    return {"cpu_model": model, "logical_cpus": os.cpu_count() or 1, "usable_cpus": usable}
+
+
 def cpu_baseline(wl, nnz_gpu: int, budget_s: float):
-    """The oracle as it stands, on a bounded number of steps of the same workload."""
+    """The oracle as it stands, timed on a bounded number of steps of the same
+    workload after its bond build: with as many threads as the host gives this
+    process (at most 16) and with one thread."""
     from oracle import pdref
-    threads = max(1, min(16, os.cpu_count() or 1))
+    hi = host_info()
+    threads = max(1, min(16, hi["usable_cpus"]))
+    t0 = time.perf_counter()
     ora = pdref.Oracle(wl, flags=pdref.CELL_LIST, threads=threads)
-    t0 = time.perf_counter()
-    ora.step(1)
-    t1 = time.perf_counter() - t0
-    n = max(1, min(200, int(budget_s / max(t1, 1e-6))))
-    t0 = time.perf_counter()
-    ora.step(n)
-    dt = time.perf_counter() - t0
+    build_s = time.perf_counter() - t0
+    assert ora.nnz == nnz_gpu, (ora.nnz, nnz_gpu)
+    print(f"[bench] oracle built in {build_s:.1f} s", file=sys.stderr, flush=True)
+
+    def timed(nthreads, share):
+        pdref.lib().pdref_set_threads(nthreads)
+        t = time.perf_counter()
+        ora.step(1)
+        one = time.perf_counter() - t
+        if one >= share * budget_s:  # one step already fills the share
+            return 1, one
+        n = max(1, min(200, int(share * budget_s / max(one, 1e-6))))
+        t = time.perf_counter()
+        ora.step(n)
+        return n, time.perf_counter() - t
+
+    n_all, t_all = timed(threads, 0.6)
+    n_one, t_one = timed(1, 0.4)
     nnz = ora.nnz
-    assert nnz == nnz_gpu, (nnz, nnz_gpu)
-    return {"value": nnz * n / dt, "unit": "bond-updates/s", "cores": threads, "kind": "oracle",
-            "sample": f"{n} steps of the same {wl.n_nodes}-node workload after its bond build "
-                      f"({dt:.2f} s, {threads} OpenMP threads, plain C FP64)"}
+    return {"value": nnz * n_all / t_all, "unit": "bond-updates/s", "cores": threads, "kind": "oracle",
+            "sample": f"{n_all} steps of the same {wl.n_nodes}-node workload after its bond build "
+                      f"({t_all:.2f} s on {threads} OpenMP threads, plain C FP64, -O2 -ffp-contract=off); "
+                      f"one thread: {n_one} steps in {t_one:.2f} s",
+            "one_thread_value": nnz * n_one / t_one, "host": hi}
+
+
+def traffic_record(workload_name: str, kernel: str):
+    """HBM bytes per launch of the kernel from rocprofv3 counters, when the record
+    was taken on the current kernel source."""
+    path = os.path.join(PROFILES, f"traffic_{kernel}_{workload_name}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        tr = json.load(f)
+    if tr.get("kernel_src_sha256_16") != kernel_hash() or tr.get("workload") != workload_name:
+        return None
+    return tr.get("bytes_per_launch")
+
+
+def time_workload(name: str, steps: int, warmup: int, bond_path_arg: str):
+    """Build the workload, warm it up, align to the captured loop and time
+    `steps` steps.  Returns the measurement and the workload."""
+    import torch
+    from paper_2506_05362_amd import pd
+
+    wl = workload(name)
+    t0 = time.perf_counter()
+    sim = pd.Sim(wl)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - t0
+    bond_path = pd.BONDS_SLICES
+    if bond_path_arg in ("auto", "tiles"):
+        try:
+            sim.set_launch(bond_path=pd.BONDS_TILES)
+            bond_path = pd.BONDS_TILES
+        except pd.PDError:
+            if bond_path_arg == "tiles":
+                raise
+    info = sim.info()
+    nnz, N = info["nnz"], info["n_nodes"]
+    print(f"[bench] {name}: {N} nodes, {nnz} bonds, padded {info['padded']}, build {build_s:.2f} s",
+          file=sys.stderr, flush=True)
+    sim.step(warmup)
+    # the captured loop replays runs of graph_len steps that start on a multiple
+    # of graph_len: step on (untimed) to the next such start
+    graph_len = wl.params.rebuild_every if wl.params.rebuild_every % 2 == 0 else 2 * wl.params.rebuild_every
+    align = (-(warmup)) % graph_len
+    sim.step(align)
+    torch.cuda.synchronize()
+    print(f"[bench] {name}: warmup {warmup} + {align} alignment steps done", file=sys.stderr, flush=True)
+
+    stream = sim.plumbing.stream  # the stream every kernel of the context runs on
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    counts0 = sim.loop_counts()
+    sim.set_timing(True)
+    torch.cuda.synchronize()
+    start.record(stream)
+    sim.step(steps)
+    stop.record(stream)
+    torch.cuda.synchronize()
+    total_ms = start.elapsed_time(stop)
+    launches, kern_ms = sim.timing()
+    sim.set_timing(False)
+    counts1 = sim.loop_counts()
+    replayed = counts1["graph_steps"] - counts0["graph_steps"]
+    direct = counts1["direct_steps"] - counts0["direct_steps"]
+    avg_kernel_s = kern_ms / 1e3 / max(launches, 1)
+    print(f"[bench] {name}: timed {steps} steps ({replayed} in graph replays, {direct} direct): "
+          f"{total_ms:.2f} ms, step kernel {avg_kernel_s * 1e6:.1f} us over {launches} launches",
+          file=sys.stderr, flush=True)
+    kernel = "k_step_tile" if bond_path == pd.BONDS_TILES else "k_step"
+    bytes_launch = nnz * BYTES_PER_BOND + N * BYTES_PER_NODE
+    achieved = bytes_launch / avg_kernel_s / 1e9
+    out = {
+        "value": nnz * steps / (total_ms / 1e3),
+        "ms_per_step": total_ms / steps,
+        "config": {"workload": name, "nodes": N, "bonds": nnz, "grains": wl.n_grains,
+                   "step_loop": f"hip graph replay ({replayed} of {steps} timed steps; {direct} launched directly)",
+                   "bond_path": pd.BOND_PATH_NAMES[bond_path], "padded_slots": info["padded"],
+                   "dt": wl.params.dt, "horizon_factor": wl.params.horizon_factor,
+                   "rebuild_every": wl.params.rebuild_every, "walls": len(wl.walls),
+                   "timed_steps": [warmup + align + 1, warmup + align + steps],
+                   "build_s": round(build_s, 3)},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(name, kernel),
+                     "kernel": kernel, "avg_launch_us": avg_kernel_s * 1e6, "launches": launches,
+                     "algorithmic_bytes_per_launch": bytes_launch,
+                     "bytes_model": f"{BYTES_PER_BOND} B per directed bond + {BYTES_PER_NODE} B per node",
+                     "kernel_bond_updates_per_s": nnz / avg_kernel_s},
+    }
+    sim.close()
+    return out, wl
 
 
 def copy_probe():
-    """Plain device kernels of known size, for scaling hardware byte counters:
-    a fill (writes 1 GiB) and a scale (reads 1 GiB, writes 1 GiB)."""
+    """Attainable HBM bandwidth: a plain device copy of 4 GiB (reads 4 GiB, writes
+    4 GiB) timed with events, best of 5."""
     import torch
-    n = 1 << 27  # 1 GiB of float64
+    n = 1 << 29  # 4 GiB of float64
     x = torch.ones(n, dtype=torch.float64, device="cuda")
     y = torch.empty_like(x)
-    for _ in range(3):
-        torch.mul(x, 2.0, out=y)
-    torch.cuda.synchronize()
-    print(json.dumps({"copy_probe_bytes": 8 * n}), flush=True)
+    best = None
+    for _ in range(6):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        torch.cuda.synchronize()
+        ms = a.elapsed_time(b)
+        best = ms if best is None else min(best, ms)
+    del x, y
+    torch.cuda.empty_cache()
+    return {"bytes": 16 * n, "best_ms": best, "GB_per_s": 16 * n / (best / 1e3) / 1e9}
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=2000)
-    ap.add_argument("--warmup", type=int, default=200)
-    ap.add_argument("--workload", default="notched_plate")
-    ap.add_argument("--cpu-budget", type=float, default=15.0)
+    ap.add_argument("--steps", type=int, default=40)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="large_aggregate")
+    ap.add_argument("--secondary", default="notched_plate",
+                    help="second workload timed in the same run ('' for none)")
+    ap.add_argument("--cpu-budget", type=float, default=25.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-probe", action="store_true")
+    ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--bond-path", choices=["auto", "slices", "tiles"], default="auto",
                     help="bond loop: LDS tiles where the mesh allows (auto), or force one")
     ap.add_argument("--surrogate", action="store_true",
                     help="also run the representative-volume surrogate pipeline (64 simulated "
-                         "paths, training, held-out error, inference speed; several minutes)")
+                         "paths, training, held-out error, inference speed; many minutes)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
@@ -103,104 +243,37 @@ def main():
               "would shard grains by spatial bisection and exchange surface-node halos)", file=sys.stderr)
         sys.exit(2)
 
-    import torch
-    from paper_2506_05362_amd import pd
+    import torch  # noqa: F401
 
-    if args.copy_probe:
-        copy_probe()
-
-    wl = workload(args.workload)
-    t0 = time.perf_counter()
-    sim = pd.Sim(wl)
-    torch.cuda.synchronize()
-    build_s = time.perf_counter() - t0
-    bond_path = pd.BONDS_SLICES
-    if args.bond_path in ("auto", "tiles"):
-        try:
-            sim.set_launch(bond_path=pd.BONDS_TILES)
-            bond_path = pd.BONDS_TILES
-        except pd.PDError:
-            if args.bond_path == "tiles":
-                raise
-    info = sim.info()
-    nnz, N = info["nnz"], info["n_nodes"]
-    print(f"[bench] {args.workload}: {N} nodes, {nnz} bonds, padded {info['padded']}, "
-          f"build {build_s:.2f} s", file=sys.stderr, flush=True)
-
-    sim.step(args.warmup)
-    torch.cuda.synchronize()
-    print(f"[bench] warmup {args.warmup} steps done", file=sys.stderr, flush=True)
-
-    stream = sim.plumbing.stream  # the stream every kernel of the context runs on
-    start = torch.cuda.Event(enable_timing=True)
-    stop = torch.cuda.Event(enable_timing=True)
-
-    # timed region 1: the production path (captured step loop replayed as HIP graphs)
-    torch.cuda.synchronize()
-    start.record(stream)
-    sim.step(args.steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    total_ms = start.elapsed_time(stop)
-    print(f"[bench] timed {args.steps} steps (graph replay): {total_ms:.1f} ms", file=sys.stderr,
-          flush=True)
-
-    # timed region 2: the same steps launched directly, every step kernel bracketed
-    # by HIP events on the context stream (its average duration feeds the roofline)
-    sim.set_timing(True)
-    torch.cuda.synchronize()
-    start.record(stream)
-    sim.step(args.steps)
-    stop.record(stream)
-    torch.cuda.synchronize()
-    direct_ms = start.elapsed_time(stop)
-    launches, kern_ms = sim.timing()
-    sim.set_timing(False)
-    print(f"[bench] timed {args.steps} steps (direct launches): {direct_ms:.1f} ms, step kernel "
-          f"{kern_ms / max(launches, 1) * 1e3:.1f} us", file=sys.stderr, flush=True)
-
-    value = nnz * args.steps / (total_ms / 1e3)
-    avg_kernel_s = kern_ms / 1e3 / max(launches, 1)
-    bytes_launch = nnz * BYTES_PER_BOND + N * BYTES_PER_NODE
-    achieved = bytes_launch / avg_kernel_s / 1e9
-
-    traffic = None
-    if os.path.exists(TRAFFIC_FILE):
-        with open(TRAFFIC_FILE) as f:
-            tr = json.load(f)
-        if tr.get("kernel_src_sha256_16") == kernel_hash() and tr.get("workload") == args.workload:
-            traffic = tr.get("bytes_per_launch")
-
+    probe = None if args.no_copy_probe else copy_probe()
+    if probe:
+        print(f"[bench] copy probe: {probe['GB_per_s']:.0f} GB/s", file=sys.stderr, flush=True)
+    head, wl = time_workload(args.workload, args.steps, args.warmup, args.bond_path)
     out = {
         "metric": "bond updates/s",
-        "value": value,
+        "value": head["value"],
         "unit": "bond-updates/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": total_ms / args.steps,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": args.workload, "nodes": N, "bonds": nnz,
-                   "step_loop": "hip graph replay", "bond_path": pd.BOND_PATH_NAMES[bond_path],
-                   "direct_launch_ms_per_step": direct_ms / args.steps,
-                   "padded_slots": info["padded"], "dt": wl.params.dt,
-                   "horizon_factor": wl.params.horizon_factor,
-                   "rebuild_every": wl.params.rebuild_every, "walls": len(wl.walls),
-                   "build_s": round(build_s, 3)},
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel": "k_step_tile" if bond_path == pd.BONDS_TILES else "k_step<MODE_STEP>",
-                     "avg_launch_us": avg_kernel_s * 1e6,
-                     "launches": launches, "algorithmic_bytes_per_launch": bytes_launch,
-                     "kernel_bond_updates_per_s": nnz / avg_kernel_s},
+        "config": head["config"],
+        "roofline": head["roofline"],
     }
-    sim.close()
+    if probe:
+        out["roofline"]["attainable_copy_GBps"] = probe["GB_per_s"]
+        out["roofline"]["frac_of_attainable"] = out["roofline"]["achieved"] / probe["GB_per_s"]
+    if args.secondary:
+        sec, _ = time_workload(args.secondary, args.steps, args.warmup, args.bond_path)
+        out["secondary"] = {"workload": args.secondary, "value": sec["value"], "ms_per_step": sec["ms_per_step"],
+                            "config": sec["config"], "roofline": sec["roofline"]}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(wl, nnz, args.cpu_budget)
+        out["cpu_baseline"] = cpu_baseline(wl, head["config"]["bonds"], args.cpu_budget)
     if args.surrogate:
         from paper_2506_05362_amd import surrogate
         r = surrogate.run(log=lambda s: print(s, file=sys.stderr, flush=True))

@@ -209,8 +209,10 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
 pd_status pd_build_bonds(pd_ctx* ctx, const pd_cut* cuts, int32_t n_cuts);
 
 /* Advance n_steps velocity-Verlet steps.  Enqueues on the context stream and
-   waits for the device status word at the end; PD_ERR_UNSTABLE reports a flag
-   raised during these steps (the state is the last completed step).  Chunks of
+   waits for the device status word at the end.  PD_ERR_UNSTABLE reports a flag
+   raised during these steps: the step that raised it completes, the steps
+   after it change nothing, and the context is left at that step (PD_STEP and
+   every field report it); the flag is cleared once reported.  Chunks of
    rebuild_every steps (doubled when odd) that start on a multiple of that
    length replay one captured HIP graph; the rest launch kernels directly. */
 pd_status pd_step(pd_ctx* ctx, int64_t n_steps);
@@ -231,16 +233,23 @@ pd_status pd_get_state(pd_ctx* ctx, void* blob, int64_t* bytes);
 /* Restore a checkpoint taken from a context built from the same inputs. */
 pd_status pd_set_state(pd_ctx* ctx, const void* blob, int64_t bytes);
 
-/* Measurement hook: with enable != 0, pd_step launches every step directly
-   (no graph replay) and brackets each launch of the fused step kernel with a
-   pair of HIP events on the context stream.  pd_timing waits for the stream,
-   returns the number of bracketed launches and their summed duration in
-   milliseconds, and clears the record. */
+/* Measurement hook: with enable != 0, pd_step brackets each launch of the
+   fused step kernel with a pair of HIP events on the context stream.  A
+   directly launched step records them around its launch; a replayed step loop
+   is a second captured graph with event-record nodes around each step kernel,
+   and pd_step waits after each replay to read them.  pd_timing waits for the
+   stream, returns the number of bracketed launches and their summed duration
+   in milliseconds, and clears the record. */
 pd_status pd_set_timing(pd_ctx* ctx, int32_t enable);
 pd_status pd_timing(pd_ctx* ctx, int64_t* launches, double* total_ms);
 
 /* Counts: n_nodes, nnz (real bonds), padded slots, candidates, steps. */
 pd_status pd_info(pd_ctx* ctx, int64_t* out5);
+
+/* How the steps of this context were launched so far: out5 = graph replays,
+   steps run inside them, steps launched directly, persistent launches, steps
+   run inside those. */
+pd_status pd_loop_counts(pd_ctx* ctx, int64_t* out5);
 
 /* How pd_step launches the step.  GRAPH, DIRECT and PERSISTENT, with any
    slices_per_block and xcd_remap, compute bitwise the same node state and wall
@@ -264,7 +273,7 @@ pd_status pd_info(pd_ctx* ctx, int64_t* out5);
    bond_path: how the bond sum (Sec. 3.1) reads its neighbours.
      PD_BONDS_SLICES  sliced-ELL rows of column words, neighbour u gathered from
                       HBM (default; every loop);
-     PD_BONDS_TILES   workgroups over 4 x 4 x 16-cell tiles of each grain's
+     PD_BONDS_TILES   workgroups over 8 x 4 x 16-cell tiles of each grain's
                       lattice with u of the tile and a 3-cell halo staged in LDS,
                       the bond memory in per-node class masks.  Needs the bonds
                       built, horizon factor 3 and every grain's nodes in

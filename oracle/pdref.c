@@ -113,6 +113,7 @@ struct pdref {
   int32_t* cand;
   double* u_at_build;
   int64_t step;
+  double* margin; /* [nnz] min over the bond's evaluations of its break margin */
   double min_margin;
   int built;
 };
@@ -396,7 +397,7 @@ void pdref_destroy(pdref* s) {
   free(s->ijk); free(s->fixed); free(s->grain_begin); free(s->gmat); free(s->gh);
   free(s->mat); free(s->grain_of); free(s->gc); free(s->gs0); free(s->gV); free(s->grho);
   free(s->gK); free(s->walls); free(s->cuts); free(s->row_ptr); free(s->col); free(s->broken);
-  free(s->n0); free(s->cand_ptr); free(s->cand);
+  free(s->n0); free(s->cand_ptr); free(s->cand); free(s->margin);
   free(s);
 }
 
@@ -529,6 +530,8 @@ static void build_bonds(pdref* s) {
   s->row_ptr[n] = nnz;
   s->col = col;
   s->broken = (uint8_t*)calloc((size_t)(nnz > 0 ? nnz : 1), 1);
+  s->margin = (double*)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  for (int64_t e = 0; e < nnz; ++e) s->margin[e] = INFINITY;
 }
 
 /* ------------------------------------------------------------------------- */
@@ -770,13 +773,18 @@ static int eval_force(pdref* s) {
       double l0 = sqrt((xi[0] * xi[0] + xi[1] * xi[1]) + xi[2] * xi[2]);
       double l = sqrt((y[0] * y[0] + y[1] * y[1]) + y[2] * y[2]);
       double st = stretch(xi, eta, l0, l);
-      int over = (s->flags & PDREF_ABS_STRETCH) ? (fabs(st) > s0) : (st > s0);
+      const int absr = (s->flags & PDREF_ABS_STRETCH) != 0;
+      /* how far this evaluation's break decision is from the threshold, relative
+         to s0: |s/s0 - 1| for the tension test, ||s|/s0 - 1| for the |s| test;
+         recorded at every evaluation, the one that breaks the bond included */
+      double r = fabs((absr ? fabs(st) : st) / s0 - 1.0);
+      if (r < s->margin[e]) s->margin[e] = r;
+      if (r < margin) margin = r;
+      int over = absr ? (fabs(st) > s0) : (st > s0);
       if (over) {
         s->broken[e] = 1;
         continue;
       }
-      double r = fabs(st / s0 - 1.0);
-      if (r < margin) margin = r;
       double coef = c * bond_weight(s, g, l0) * st * Vj / l;
       for (int q = 0; q < 3; ++q) Fi[q] += coef * y[q];
     }
@@ -1094,6 +1102,13 @@ void pdref_energy(const pdref* s, double* out4) {
 }
 
 double pdref_min_margin(const pdref* s) { return s->min_margin; }
+
+void pdref_bond_margin(const pdref* s, double* out) {
+  const int64_t nnz = pdref_nnz(s);
+  if (out && nnz > 0) memcpy(out, s->margin, sizeof(double) * (size_t)nnz);
+}
+
+int32_t pdref_skin_exceeded(const pdref* s) { return skin_exceeded(s); }
 
 void pdref_set_u(pdref* s, const double* u) {
   memcpy(s->u, u, sizeof(double) * (size_t)(3 * s->n));

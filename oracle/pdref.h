@@ -89,8 +89,17 @@ int64_t pdref_n_candidates(const pdref* s);
 void pdref_get_candidates(const pdref* s, int64_t* row_ptr, int32_t* col);
 /* energies: kinetic, elastic (bonds), contact, gravity potential */
 void pdref_energy(const pdref* s, double* out4);
-/* min over evaluated intact bonds and steps of |s/s0 - 1| (break-decision margin) */
+/* Break-decision margin of a bond: the minimum, over every evaluation of the
+   bond (the one that breaks it included), of |s/s0 - 1| (with
+   PDREF_ABS_STRETCH: ||s|/s0 - 1|).  A bond whose margin exceeds a tolerance
+   took every break decision with that much room on either side.
+   pdref_bond_margin fills [nnz] (aligned with the bond columns, +inf for a
+   bond never evaluated); pdref_min_margin is the minimum over all bonds. */
 double pdref_min_margin(const pdref* s);
+void pdref_bond_margin(const pdref* s, double* out);
+/* 1 when some node moved more than skin/2 since the last candidate rebuild
+   (the guard pdref_step applies at each rebuild when contacts can exist) */
+int32_t pdref_skin_exceeded(const pdref* s);
 /* overwrite u (tests compare lists on identical positions) and rebuild candidates */
 void pdref_set_u(pdref* s, const double* u);
 /* recompute the candidate list from the current u */

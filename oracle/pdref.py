@@ -69,6 +69,9 @@ def lib():
         L.pdref_energy.argtypes = [P, P]
         L.pdref_min_margin.argtypes = [P]
         L.pdref_min_margin.restype = C.c_double
+        L.pdref_bond_margin.argtypes = [P, P]
+        L.pdref_skin_exceeded.argtypes = [P]
+        L.pdref_skin_exceeded.restype = C.c_int32
         L.pdref_set_u.argtypes = [P, P]
         L.pdref_rebuild_candidates.argtypes = [P]
         L.pdref_energy_density.argtypes = [P, P]
@@ -240,6 +243,16 @@ class Oracle:
 
     def min_margin(self) -> float:
         return float(lib().pdref_min_margin(self.h))
+
+    def bond_margin(self) -> np.ndarray:
+        """Per directed bond (aligned with bonds()), the smallest |s/s0 - 1| any of
+        its break decisions saw (inf for a bond never evaluated)."""
+        m = np.zeros(max(self.nnz, 1))
+        lib().pdref_bond_margin(self.h, _p(m))
+        return m[: self.nnz]
+
+    def skin_exceeded(self) -> bool:
+        return bool(lib().pdref_skin_exceeded(self.h))
 
     def set_u(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64)

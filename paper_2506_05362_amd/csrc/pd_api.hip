@@ -62,6 +62,7 @@ struct pd_ctx {
   int32_t n_box_chunks = 0;
   int64_t* step_d = nullptr;
   uint32_t* status = nullptr;
+  uint32_t* halt = nullptr;  // status when the current step began: later steps do nothing once set
   // bonds
   int64_t nslices = 0, padded = 0, nnz = 0;
   int32_t* rowlen = nullptr;
@@ -112,11 +113,20 @@ struct pd_ctx {
   uint32_t* mask = nullptr;  // [kMaskWords][N]
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
-  // captured step loop of graph_len steps
+  // captured step loop of graph_len steps; with timing on, a second capture
+  // whose step kernels are bracketed by event-record nodes (tev, one pair per step)
   int use_graph = 1;
   int64_t graph_len = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  hipGraph_t graph_t = nullptr;
+  hipGraphExec_t graph_exec_t = nullptr;
+  std::vector<hipEvent_t> tev;
+  double timed_ms = 0.0;  // step-kernel time of replayed timed graphs since the last pd_timing
+  int64_t timed_n = 0;
+  // how the steps of this context were launched: graph replays, steps in them,
+  // directly launched steps, persistent launches and the steps in them
+  int64_t counts[5] = {0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -302,6 +312,7 @@ StepArgs step_args(pd_ctx* c) {
   A.step = c->step_d;
   A.advance = 1;
   A.status = c->status;
+  A.halt = c->halt;
   A.n = c->n;
   A.nslices = c->nslices;
   A.n_walls = c->n_walls;
@@ -344,6 +355,7 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.n_box_chunks = c->n_box_chunks;
   C.n_grains = c->n_grains;
   C.status = c->status;
+  C.halt = c->halt;
   C.n = c->n;
   C.T = c->T;
   C.capacity = c->capacity;
@@ -355,9 +367,15 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   return C;
 }
 
+// the closing event of captured step p (1-based) of the timed graph
+hipEvent_t ev1_node(pd_ctx* c, int64_t p) {
+  const size_t k = (size_t)(2 * (p - 1) + 1);
+  return k < c->tev.size() ? c->tev[k] : nullptr;
+}
+
 // one step on the device: rebuild on cadence, force+Verlet, walls.
 // ev0/ev1 (optional) bracket the step kernel.
-pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) {
+pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1, bool record_nodes = false) {
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
     ContactArgs C = contact_args(c, nxt);
@@ -366,7 +384,10 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
   HIPCHK(c, launch_wall_corners(A, 0, c->stream));
-  // a single step launch records ev0/ev1 itself, tightly around the kernel
+  // a single step launch records ev0/ev1 itself, tightly around the kernel;
+  // under stream capture the events become record nodes around the kernel node
+  if (record_nodes && ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
+  if (record_nodes) ev0 = ev1 = nullptr;
   if (c->launch.bond_path == PD_BONDS_TILES) {
     A.partial_stride = kTS * c->n_tiles;  // one wall-partial column per tile wavefront
     HIPCHK(c, launch_step_tile(A, c->stream, ev0, ev1));
@@ -389,6 +410,7 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
   } else {
     HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream, ev0, ev1));
   }
+  if (record_nodes && ev1_node(c, s)) HIPCHK(c, hipEventRecord(ev1_node(c, s), c->stream));
   HIPCHK(c, launch_wall_finalize(A, c->stream));
   return PD_OK;
 }
@@ -420,14 +442,25 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
   return PD_OK;
 }
 
-// capture graph_len steps starting at a multiple of graph_len (buffer parity 0)
-pd_status capture_graph(pd_ctx* c) {
-  if (c->graph_exec) return PD_OK;
+// capture graph_len steps starting at a multiple of graph_len (buffer parity 0);
+// timed: every step kernel between a pair of event-record nodes
+pd_status capture_graph(pd_ctx* c, bool timed) {
+  hipGraphExec_t& exec = timed ? c->graph_exec_t : c->graph_exec;
+  hipGraph_t& graph = timed ? c->graph_t : c->graph;
+  if (exec) return PD_OK;
+  if (timed) {
+    while ((int64_t)c->tev.size() < 2 * c->graph_len) {
+      hipEvent_t e;
+      HIPCHK(c, hipEventCreate(&e));
+      c->tev.push_back(e);
+    }
+  }
   const int cur0 = c->cur;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   pd_status st = PD_OK;
-  for (int64_t p = 1; p <= c->graph_len && st == PD_OK; ++p)
-    st = enqueue_step_ev(c, p, nullptr, nullptr);  // p stands for any step congruent to it
+  for (int64_t p = 1; p <= c->graph_len && st == PD_OK; ++p)  // p stands for any step congruent to it
+    st = timed ? enqueue_step_ev(c, p, c->tev[(size_t)(2 * (p - 1))], nullptr, true)
+               : enqueue_step_ev(c, p, nullptr, nullptr);
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(c->stream, &g);
   c->cur = cur0;
@@ -436,8 +469,19 @@ pd_status capture_graph(pd_ctx* c) {
     return st;
   }
   if (ec != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorName(ec));
-  c->graph = g;
-  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
+  graph = g;
+  HIPCHK(c, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+  return PD_OK;
+}
+
+pd_status drop_graphs(pd_ctx* c) {
+  if (c->graph_exec || c->graph_exec_t) HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+  if (c->graph_exec_t) HIPCHK(c, hipGraphExecDestroy(c->graph_exec_t));
+  if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
+  if (c->graph_t) HIPCHK(c, hipGraphDestroy(c->graph_t));
+  c->graph_exec = c->graph_exec_t = nullptr;
+  c->graph = c->graph_t = nullptr;
   return PD_OK;
 }
 
@@ -476,12 +520,20 @@ pd_status read_status(pd_ctx* c, uint32_t* st) {
   return PD_OK;
 }
 
+// A flag raised by a step lets that step complete and halts the steps after
+// it (their kernels change nothing): the context's step count and state are
+// those of the step that raised it.  The flags are cleared once reported.
 pd_status report_status(pd_ctx* c) {
   uint32_t st = 0;
   TRY(read_status(c, &st));
   if (!st) return PD_OK;
+  int64_t done = 0;
+  HIPCHK(c, hipMemcpyAsync(&done, c->step_d, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->halt, 0, sizeof(uint32_t), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = done;
+  c->cur = (int)(done & 1);  // u4[step % 2] holds u_step
   std::string why;
   if (st & ST_NAN) why += " non-finite force;";
   if (st & ST_PENETRATION) why += " node at or beyond -R_c behind a wall;";
@@ -519,7 +571,7 @@ constexpr int kAxisOrders[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {
 
 // Tiles of the bond loop: for every grain an axis order in which its node
 // indices ascend lexicographically (the order of the slice path's sorted rows),
-// its box on those axes, a cell -> node map, the 4 x 4 x 16-cell tiles that hold
+// its box on those axes, a cell -> node map, the 8 x 4 x 16-cell tiles that hold
 // nodes, the bond table of each (stencil class, axis order) in tile class order
 // and the class masks of the built bonds.  Leaves tile_ok = 0 when some grain
 // has no such order or the horizon factor is not 3.
@@ -870,6 +922,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   }
   TRY(alloc_n(c, &c->step_d, 1, "step"));
   TRY(alloc_n(c, &c->status, 1, "status"));
+  TRY(alloc_n(c, &c->halt, 1, "halt"));
   TRY(alloc_n(c, &c->fin_counter, 1, "finalize counter"));
   if (mesh->fixed) TRY(alloc_n(c, &c->fixed, N, "fixed"));
   hipStream_t s = c->stream;
@@ -882,6 +935,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (mesh->fixed) HIPCHK(c, hipMemcpyAsync(c->fixed, mesh->fixed, (size_t)N, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemsetAsync(c->step_d, 0, sizeof(int64_t), s));
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), s));
+  HIPCHK(c, hipMemsetAsync(c->halt, 0, sizeof(uint32_t), s));
   HIPCHK(c, hipMemsetAsync(c->fin_counter, 0, sizeof(uint32_t), s));
   if (mesh->v0)
     HIPCHK(c, hipMemcpyAsync(c->v, mesh->v0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
@@ -1152,20 +1206,36 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
     TRY(enqueue_persistent(c, left, &k, e0, e1));
     c->step += k;
     left -= k;
+    c->counts[3] += 1;
+    c->counts[4] += k;
   }
   while (left > 0) {
-    // timing brackets each step kernel with events, so it launches directly
-    const bool aligned = c->use_graph && c->launch.loop == PD_LOOP_GRAPH && !c->timing &&
-                         c->step % c->graph_len == 0 && left >= c->graph_len;
+    const bool aligned = c->use_graph && c->launch.loop == PD_LOOP_GRAPH && c->step % c->graph_len == 0 &&
+                         left >= c->graph_len;
     if (aligned) {
-      TRY(capture_graph(c));
-      HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
+      // with timing on, the replayed graph carries event-record nodes around each
+      // step kernel; their times are collected after the replay (the next replay
+      // records the same events again)
+      TRY(capture_graph(c, c->timing != 0));
+      HIPCHK(c, hipGraphLaunch(c->timing ? c->graph_exec_t : c->graph_exec, c->stream));
+      if (c->timing) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        for (int64_t p = 0; p < c->graph_len; ++p) {
+          float ms = 0.0f;
+          HIPCHK(c, hipEventElapsedTime(&ms, c->tev[(size_t)(2 * p)], c->tev[(size_t)(2 * p + 1)]));
+          c->timed_ms += ms;
+          c->timed_n += 1;
+        }
+      }
       c->step += c->graph_len;
       left -= c->graph_len;
+      c->counts[0] += 1;
+      c->counts[1] += c->graph_len;
     } else {
       TRY(enqueue_step(c, c->step + 1));
       c->step += 1;
       left -= 1;
+      c->counts[2] += 1;
     }
   }
   return report_status(c);
@@ -1192,15 +1262,7 @@ pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
     if (l->loop != PD_LOOP_GRAPH && l->loop != PD_LOOP_DIRECT)
       return fail(c, PD_ERR_INVALID, "the tiled bond loop runs with the graph or direct step loop only");
   }
-  if (c->graph_exec) {
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
-    c->graph_exec = nullptr;
-  }
-  if (c->graph) {
-    HIPCHK(c, hipGraphDestroy(c->graph));
-    c->graph = nullptr;
-  }
+  TRY(drop_graphs(c));
   if (c->built && l->bond_path != c->launch.bond_path) {
     // hand the bond memory over: column words <-> class masks
     StepArgs A = step_args(c);
@@ -1222,14 +1284,18 @@ pd_status pd_set_timing(pd_ctx* c, int32_t enable) {
   if (!c) return PD_ERR_INVALID;
   c->timing = enable != 0;
   c->ev_used = 0;
+  c->timed_ms = 0.0;
+  c->timed_n = 0;
   return PD_OK;
 }
 
 pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
   if (!c || !launches || !total_ms) return PD_ERR_INVALID;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double tot = 0.0;
-  int64_t n = 0;
+  double tot = c->timed_ms;
+  int64_t n = c->timed_n;
+  c->timed_ms = 0.0;
+  c->timed_n = 0;
   for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
     float ms = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
@@ -1239,6 +1305,12 @@ pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
   *launches = n;
   *total_ms = tot;
   c->ev_used = 0;
+  return PD_OK;
+}
+
+pd_status pd_loop_counts(pd_ctx* c, int64_t* out5) {
+  if (!c || !out5) return PD_ERR_INVALID;
+  for (int k = 0; k < 5; ++k) out5[k] = c->counts[k];
   return PD_OK;
 }
 
@@ -1557,8 +1629,11 @@ void pd_destroy(pd_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
+  if (c->graph_exec_t) (void)hipGraphExecDestroy(c->graph_exec_t);
   if (c->graph) (void)hipGraphDestroy(c->graph);
+  if (c->graph_t) (void)hipGraphDestroy(c->graph_t);
   std::vector<void*> all = c->owned;
   for (void* p : all) dev_free(c, p);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);

@@ -142,6 +142,10 @@ struct StepArgs {
   int64_t* step;         // device step counter
   int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;
+  // status as it stood when the current step began (written by the last kernel
+  // of each step): once nonzero, the kernels of later steps change nothing, so
+  // the state stays at the step that raised the flag
+  uint32_t* halt;
   int64_t n;
   int64_t nslices;
   int32_t n_walls;
@@ -234,6 +238,7 @@ struct ContactArgs {
   int32_t n_box_chunks;
   int32_t n_grains;
   uint32_t* status;
+  const uint32_t* halt;   // nonzero: an earlier step raised a flag; leave the positions at rebuild alone
   int64_t n;
   uint32_t T;             // power of two
   int64_t capacity;

@@ -36,6 +36,11 @@ __device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
   return x * q + (x < r ? x : r) + (b >> 3);
 }
 
+// the halt word, read the same by every lane of the launch
+__device__ __forceinline__ bool halted(const uint32_t* halt) {
+  return __builtin_amdgcn_readfirstlane(__hip_atomic_load(halt, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) != 0u;
+}
+
 __device__ __forceinline__ int unpack_x(int p) { return p & 1023; }
 __device__ __forceinline__ int unpack_y(int p) { return (p >> 10) & 1023; }
 __device__ __forceinline__ int unpack_z(int p) { return (p >> 20) & 1023; }
@@ -433,7 +438,7 @@ __device__ void wall_corner_terms(const StepArgs& A, double Kn, const double* hd
 // the last evaluation.
 __global__ void k_wall_corners(StepArgs A, int force_only) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
+  if (i >= A.n || (!force_only && halted(A.halt))) return;
   const double4 ui = A.ucur[i];
   const GrainC* G = A.grains + packed_grain(ui.w);
   const int p = packed_ijk(ui.w);
@@ -816,6 +821,7 @@ template <int MODE, bool ABS, int SPB>
 __global__ __launch_bounds__(SPB * kWave) __attribute__((amdgpu_waves_per_eu(PD_STEP_WAVES_PER_EU)))
 void k_step(StepArgs A) {
   extern __shared__ StencilC s_st[];
+  if (MODE == MODE_STEP && halted(A.halt)) return;
   stage_stencil(A, s_st);
   const int64_t blk = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
   step_body<MODE, ABS, SPB>(A, s_st, blk);
@@ -948,6 +954,7 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   __shared__ double s_u[3 * kHalo];
   constexpr int kNT = kTS * kWave;
   constexpr int kFill = (kHalo + kNT - 1) / kNT;  // halo cells per thread
+  if (halted(A.halt)) return;
   const int tid = threadIdx.x, lane = tid & 63;
   const int wid = __builtin_amdgcn_readfirstlane(tid >> 6);
   const int64_t t = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
@@ -1158,6 +1165,8 @@ __device__ __forceinline__ void finalize_level2(const StepArgs& A, double (*red)
       tot[tid] = t;
     }
   }
+  // a halted step changes neither the walls nor the step count
+  if (A.advance && halted(A.halt)) return;
   if (tid == 0) *s_step = *A.step + A.advance;  // the step this evaluation belonged to
   __syncthreads();
   const int64_t s = *s_step;
@@ -1208,7 +1217,12 @@ __global__ __launch_bounds__(kWave) void k_wall_finalize(StepArgs A, uint32_t* c
   if (!last) return;
   __threadfence();
   finalize_level2<kWave>(A, red, tot, &s_step);
-  if (threadIdx.x == 0) atomicExch(counter, 0u);
+  if (threadIdx.x == 0) {
+    // the last kernel of the step: the next step halts if this one raised a flag
+    __hip_atomic_store(A.halt, __hip_atomic_load(A.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                       __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    atomicExch(counter, 0u);
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -1250,6 +1264,7 @@ void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
+  if (halted(A.halt)) return;
   stage_stencil(A, s_st);
   for (int64_t k = 0; k < nsteps; ++k) {
     for (int64_t vb = blockIdx.x; vb < nvblocks; vb += gridDim.x) {
@@ -1267,8 +1282,13 @@ void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs
       __threadfence_block();
       __syncthreads();
       finalize_level2<4 * kWave>(A, red, tot, &s_step);
+      if (threadIdx.x == 0)
+        __hip_atomic_store(A.halt, __hip_atomic_load(A.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
     grid_barrier(B, gridDim.x, A.status);
+    // every workgroup reads the halt word workgroup 0 wrote before this barrier
+    if (halted(A.halt)) break;
     // the drift just written is the next step's position; mid-step velocities likewise
     const double4* uc = A.ucur;
     A.ucur = A.unext;
@@ -1585,7 +1605,7 @@ __global__ void k_cand_capacity(ContactArgs c) {
 // displacement since the last rebuild beyond skin/2 invalidates the list
 __global__ void k_skin(ContactArgs c, int check) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= c.n) return;
+  if (i >= c.n || halted(c.halt)) return;
   const double4 u = c.u[i];
   if (check) {
     const double dx = u.x - c.u_build[i], dy = u.y - c.u_build[c.n + i], dz = u.z - c.u_build[2 * c.n + i];

@@ -109,6 +109,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_get_state.argtypes = [P, P, C.POINTER(C.c_int64)]
     L.pd_set_state.argtypes = [P, P, C.c_int64]
     L.pd_info.argtypes = [P, P]
+    L.pd_loop_counts.argtypes = [P, P]
     L.pd_set_timing.argtypes = [P, C.c_int32]
     L.pd_timing.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
     L.pd_set_launch.argtypes = [P, C.POINTER(pd_launch)]
@@ -119,7 +120,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_status_string.argtypes = [C.c_int32]
     L.pd_status_string.restype = C.c_char_p
     for name in ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get",
-                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_set_timing",
+                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_loop_counts", "pd_set_timing",
                  "pd_timing", "pd_set_launch", "pd_get_launch"]:
         getattr(L, name).restype = C.c_int32
     return L
@@ -306,6 +307,12 @@ class Sim:
         self._check(lib().pd_info(self.h, _ptr(o)))
         return dict(n_nodes=int(o[0]), nnz=int(o[1]), padded=int(o[2]), candidates=int(o[3]),
                     step=int(o[4]))
+
+    def loop_counts(self) -> dict:
+        o = np.zeros(5, dtype=np.int64)
+        self._check(lib().pd_loop_counts(self.h, _ptr(o)))
+        return dict(graph_replays=int(o[0]), graph_steps=int(o[1]), direct_steps=int(o[2]),
+                    persistent_launches=int(o[3]), persistent_steps=int(o[4]))
 
     def set_launch(self, loop: int = LOOP_GRAPH, slices_per_block: int = 4, xcd_remap: int = 1,
                    persistent_blocks: int = 0, bond_path: int = BONDS_SLICES):

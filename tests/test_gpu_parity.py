@@ -45,13 +45,41 @@ def assert_state_close(sim, ora, rel=REL, what="", a_scale=None):
     assert r <= rel, f"{what} force: rel err {r:.3e}"
 
 
+MARGIN = 1e-9
+
+
+def assert_broken_sets(sim, ora, tol=MARGIN, what=""):
+    """Broken-bond sets bit-exact on every bond whose break decisions all had a
+    margin |s/s0 - 1| above tol in the oracle; the few closer to the threshold
+    (where the two sides' last-ulp differences may decide) are left out and
+    counted.  Damage and intact counts are compared on the nodes none of whose
+    bonds was left out.  Returns the number of bonds left out."""
+    rp, col, br = sim.bonds()
+    rpo, colo, bro = ora.bonds()
+    assert np.array_equal(rp, rpo) and np.array_equal(col, colo)
+    m = ora.bond_margin()
+    keep = m > tol
+    excluded = int((~keep).sum())
+    bad = np.flatnonzero(keep & (br != bro))
+    assert bad.size == 0, f"{what}: {bad.size} broken bits differ (first bond {bad[:5]}), {excluded} excluded"
+    rows = np.repeat(np.arange(len(rp) - 1), np.diff(rp))
+    clean = np.ones(len(rp) - 1, dtype=bool)
+    clean[rows[~keep]] = False
+    d, it, _ = ora.damage()
+    assert np.array_equal(sim.get("intact_count")[clean], it[clean]), what
+    assert np.array_equal(sim.get("damage")[clean], d[clean]), what
+    print(f"[broken sets] {what}: {int(bro.sum())} broken, {excluded} of {len(m)} bonds within "
+          f"{tol:g} of the threshold left out", flush=True)
+    return excluded
+
+
 def assert_bonds_equal(sim, ora, broken=True):
     rp, col, br = sim.bonds()
     rpo, colo, bro = ora.bonds()
     assert np.array_equal(rp, rpo)
     assert np.array_equal(col, colo)
     if broken:
-        assert np.array_equal(br, bro)
+        assert_broken_sets(sim, ora)
 
 
 def small_cases():
@@ -125,14 +153,11 @@ def test_two_spheres_trajectory(oracle_lib, speed, steps):
         sim.step(100)
         ora.step(100)
     assert_state_close(sim, ora, what=f"speed {speed}")
-    margin = ora.min_margin()
-    rp, col, br = sim.bonds()
-    _, _, bro = ora.bonds()
-    if margin > 1e-9:
-        assert np.array_equal(br, bro), f"margin {margin:.2e}"
+    excluded = assert_broken_sets(sim, ora, what=f"speed {speed}")
+    bro = ora.bonds()[2]
     if speed > 10:
         assert bro.sum() > 0
-    assert np.array_equal(sim.get("damage"), ora.damage()[0]) or margin <= 1e-9
+        assert excluded < 1e-3 * bro.sum()
 
 
 def test_notched_plate_with_moving_wall(oracle_lib):
@@ -393,8 +418,8 @@ def test_conic_micromodulus_matches_oracle(oracle_lib):
         sim.set_launch(bond_path=bp)
         sim.step(80)
         assert_state_close(sim, ora, what=f"conic, bond path {bp}")
-        # broken sets bit-exact where no stretch came within 1e-9 of s0
-        assert_bonds_equal(sim, ora, broken=ora.min_margin() > 1e-9)
+        # broken sets bit-exact on every bond whose stretch stayed 1e-9 away from s0
+        assert_bonds_equal(sim, ora)
         assert sim.bonds()[2].any()
         eg = sim.get("energy")
         assert eg[1] == pytest.approx(eo["elastic"], rel=1e-9)
@@ -478,7 +503,7 @@ def test_self_contact_matches_oracle(oracle_lib, bond_path):
     sim.set_launch(bond_path=bond_path)
     sim.step(30)
     assert_state_close(sim, ora, what=f"self-contact, bond path {bond_path}")
-    assert np.array_equal(sim.bonds()[2], ora.bonds()[2])
+    assert_broken_sets(sim, ora, what=f"self-contact, bond path {bond_path}")
     sim.close()
     off = oracle_lib.Oracle(_notched_ball(self_contact=False), flags=flags)
     off.step(30)
@@ -608,40 +633,48 @@ def test_large_aggregate_with_corners_and_self_contact_matches_oracle(oracle_lib
         sim.close()
 
 
+@pytest.mark.timeout(900)
 def test_notched_plate_full_size_in_the_bench_configuration(oracle_lib):
-    """The benchmark workload at full size (720,000 nodes, 80,821,072 bonds) in
-    the configuration the benchmark times (tiled bond path, graph-replayed
-    steps): after 150 steps of the impact every node's u, v, a and F within
-    1e-9 of the oracle and the projectile wall's reaction within 1e-6."""
+    """The double-notched plate at full size (720,000 nodes, 80,821,072 bonds) in
+    the tiled, graph-replayed configuration, through 1000 steps of the impact:
+    the cracks start at the notch tips after about 700 steps, so the broken-bond
+    sets, intact counts and damage are compared with tens of thousands of bonds
+    broken; every node's u, v, a and F within 1e-9 of the oracle and the
+    projectile wall's reaction within 1e-6."""
     from paper_2506_05362_amd import pd
     wl = I.notched_plate()
     sim = gpu_sim(wl)
     sim.set_launch(loop=pd.LOOP_GRAPH, bond_path=pd.BONDS_TILES)
-    sim.step(150)
+    sim.step(1000)
     print("gpu done", flush=True)
     ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
-    assert ora.step(150) == 0
-    print("oracle done", flush=True)
-    assert ora.min_margin() > 1e-9  # no stretch near s0: bond decisions are unambiguous
+    for k in range(10):
+        assert ora.step(100) == 0
+        print(f"oracle step {ora.step_count}", flush=True)
+    assert ora.bonds()[2].sum() > 10000  # crack growth inside the window
     assert_state_close(sim, ora, what="full-size plate")
     fo, _ = ora.walls()
     assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
-    assert np.array_equal(sim.bonds()[2], ora.bonds()[2])
+    excluded = assert_broken_sets(sim, ora, what="full-size plate")
+    assert excluded < 100
     sim.close()
 
 
+@pytest.mark.timeout(900)
 def test_uneven_aggregate_full_size_matches_oracle(oracle_lib):
     """The uneven-grain aggregate at full size (100 grains of 2e3-5e4 nodes,
-    1.72 M nodes) in the batched graph-replayed launch: after 40 steps state
+    1.72 M nodes) in the batched graph-replayed launch: after 100 steps state
     within 1e-9 of the oracle and platen forces within 1e-6."""
     from paper_2506_05362_amd import pd
     wl = I.grain_aggregate(seed=0, rebuild_every=20)
     sim = gpu_sim(wl)
     sim.set_launch(loop=pd.LOOP_GRAPH)
-    sim.step(40)
+    sim.step(100)
     print("gpu done", flush=True)
     ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
-    assert ora.step(40) == 0
+    for k in range(5):
+        assert ora.step(20) == 0
+        print(f"oracle step {ora.step_count}", flush=True)
     print("oracle done", flush=True)
     assert_state_close(sim, ora, what="full-size aggregate", a_scale=None)
     fo, _ = ora.walls()
