@@ -246,6 +246,11 @@ pd_status pd_timing(pd_ctx* ctx, int64_t* launches, double* total_ms);
 /* Counts: n_nodes, nnz (real bonds), padded slots, candidates, steps. */
 pd_status pd_info(pd_ctx* ctx, int64_t* out5);
 
+/* The tiled bond loop's layout: the number of tiles (0 when the tiled loop is
+   unavailable) and whether they cover one box over all grains (lattice mode:
+   every grain on one lattice with one spacing, bond table and node order). */
+pd_status pd_tile_info(pd_ctx* ctx, int64_t* n_tiles, int32_t* lattice);
+
 /* How the steps of this context were launched so far: out5 = graph replays,
    steps run inside them, steps launched directly, persistent launches, steps
    run inside those. */
@@ -274,8 +279,9 @@ pd_status pd_loop_counts(pd_ctx* ctx, int64_t* out5);
      PD_BONDS_SLICES  sliced-ELL rows of column words, neighbour u gathered from
                       HBM (default; every loop);
      PD_BONDS_TILES   workgroups over 8 x 4 x 16-cell tiles of each grain's
-                      lattice with u of the tile and a 3-cell halo staged in LDS,
-                      the bond memory in per-node class masks.  Needs the bonds
+                      lattice (or of one box over all grains when they share a
+                      lattice, see pd_tile_info) with u of the tile and a 3-cell
+                      halo staged in LDS, the bond memory in per-node class masks.  Needs the bonds
                       built, horizon factor 3 and every grain's nodes in
                       lexicographic lattice order along some axis order
                       (PD_ERR_UNSUPPORTED otherwise), and the GRAPH or DIRECT

@@ -7,6 +7,7 @@
 #include <string.h>
 
 #include <algorithm>
+#include <array>
 #include <new>
 #include <string>
 #include <vector>
@@ -101,6 +102,7 @@ struct pd_ctx {
   // tiled bond loop (PD_BONDS_TILES): available when the horizon factor is 3
   // and every grain's nodes are in lexicographic order of some axis order
   int tile_ok = 0;
+  int tile_lattice = 0;  // the tiles cover one box over every grain
   int64_t n_tiles = 0;
   int4* tiles = nullptr;
   TileGrain* tgrain = nullptr;
@@ -573,10 +575,15 @@ constexpr int kAxisOrders[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {
 // indices ascend lexicographically (the order of the slice path's sorted rows),
 // its box on those axes, a cell -> node map, the 8 x 4 x 16-cell tiles that hold
 // nodes, the bond table of each (stencil class, axis order) in tile class order
-// and the class masks of the built bonds.  Leaves tile_ok = 0 when some grain
-// has no such order or the horizon factor is not 3.
+// and the class masks of the built bonds.  When every grain shares one
+// lattice (equal spacing, origins a whole number of spacings apart), one bond
+// table and one axis order, the tiles cover one box over all grains instead
+// (lattice mode): a dense aggregate then fills its tiles, and bonds, which
+// never join two grains, are told apart by the class masks.  Leaves tile_ok = 0
+// when some grain has no such order or the horizon factor is not 3.
 pd_status build_tiles(pd_ctx* c) {
   c->tile_ok = 0;
+  c->tile_lattice = 0;
   if (c->m != kTileR || c->n_stencil != kTileClasses) return PD_OK;
   const int64_t N = c->n;
   const int32_t G = c->n_grains;
@@ -585,6 +592,13 @@ pd_status build_tiles(pd_ctx* c) {
   int64_t map_total = 0;
   std::vector<int> table_of((size_t)6 * c->n_classes, -1);
   int n_tables = 0;
+  auto table_for = [&](int perm, int cls) {
+    int& tab = table_of[(size_t)perm * c->n_classes + cls];
+    if (tab < 0) tab = n_tables++;
+    return tab;
+  };
+  // each grain's axis order and lattice box
+  std::vector<std::array<int, 3>> glo((size_t)G), ghi((size_t)G);
   for (int32_t g = 0; g < G; ++g) {
     const int64_t b = c->grain_begin[(size_t)g], e = c->grain_begin[(size_t)g + 1];
     int perm = -1;
@@ -601,40 +615,126 @@ pd_status build_tiles(pd_ctx* c) {
       if (ok) perm = p;
     }
     if (perm < 0) return PD_OK;  // this grain's node order is not a lattice order
-    const int* P = kAxisOrders[perm];
     int lo[3] = {1 << 30, 1 << 30, 1 << 30}, hi[3] = {0, 0, 0};
     for (int64_t i = b; i < e; ++i)
       for (int q = 0; q < 3; ++q) {
-        lo[q] = std::min(lo[q], c->ijk_h[P[q] * N + i]);
-        hi[q] = std::max(hi[q], c->ijk_h[P[q] * N + i]);
+        lo[q] = std::min(lo[q], c->ijk_h[q * N + i]);
+        hi[q] = std::max(hi[q], c->ijk_h[q * N + i]);
       }
     if (e == b) lo[0] = lo[1] = lo[2] = hi[0] = hi[1] = hi[2] = 0;
-    TileGrain& T = tg[(size_t)g];
-    T.perm = perm;
-    T.lo_s = lo[0];
-    T.lo_m = lo[1];
-    T.lo_f = lo[2];
-    T.es = hi[0] - lo[0] + 1;
-    T.em = hi[1] - lo[1] + 1;
-    T.ef = hi[2] - lo[2] + 1;
+    for (int q = 0; q < 3; ++q) {
+      glo[(size_t)g][(size_t)q] = lo[q];
+      ghi[(size_t)g][(size_t)q] = hi[q];
+    }
+    tg[(size_t)g].perm = perm;
+    tg[(size_t)g].box = g;
+  }
+  // lattice mode: one spacing, one bond table, one axis order, origins on one lattice
+  bool lattice = G > 1;
+  std::vector<std::array<int64_t, 3>> koff((size_t)G);
+  for (int32_t g = 0; g < G && lattice; ++g) {
+    const GrainC& a = c->grains_h[0];
+    const GrainC& b = c->grains_h[(size_t)g];
+    if (b.h != a.h || b.cls != a.cls || tg[(size_t)g].perm != tg[0].perm) lattice = false;
+    for (int q = 0; q < 3 && lattice; ++q) {
+      const double k = (b.origin[q] - a.origin[q]) / a.h;
+      const double kr = nearbyint(k);
+      if (!(fabs(k - kr) <= 1e-6) || fabs(kr) > (1 << 20)) lattice = false;
+      koff[(size_t)g][(size_t)q] = (int64_t)kr;
+    }
+  }
+  // the boxes to tile: each grain's, or the shared one
+  struct Box {
+    int perm, lo[3], hi[3];  // lo/hi on the x, y, z axes of the box's lattice
+    int cls;
+    std::vector<int32_t> grains;
+  };
+  std::vector<Box> boxes;
+  if (lattice) {
+    int64_t kmin[3] = {0, 0, 0};
+    for (int32_t g = 0; g < G; ++g)
+      for (int q = 0; q < 3; ++q) kmin[q] = std::min(kmin[q], koff[(size_t)g][(size_t)q]);
+    Box B;
+    B.perm = tg[0].perm;
+    B.cls = c->grains_h[0].cls;
+    for (int q = 0; q < 3; ++q) {
+      B.lo[q] = 1 << 30;
+      B.hi[q] = -(1 << 30);
+    }
+    for (int32_t g = 0; g < G; ++g) {
+      for (int q = 0; q < 3; ++q) {
+        const int64_t o = koff[(size_t)g][(size_t)q] - kmin[q];
+        tg[(size_t)g].goff[q] = (int32_t)o;
+        if (c->grain_begin[(size_t)g + 1] > c->grain_begin[(size_t)g]) {
+          B.lo[q] = std::min<int64_t>(B.lo[q], glo[(size_t)g][(size_t)q] + o);
+          B.hi[q] = std::max<int64_t>(B.hi[q], ghi[(size_t)g][(size_t)q] + o);
+        }
+      }
+      tg[(size_t)g].box = G;
+      B.grains.push_back(g);
+    }
+    if (B.lo[0] > B.hi[0]) B.lo[0] = B.lo[1] = B.lo[2] = B.hi[0] = B.hi[1] = B.hi[2] = 0;
+    if ((int64_t)(B.hi[0] - B.lo[0] + 1) * (B.hi[1] - B.lo[1] + 1) * (B.hi[2] - B.lo[2] + 1) > ((int64_t)1 << 31))
+      lattice = false;
+    else
+      boxes.push_back(B);
+  }
+  if (!lattice) {
+    boxes.clear();
+    for (int32_t g = 0; g < G; ++g) {
+      Box B;
+      B.perm = tg[(size_t)g].perm;
+      B.cls = c->grains_h[(size_t)g].cls;
+      for (int q = 0; q < 3; ++q) {
+        B.lo[q] = glo[(size_t)g][(size_t)q];
+        B.hi[q] = ghi[(size_t)g][(size_t)q];
+        tg[(size_t)g].goff[q] = 0;
+      }
+      tg[(size_t)g].box = g;
+      B.grains.push_back(g);
+      boxes.push_back(B);
+    }
+  }
+  // box records (appended after the grains in lattice mode), their maps and tiles
+  std::vector<TileGrain> rec = tg;
+  for (size_t bi = 0; bi < boxes.size(); ++bi) {
+    const Box& B = boxes[bi];
+    const int* P = kAxisOrders[B.perm];
+    const int32_t r = lattice ? G : B.grains[0];
+    if (lattice) rec.push_back(TileGrain{});
+    TileGrain& T = rec[(size_t)r];
+    T.perm = B.perm;
+    T.box = r;
+    T.lo_s = B.lo[P[0]];
+    T.lo_m = B.lo[P[1]];
+    T.lo_f = B.lo[P[2]];
+    T.es = B.hi[P[0]] - B.lo[P[0]] + 1;
+    T.em = B.hi[P[1]] - B.lo[P[1]] + 1;
+    T.ef = B.hi[P[2]] - B.lo[P[2]] + 1;
     T.map_off = map_total;
     map_total += (int64_t)T.es * T.em * T.ef;
-    const int cls = c->grains_h[(size_t)g].cls;
-    int& tab = table_of[(size_t)perm * c->n_classes + cls];
-    if (tab < 0) tab = n_tables++;
-    T.table = tab;
+    T.table = table_for(B.perm, B.cls);
+    for (int32_t g : B.grains) tg[(size_t)g].table = T.table;
     // tiles holding at least one node, in (s, m, f) tile order
     const int nts = (T.es + kTS - 1) / kTS, ntm = (T.em + kTM - 1) / kTM, ntf = (T.ef + kTF - 1) / kTF;
     std::vector<uint8_t> used((size_t)nts * ntm * ntf, 0);
-    for (int64_t i = b; i < e; ++i) {
-      const int ts = (c->ijk_h[P[0] * N + i] - lo[0]) / kTS, tm = (c->ijk_h[P[1] * N + i] - lo[1]) / kTM,
-                tf = (c->ijk_h[P[2] * N + i] - lo[2]) / kTF;
-      used[((size_t)ts * ntm + tm) * ntf + tf] = 1;
-    }
+    for (int32_t g : B.grains)
+      for (int64_t i = c->grain_begin[(size_t)g]; i < c->grain_begin[(size_t)g + 1]; ++i) {
+        int x[3];
+        for (int q = 0; q < 3; ++q) x[q] = c->ijk_h[q * N + i] + tg[(size_t)g].goff[q];
+        const int ts = (x[P[0]] - T.lo_s) / kTS, tm = (x[P[1]] - T.lo_m) / kTM, tf = (x[P[2]] - T.lo_f) / kTF;
+        used[((size_t)ts * ntm + tm) * ntf + tf] = 1;
+      }
     for (int ts = 0; ts < nts; ++ts)
       for (int tm = 0; tm < ntm; ++tm)
         for (int tf = 0; tf < ntf; ++tf)
-          if (used[((size_t)ts * ntm + tm) * ntf + tf]) tiles.push_back(make_int4(g, ts * kTS, tm * kTM, tf * kTF));
+          if (used[((size_t)ts * ntm + tm) * ntf + tf]) tiles.push_back(make_int4(r, ts * kTS, tm * kTM, tf * kTF));
+  }
+  for (int32_t g = 0; g < G; ++g) {
+    rec[(size_t)g].perm = tg[(size_t)g].perm;
+    rec[(size_t)g].box = tg[(size_t)g].box;
+    rec[(size_t)g].table = tg[(size_t)g].table;
+    for (int q = 0; q < 3; ++q) rec[(size_t)g].goff[q] = tg[(size_t)g].goff[q];
   }
   // tile class K of axis order p is the offset (ds, dm, df) K-th in lexicographic
   // order; (dx, dy, dz) puts ds on axis P[0] and so on
@@ -674,14 +774,14 @@ pd_status build_tiles(pd_ctx* c) {
   hipStream_t s = c->stream;
   c->n_tiles = (int64_t)tiles.size();
   TRY(alloc_n(c, &c->tiles, std::max<int64_t>(c->n_tiles, 1), "tiles"));
-  TRY(alloc_n(c, &c->tgrain, std::max<int64_t>(G, 1), "tile grains"));
+  TRY(alloc_n(c, &c->tgrain, std::max<int64_t>((int64_t)rec.size(), 1), "tile boxes"));
   TRY(alloc_n(c, &c->tmap, std::max<int64_t>(map_total, 1), "tile cell map"));
   TRY(alloc_n(c, &c->ttab, std::max<int64_t>((int64_t)ttab.size(), 1), "tile bond tables"));
   TRY(alloc_n(c, &c->ctob, std::max<int64_t>((int64_t)ctob.size(), 1), "class to mask bit"));
   TRY(alloc_n(c, &c->mask, std::max<int64_t>((int64_t)kMaskWords * N, 1), "class masks"));
   if (c->n_tiles)
     HIPCHK(c, hipMemcpyAsync(c->tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s));
-  if (G) HIPCHK(c, hipMemcpyAsync(c->tgrain, tg.data(), sizeof(TileGrain) * G, hipMemcpyHostToDevice, s));
+  HIPCHK(c, hipMemcpyAsync(c->tgrain, rec.data(), sizeof(TileGrain) * rec.size(), hipMemcpyHostToDevice, s));
   if (!ttab.empty())
     HIPCHK(c, hipMemcpyAsync(c->ttab, ttab.data(), sizeof(StencilC) * ttab.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->ctob, ctob.data(), sizeof(int16_t) * ctob.size(), hipMemcpyHostToDevice, s));
@@ -691,6 +791,7 @@ pd_status build_tiles(pd_ctx* c) {
   HIPCHK(c, launch_cols_to_mask(A, c->ctob, c->colOrig, s));
   HIPCHK(c, hipStreamSynchronize(s));
   c->tile_ok = 1;
+  c->tile_lattice = lattice ? 1 : 0;
   return PD_OK;
 }
 
@@ -1305,6 +1406,14 @@ pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
   *launches = n;
   *total_ms = tot;
   c->ev_used = 0;
+  return PD_OK;
+}
+
+pd_status pd_tile_info(pd_ctx* c, int64_t* n_tiles, int32_t* lattice) {
+  if (!c || !n_tiles || !lattice) return PD_ERR_INVALID;
+  if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  *n_tiles = c->tile_ok ? c->n_tiles : 0;
+  *lattice = c->tile_ok ? c->tile_lattice : 0;
   return PD_OK;
 }
 

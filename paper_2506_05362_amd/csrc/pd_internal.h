@@ -71,12 +71,18 @@ constexpr int kHalo = kHS * kHM * kHF;      // 3080 cells, 73920 B of FP64 plane
 constexpr int kTileClasses = 122;           // 0 < |d|^2 <= 9
 constexpr int kMaskWords = 4;
 
+// A tile box: a grain's own lattice box, or (lattice mode) one box over every
+// grain when all of them share one lattice, spacing, bond table and node order.
+// Entries 0..G-1 describe the grains; in lattice mode entry G is the shared box
+// and each grain's box field points at it.
 struct TileGrain {
-  int64_t map_off;     // cell (s, m, f) of the grain's box -> node at tmap[map_off + (s em + m) ef + f]
+  int64_t map_off;     // cell (s, m, f) of the box -> node at tmap[map_off + (s em + m) ef + f]
   int32_t es, em, ef;  // box extents in the node-ordering axes
   int32_t table;       // bond table: ttab[table * kTileClasses + class] (slice-path StencilC rows)
   int32_t perm;        // node-ordering axes (slowest first): index into the six axis orders
   int32_t lo_s, lo_m, lo_f;  // lattice index of the box corner on those axes
+  int32_t box;         // the box this grain's nodes are tiled in (itself, or the shared box)
+  int32_t goff[3];     // x, y, z offset of the grain's lattice indices in that box's lattice
 };
 
 struct WallDev {

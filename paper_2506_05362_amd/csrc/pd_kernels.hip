@@ -1006,7 +1006,8 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
       s_u[2 * kHalo + c] = hz_[r];
     }
   }
-  const GrainC* G = A.grains + T.x;
+  // the lane's own grain (in lattice mode a tile holds nodes of several grains)
+  const GrainC* G = A.grains + (valid ? packed_grain(ui.w) : 0);
   const int pi = packed_ijk(ui.w);
   __syncthreads();
 
@@ -1034,21 +1035,23 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
 // the six orders of the lattice axes (slowest first)
 __device__ __constant__ int kAxisPerm[6][3] = {{0, 1, 2}, {0, 2, 1}, {1, 0, 2}, {1, 2, 0}, {2, 0, 1}, {2, 1, 0}};
 
-__device__ __forceinline__ void tile_coords(const TileGrain& TG, int p, int& s, int& m, int& f) {
-  const int q[3] = {unpack_x(p), unpack_y(p), unpack_z(p)};
-  s = q[kAxisPerm[TG.perm][0]] - TG.lo_s;
-  m = q[kAxisPerm[TG.perm][1]] - TG.lo_m;
-  f = q[kAxisPerm[TG.perm][2]] - TG.lo_f;
+// cell of node (packed grain-local ijk p) of grain g in its tile box B
+__device__ __forceinline__ void tile_coords(const TileGrain& Gg, const TileGrain& B, int p, int& s, int& m, int& f) {
+  const int q[3] = {unpack_x(p) + Gg.goff[0], unpack_y(p) + Gg.goff[1], unpack_z(p) + Gg.goff[2]};
+  s = q[kAxisPerm[B.perm][0]] - B.lo_s;
+  m = q[kAxisPerm[B.perm][1]] - B.lo_m;
+  f = q[kAxisPerm[B.perm][2]] - B.lo_f;
 }
 
 __global__ void k_tile_map_fill(StepArgs A) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
   const double w = A.ucur[i].w;
-  const TileGrain TG = A.tgrain[packed_grain(w)];
+  const TileGrain Gg = A.tgrain[packed_grain(w)];
+  const TileGrain B = A.tgrain[Gg.box];
   int s, m, f;
-  tile_coords(TG, packed_ijk(w), s, m, f);
-  const_cast<int32_t*>(A.tmap)[tile_cell(TG, s, m, f)] = (int32_t)i;
+  tile_coords(Gg, B, packed_ijk(w), s, m, f);
+  const_cast<int32_t*>(A.tmap)[tile_cell(B, s, m, f)] = (int32_t)i;
 }
 
 // node i's slice-path entries: bit ctob[perm][class] of the mask is set for

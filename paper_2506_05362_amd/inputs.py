@@ -125,16 +125,21 @@ def _order_nodes(ijk: np.ndarray) -> np.ndarray:
     return np.lexsort((ijk[fast], ijk[mid], ijk[slow]))
 
 
-def _grain_block(offsets: np.ndarray, origin_of_zero: np.ndarray, h: float):
+def _grain_block(offsets: np.ndarray, origin_of_zero: np.ndarray, h: float, axes=None):
     """offsets: (3, n) integer lattice points of one grain (any sign).
 
-    Returns (ijk >= 0 ordered, origin) with X = origin + h*ijk.
+    Returns (ijk >= 0 ordered, origin) with X = origin + h*ijk.  Nodes are in
+    lexicographic order of the axes `axes` (slowest first), or of the grain's
+    own longest, shortest and remaining extents when axes is None.
     """
     lo = offsets.min(axis=1)
     ijk = (offsets - lo[:, None]).astype(np.int64)
     if ijk.max() >= 1024:
         raise ValueError("grain lattice extent exceeds 1023 cells")
-    order = _order_nodes(ijk)
+    if axes is None:
+        order = _order_nodes(ijk)
+    else:
+        order = np.lexsort((ijk[axes[2]], ijk[axes[1]], ijk[axes[0]]))
     ijk = ijk[:, order]
     origin = origin_of_zero + h * lo.astype(np.float64)
     return ijk.astype(np.int32), origin
@@ -488,7 +493,7 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
         m = gid == gr
         if int(m.sum()) < min_grain_nodes:
             continue
-        ijk, origin = _grain_block(lat_k[:, m], np.full(3, 0.5 * h), h)
+        ijk, origin = _grain_block(lat_k[:, m], np.full(3, 0.5 * h), h, axes=(0, 1, 2))
         blocks.append((ijk, origin, h, 0))
     wl = _assemble("rve_aggregate", blocks, [material], params, [], [], 1,
                    info={"seed": seed, "n_grains": len(blocks), "box": L})
@@ -596,7 +601,8 @@ def large_aggregate(seed: int = 0, n_grains: int = 1000, mean_radius: float = 0.
         sel = order[bounds[gr]:bounds[gr + 1]]
         if sel.size < min_grain_nodes:
             continue
-        ijk, origin = _grain_block(lat[:, sel], np.full(3, 0.5 * h), h)
+        # one node order (x slowest, z fastest) for every grain of the shared lattice
+        ijk, origin = _grain_block(lat[:, sel], np.full(3, 0.5 * h), h, axes=(0, 1, 2))
         blocks.append((ijk, origin, h, 0))
     wl = _assemble("large_aggregate", blocks, [material], params, [], [], 1,
                    info={"seed": seed, "n_grains": len(blocks), "box": L})

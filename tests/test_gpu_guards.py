@@ -46,13 +46,29 @@ def test_skin_guard_halts_at_the_flagged_step(oracle_lib, frac):
     sim.close()
 
 
+def _closing_blocks():
+    """Two 4 x 4 x 4 blocks 2.5 h apart face to face, closing at 50 m/s, with a
+    skin of h: the faces come within R_c + skin after about 110 steps and, a
+    few rebuilds later, each face node has its opposite node and four diagonal
+    ones in range."""
+    h = 1e-4
+    params = I.default_params(h, 1e-8, rebuild_every=5)
+    params.skin = h
+    b0 = I.grain_block(I.box_offsets(4, 4, 4), np.zeros(3), h)
+    b1 = I.grain_block(I.box_offsets(4, 4, 4), np.array([5.5 * h, 0.0, 0.0]), h)
+    wl = I.assemble("blocks", [(b0[0], b0[1], h, 0), (b1[0], b1[1], h, 0)], [I.SAND], params, [], [], 1)
+    n0 = int(wl.grain_begin[1])
+    wl.v0[0, :n0] = 25.0
+    wl.v0[0, n0:] = -25.0
+    return wl
+
+
 def test_candidate_overflow_halts_at_the_rebuild(oracle_lib):
-    """Two spheres closing in with a capacity of one candidate per node (rows of
+    """Two blocks closing in with a capacity of one candidate per node (rows of
     at most two): the first rebuild whose oracle rows exceed two candidates
     raises PD_ERR_UNSTABLE, and the context stops at that step."""
     from paper_2506_05362_amd import pd
-    wl = I.two_spheres(radius_cells=5, speed=20.0, gap=0.0, rebuild_every=5)
-    wl.u0[0, wl.grain_begin[1]:] += 1.5 * wl.params.skin  # start just out of range
+    wl = _closing_blocks()
     ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
     assert ora.candidates()[1].size == 0
     flagged = None

@@ -22,14 +22,23 @@ def cases():
                                          notch_len=15 * 5e-4, steps=1),
         "aggregate_hollow": I.grain_aggregate(n_grains=6, grid=(3, 2, 1), n_min=800, n_max=3000, seed=2,
                                               platen_speed=5.0, rebuild_every=10),
+        # tessellations on one lattice: tiles over one box across all grains
+        "lattice_aggregate": I.large_aggregate(seed=2, n_grains=30, h=1.6e-4, platen_speed=50.0),
+        "lattice_volume": I.rve_aggregate(seed=3, n_grains=12, nodes_per_grain=300, confinement=15e6,
+                                          platen_speed=20.0, rebuild_every=10),
     }
 
 
-def run(wl, steps, bond_path, loop=0):
+LATTICE_CASES = ("lattice_aggregate", "lattice_volume")
+
+
+def run(wl, steps, bond_path, loop=0, lattice=None):
     from paper_2506_05362_amd import pd
     sim = pd.Sim(wl)
     sim.set_launch(loop=loop, bond_path=bond_path)
     assert sim.get_launch()["bond_path"] == bond_path
+    if lattice is not None:
+        assert sim.tile_info()["lattice"] == lattice
     sim.step(steps)
     out = {f: sim.get(f) for f in NODE_FIELDS + ["wall_force"]}
     sim.close()
@@ -52,7 +61,7 @@ def test_tiles_bitwise_equal_to_slices(case):
     steps = 60
     ref = run(wl, steps, pd.BONDS_SLICES)
     for loop in (pd.LOOP_GRAPH, pd.LOOP_DIRECT):
-        got = run(wl, steps, pd.BONDS_TILES, loop)
+        got = run(wl, steps, pd.BONDS_TILES, loop, lattice=case in LATTICE_CASES)
         assert_same(ref, got, f"{case} loop {loop}")
     if case == "spheres_fracture":
         assert ref["bond_broken"].any()  # the comparison covered bond breaking
@@ -93,9 +102,9 @@ def test_tile_path_matches_oracle(oracle_lib):
     for name, key in (("displacement", "u"), ("velocity", "v")):
         g = sim.get(name)
         assert np.abs(g - so[key]).max() <= 1e-9 * np.abs(so[key]).max(), name
-    rp, col, br = sim.bonds()
-    rpo, colo, bro = ora.bonds()
-    assert np.array_equal(br, bro) and br.any()
+    from test_gpu_parity import assert_broken_sets
+    assert_broken_sets(sim, ora, what="tile path")
+    assert sim.bonds()[2].any()
 
 
 def test_tile_path_argument_errors():
