@@ -233,13 +233,11 @@ pd_status pd_get_state(pd_ctx* ctx, void* blob, int64_t* bytes);
 /* Restore a checkpoint taken from a context built from the same inputs. */
 pd_status pd_set_state(pd_ctx* ctx, const void* blob, int64_t bytes);
 
-/* Measurement hook: with enable != 0, pd_step brackets each launch of the
-   fused step kernel with a pair of HIP events on the context stream.  A
-   directly launched step records them around its launch; a replayed step loop
-   is a second captured graph with event-record nodes around each step kernel,
-   and pd_step waits after each replay to read them.  pd_timing waits for the
-   stream, returns the number of bracketed launches and their summed duration
-   in milliseconds, and clears the record. */
+/* Measurement hook: with enable != 0, pd_step launches every step directly
+   (no graph replay) and brackets each launch of the fused step kernel with a
+   pair of HIP events on the context stream.  pd_timing waits for the stream,
+   returns the number of bracketed launches and their summed duration in
+   milliseconds, and clears the record. */
 pd_status pd_set_timing(pd_ctx* ctx, int32_t enable);
 pd_status pd_timing(pd_ctx* ctx, int64_t* launches, double* total_ms);
 

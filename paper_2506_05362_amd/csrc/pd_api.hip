@@ -115,17 +115,11 @@ struct pd_ctx {
   uint32_t* mask = nullptr;  // [kMaskWords][N]
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
-  // captured step loop of graph_len steps; with timing on, a second capture
-  // whose step kernels are bracketed by event-record nodes (tev, one pair per step)
+  // captured step loop of graph_len steps
   int use_graph = 1;
   int64_t graph_len = 0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
-  hipGraph_t graph_t = nullptr;
-  hipGraphExec_t graph_exec_t = nullptr;
-  std::vector<hipEvent_t> tev;
-  double timed_ms = 0.0;  // step-kernel time of replayed timed graphs since the last pd_timing
-  int64_t timed_n = 0;
   // how the steps of this context were launched: graph replays, steps in them,
   // directly launched steps, persistent launches and the steps in them
   int64_t counts[5] = {0, 0, 0, 0, 0};
@@ -369,15 +363,9 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   return C;
 }
 
-// the closing event of captured step p (1-based) of the timed graph
-hipEvent_t ev1_node(pd_ctx* c, int64_t p) {
-  const size_t k = (size_t)(2 * (p - 1) + 1);
-  return k < c->tev.size() ? c->tev[k] : nullptr;
-}
-
 // one step on the device: rebuild on cadence, force+Verlet, walls.
 // ev0/ev1 (optional) bracket the step kernel.
-pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1, bool record_nodes = false) {
+pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) {
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
     ContactArgs C = contact_args(c, nxt);
@@ -386,10 +374,7 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1, 
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
   HIPCHK(c, launch_wall_corners(A, 0, c->stream));
-  // a single step launch records ev0/ev1 itself, tightly around the kernel;
-  // under stream capture the events become record nodes around the kernel node
-  if (record_nodes && ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
-  if (record_nodes) ev0 = ev1 = nullptr;
+  // a single step launch records ev0/ev1 itself, tightly around the kernel
   if (c->launch.bond_path == PD_BONDS_TILES) {
     A.partial_stride = kTS * c->n_tiles;  // one wall-partial column per tile wavefront
     HIPCHK(c, launch_step_tile(A, c->stream, ev0, ev1));
@@ -412,7 +397,6 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1, 
   } else {
     HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream, ev0, ev1));
   }
-  if (record_nodes && ev1_node(c, s)) HIPCHK(c, hipEventRecord(ev1_node(c, s), c->stream));
   HIPCHK(c, launch_wall_finalize(A, c->stream));
   return PD_OK;
 }
@@ -444,25 +428,14 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
   return PD_OK;
 }
 
-// capture graph_len steps starting at a multiple of graph_len (buffer parity 0);
-// timed: every step kernel between a pair of event-record nodes
-pd_status capture_graph(pd_ctx* c, bool timed) {
-  hipGraphExec_t& exec = timed ? c->graph_exec_t : c->graph_exec;
-  hipGraph_t& graph = timed ? c->graph_t : c->graph;
-  if (exec) return PD_OK;
-  if (timed) {
-    while ((int64_t)c->tev.size() < 2 * c->graph_len) {
-      hipEvent_t e;
-      HIPCHK(c, hipEventCreate(&e));
-      c->tev.push_back(e);
-    }
-  }
+// capture graph_len steps starting at a multiple of graph_len (buffer parity 0)
+pd_status capture_graph(pd_ctx* c) {
+  if (c->graph_exec) return PD_OK;
   const int cur0 = c->cur;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   pd_status st = PD_OK;
-  for (int64_t p = 1; p <= c->graph_len && st == PD_OK; ++p)  // p stands for any step congruent to it
-    st = timed ? enqueue_step_ev(c, p, c->tev[(size_t)(2 * (p - 1))], nullptr, true)
-               : enqueue_step_ev(c, p, nullptr, nullptr);
+  for (int64_t p = 1; p <= c->graph_len && st == PD_OK; ++p)
+    st = enqueue_step_ev(c, p, nullptr, nullptr);  // p stands for any step congruent to it
   hipGraph_t g = nullptr;
   const hipError_t ec = hipStreamEndCapture(c->stream, &g);
   c->cur = cur0;
@@ -471,19 +444,19 @@ pd_status capture_graph(pd_ctx* c, bool timed) {
     return st;
   }
   if (ec != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamEndCapture failed: %s", hipGetErrorName(ec));
-  graph = g;
-  HIPCHK(c, hipGraphInstantiate(&exec, g, nullptr, nullptr, 0));
+  c->graph = g;
+  HIPCHK(c, hipGraphInstantiate(&c->graph_exec, g, nullptr, nullptr, 0));
   return PD_OK;
 }
 
 pd_status drop_graphs(pd_ctx* c) {
-  if (c->graph_exec || c->graph_exec_t) HIPCHK(c, hipStreamSynchronize(c->stream));
-  if (c->graph_exec) HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
-  if (c->graph_exec_t) HIPCHK(c, hipGraphExecDestroy(c->graph_exec_t));
+  if (c->graph_exec) {
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipGraphExecDestroy(c->graph_exec));
+  }
   if (c->graph) HIPCHK(c, hipGraphDestroy(c->graph));
-  if (c->graph_t) HIPCHK(c, hipGraphDestroy(c->graph_t));
-  c->graph_exec = c->graph_exec_t = nullptr;
-  c->graph = c->graph_t = nullptr;
+  c->graph_exec = nullptr;
+  c->graph = nullptr;
   return PD_OK;
 }
 
@@ -1311,23 +1284,12 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
     c->counts[4] += k;
   }
   while (left > 0) {
-    const bool aligned = c->use_graph && c->launch.loop == PD_LOOP_GRAPH && c->step % c->graph_len == 0 &&
-                         left >= c->graph_len;
+    // timing brackets each step kernel with events, so it launches directly
+    const bool aligned = c->use_graph && c->launch.loop == PD_LOOP_GRAPH && !c->timing &&
+                         c->step % c->graph_len == 0 && left >= c->graph_len;
     if (aligned) {
-      // with timing on, the replayed graph carries event-record nodes around each
-      // step kernel; their times are collected after the replay (the next replay
-      // records the same events again)
-      TRY(capture_graph(c, c->timing != 0));
-      HIPCHK(c, hipGraphLaunch(c->timing ? c->graph_exec_t : c->graph_exec, c->stream));
-      if (c->timing) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
-        for (int64_t p = 0; p < c->graph_len; ++p) {
-          float ms = 0.0f;
-          HIPCHK(c, hipEventElapsedTime(&ms, c->tev[(size_t)(2 * p)], c->tev[(size_t)(2 * p + 1)]));
-          c->timed_ms += ms;
-          c->timed_n += 1;
-        }
-      }
+      TRY(capture_graph(c));
+      HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
       c->step += c->graph_len;
       left -= c->graph_len;
       c->counts[0] += 1;
@@ -1385,18 +1347,14 @@ pd_status pd_set_timing(pd_ctx* c, int32_t enable) {
   if (!c) return PD_ERR_INVALID;
   c->timing = enable != 0;
   c->ev_used = 0;
-  c->timed_ms = 0.0;
-  c->timed_n = 0;
   return PD_OK;
 }
 
 pd_status pd_timing(pd_ctx* c, int64_t* launches, double* total_ms) {
   if (!c || !launches || !total_ms) return PD_ERR_INVALID;
   HIPCHK(c, hipStreamSynchronize(c->stream));
-  double tot = c->timed_ms;
-  int64_t n = c->timed_n;
-  c->timed_ms = 0.0;
-  c->timed_n = 0;
+  double tot = 0.0;
+  int64_t n = 0;
   for (size_t k = 0; k + 1 < c->ev_used; k += 2) {
     float ms = 0.0f;
     HIPCHK(c, hipEventElapsedTime(&ms, c->ev_pool[k], c->ev_pool[k + 1]));
@@ -1738,11 +1696,8 @@ void pd_destroy(pd_ctx* c) {
   if (!c) return;
   (void)hipStreamSynchronize(c->stream);
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
-  for (hipEvent_t e : c->tev) (void)hipEventDestroy(e);
   if (c->graph_exec) (void)hipGraphExecDestroy(c->graph_exec);
-  if (c->graph_exec_t) (void)hipGraphExecDestroy(c->graph_exec_t);
   if (c->graph) (void)hipGraphDestroy(c->graph);
-  if (c->graph_t) (void)hipGraphDestroy(c->graph_t);
   std::vector<void*> all = c->owned;
   for (void* p : all) dev_free(c, p);
   if (c->own_stream) (void)hipStreamDestroy(c->stream);
