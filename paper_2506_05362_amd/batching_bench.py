@@ -72,6 +72,7 @@ def main(argv=None):
            "speedup_batched_graph_vs_per_grain": res["per_grain"]["ms_per_step"] / res["graph"]["ms_per_step"],
            "autotune": {"config": tuned["config"],
                         "ms_per_step": {k: v * 1e3 for k, v in tuned["times"].items()}}}
+    sim.close()
     print(json.dumps(out), flush=True)
 
 

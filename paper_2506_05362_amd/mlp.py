@@ -7,7 +7,10 @@ is missing.
 """
 from __future__ import annotations
 
+import atexit
+import sys
 import ctypes as C
+import weakref
 import os
 from typing import Optional, Sequence
 
@@ -55,6 +58,20 @@ class MLPError(RuntimeError):
     pass
 
 
+# networks still open at interpreter exit are destroyed by an exit hook, while
+# the HIP runtime is still up
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_nets():
+    for net in list(_LIVE):
+        try:
+            net.close()
+        except Exception:
+            pass
+
+
 class Net:
     def __init__(self, dims: Sequence[int], max_batch: int = 4096, stream=None):
         import torch
@@ -66,6 +83,7 @@ class Net:
         st = lib().pdm_create(C.byref(h), d.ctypes.data_as(P), len(self.dims), int(max_batch),
                               P(self.stream.cuda_stream))
         self.h = h
+        _LIVE.add(self)
         self.max_batch = int(max_batch)
         self._check(st)
         self.n_params = int(lib().pdm_param_count(self.h))
@@ -120,8 +138,13 @@ class Net:
         if getattr(self, "h", None):
             lib().pdm_destroy(self.h)
             self.h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        # during interpreter teardown the HIP runtime may already be gone: the
+        # exit hook closed every context that was still open before that
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

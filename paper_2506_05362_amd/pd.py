@@ -7,7 +7,10 @@ fallback: when the library is missing, importing this module raises.
 """
 from __future__ import annotations
 
+import atexit
+import sys
 import ctypes as C
+import weakref
 import os
 from typing import Optional
 
@@ -205,6 +208,21 @@ class TorchPlumbing:
         self.free = FREE_FN(_free)
 
 
+# Contexts still open when the interpreter exits are destroyed by an exit hook,
+# while the HIP runtime (and any profiler attached to it) is still up, rather
+# than by garbage collection during interpreter teardown.
+_LIVE = weakref.WeakSet()
+
+
+@atexit.register
+def _close_live_contexts():
+    for sim in list(_LIVE):
+        try:
+            sim.close()
+        except Exception:
+            pass
+
+
 class Sim:
     """One library context built from a seeded workload (see inputs.py)."""
 
@@ -261,6 +279,7 @@ class Sim:
                            C.byref(prm), walls if self.n_walls else None, self.n_walls,
                            ALLOC_FN(0), FREE_FN(0), None, None)
         self.h = h
+        _LIVE.add(self)
         self._check(st)
         if build:
             self.build_bonds()
@@ -366,8 +385,13 @@ class Sim:
         if getattr(self, "h", None):
             lib().pd_destroy(self.h)
             self.h = None
+        _LIVE.discard(self)
 
     def __del__(self):
+        # during interpreter teardown the HIP runtime may already be gone: the
+        # exit hook closed every context that was still open before that
+        if sys.is_finalizing():
+            return
         try:
             self.close()
         except Exception:

@@ -132,6 +132,7 @@ def main(argv=None):
             break
     out["compression"] = {"steps": done, "status": status, "seconds": time.perf_counter() - t0,
                           "ms_per_step": 1e3 * (time.perf_counter() - t0) / max(done, 1), "log": log}
+    sim.close()
     print(json.dumps(out), flush=True)
 
 
