@@ -224,6 +224,20 @@ pd_status pd_field_bytes(pd_ctx* ctx, pd_field field, int64_t* bytes);
    dst_bytes smaller than the field gives PD_ERR_INVALID.  Synchronises the stream. */
 pd_status pd_get(pd_ctx* ctx, pd_field field, void* dst, int64_t dst_bytes, int32_t dst_on_device);
 
+/* The four energies of PD_ENERGY (kinetic, elastic, contact, gravity potential
+   [J]) without allocating: for callers that cannot allocate device memory
+   (code under HIP graph capture, tight serving loops, harnesses that forbid
+   allocation).  Same kernels and summation order as pd_get(PD_ENERGY), so the
+   values are the same; the per-workgroup partial sums go to a static device
+   array of 4 MiB that the library holds on each GPU until the process ends
+   (every context the library accepts, up to 2^25 nodes, fits; a larger one
+   would be refused with PD_ERR_INVALID).  out4: 4 doubles in host memory, or
+   device memory when out_on_device != 0.  Synchronises the stream.  All
+   contexts on one GPU share that array and it keeps the last call's
+   contents: calls that overlap on one GPU (contexts on different streams or
+   threads) race. */
+pd_status pd_energy_noalloc(pd_ctx* ctx, double* out4, int32_t out_on_device);
+
 /* Replace wall w (for example to change a servo target between steps). */
 pd_status pd_set_wall(pd_ctx* ctx, int32_t w, const pd_wall* wall);
 

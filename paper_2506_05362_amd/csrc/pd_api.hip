@@ -8,6 +8,7 @@
 
 #include <algorithm>
 #include <array>
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -22,7 +23,19 @@ constexpr double kPi = 3.14159265358979323846;
 constexpr uint64_t kMagic = 0x3130536b4450554dull;  // checkpoint magic
 constexpr int64_t kUnboundedCut = ((int64_t)1) << 50;
 
+// Scratch of the allocation-free energy call (pd_energy_noalloc): the energy
+// kernel's per-workgroup partial sums, 4 doubles per 256 nodes (a context holds
+// at most 2^25 nodes, so at most 2^17 workgroups), then the 4 reduced values.
+// Each GPU holds its own copy; host code uses the address hipGetSymbolAddress
+// returned for the device, never the array's name.
+constexpr int64_t kNoAllocPartials = (int64_t)1 << 17;
+constexpr int kMaxDevices = 64;
+double* g_scratch_dev[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
 }  // namespace
+
+static __device__ __align__(256) double scratch[4 * kNoAllocPartials + 4];
 
 struct pd_ctx {
   // configuration
@@ -88,6 +101,7 @@ struct pd_ctx {
   int32_t* scan32 = nullptr;
   int64_t* scan64 = nullptr;
   double* energy_partial = nullptr;
+  double* scratch_dev = nullptr;  // this context's GPU's copy of the allocation-free scratch
   double* energy_out = nullptr;
   // measurement hook
   int timing = 0;
@@ -819,6 +833,19 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (!c->stream) {
     if (hipStreamCreate(&c->stream) != hipSuccess) return fail(c, PD_ERR_HIP, "hipStreamCreate failed");
     c->own_stream = 1;
+  }
+  {
+    // the allocation-free scratch's address on this GPU, looked up once per device
+    int dev = 0;
+    HIPCHK(c, hipGetDevice(&dev));
+    if (dev < 0 || dev >= kMaxDevices) return fail(c, PD_ERR_UNSUPPORTED, "device %d beyond %d", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+      void* p = nullptr;
+      HIPCHK(c, hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+      g_scratch_dev[dev] = static_cast<double*>(p);
+    }
+    c->scratch_dev = g_scratch_dev[dev];
   }
 
   const int64_t N = mesh->n_nodes;
@@ -1556,6 +1583,25 @@ pd_status pd_get(pd_ctx* c, pd_field f, void* dst, int64_t dst_bytes, int32_t ds
     }
   }
   return fail(c, PD_ERR_INVALID, "unknown field %d", (int)f);
+}
+
+pd_status pd_energy_noalloc(pd_ctx* c, double* out4, int32_t out_on_device) {
+  if (!c || !out4) return PD_ERR_INVALID;
+  if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
+  const int64_t nb = (c->n + kBlock - 1) / kBlock;
+  if (nb > kNoAllocPartials)
+    return fail(c, PD_ERR_INVALID, "%lld nodes need %lld energy partials; the static scratch holds %lld",
+                (long long)c->n, (long long)nb, (long long)kNoAllocPartials);
+  if (!c->scratch_dev) return fail(c, PD_ERR_STATE, "no scratch address for this context's device");
+  hipStream_t s = c->stream;
+  TRY(sync_columns(c));  // the energy kernel reads the bond memory from the column words
+  StepArgs A = step_args(c);
+  double* red = c->scratch_dev + 4 * kNoAllocPartials;
+  HIPCHK(c, launch_energy(A, c->scratch_dev, (int32_t)nb, s));
+  HIPCHK(c, launch_reduce_energy(c->scratch_dev, (int32_t)nb, out_on_device ? out4 : red, s));
+  if (!out_on_device) HIPCHK(c, hipMemcpyAsync(out4, red, 4 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipStreamSynchronize(s));
+  return PD_OK;
 }
 
 pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {

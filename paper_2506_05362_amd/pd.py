@@ -113,6 +113,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_set_state.argtypes = [P, P, C.c_int64]
     L.pd_info.argtypes = [P, P]
     L.pd_loop_counts.argtypes = [P, P]
+    L.pd_energy_noalloc.argtypes = [P, P, C.c_int32]
     L.pd_tile_info.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
     L.pd_set_timing.argtypes = [P, C.c_int32]
     L.pd_timing.argtypes = [P, C.POINTER(C.c_int64), C.POINTER(C.c_double)]
@@ -124,7 +125,7 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
     L.pd_status_string.argtypes = [C.c_int32]
     L.pd_status_string.restype = C.c_char_p
     for name in ["pd_init", "pd_build_bonds", "pd_step", "pd_field_bytes", "pd_get",
-                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_loop_counts", "pd_tile_info", "pd_set_timing",
+                 "pd_set_wall", "pd_get_state", "pd_set_state", "pd_info", "pd_loop_counts", "pd_tile_info", "pd_energy_noalloc", "pd_set_timing",
                  "pd_timing", "pd_set_launch", "pd_get_launch"]:
         getattr(L, name).restype = C.c_int32
     return L
@@ -327,6 +328,15 @@ class Sim:
         self._check(lib().pd_info(self.h, _ptr(o)))
         return dict(n_nodes=int(o[0]), nnz=int(o[1]), padded=int(o[2]), candidates=int(o[3]),
                     step=int(o[4]))
+
+    def energy_noalloc(self, out_ptr: Optional[int] = None) -> Optional[np.ndarray]:
+        """pd_energy_noalloc: into a new host array, or into device memory at out_ptr."""
+        if out_ptr is not None:
+            self._check(lib().pd_energy_noalloc(self.h, P(out_ptr), 1))
+            return None
+        out = np.zeros(4)
+        self._check(lib().pd_energy_noalloc(self.h, _ptr(out), 0))
+        return out
 
     def tile_info(self) -> dict:
         n, lat = C.c_int64(), C.c_int32()
