@@ -36,10 +36,13 @@ extern "C" {
 typedef struct pdm_net pdm_net;
 
 /* Create a network; n_dims >= 2, every dim in [1, 1024]; max_batch bounds the
-   batch of pdm_train_step / pdm_gradients (workspace is sized for it);
+   batch of pdm_train_step / pdm_gradients (workspace is sized for it).
+   alloc/free_fn: the caller's device allocator (for example PyTorch's caching
+   allocator), used for every device buffer of the network; both NULL for
+   hipMalloc/hipFree, one NULL without the other is PD_ERR_INVALID.
    stream: hipStream_t (not the legacy null stream) or NULL for an owned one. */
 pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t max_batch,
-                     void* stream);
+                     pd_alloc_fn alloc, pd_free_fn free_fn, void* alloc_user, void* stream);
 int64_t pdm_param_count(const pdm_net* net);
 /* Load parameters (host FP32 vector of pdm_param_count entries); resets Adam. */
 pd_status pdm_set_params(pdm_net* net, const float* params, int64_t n);
@@ -49,7 +52,8 @@ pd_status pdm_get_params(pdm_net* net, float* params, int64_t n);
    the gradient moments. */
 pd_status pdm_set_adam(pdm_net* net, float beta1, float beta2, float eps, float weight_decay);
 /* Inference: y[batch][dims[n-1]] = net(x[batch][dims[0]]); any batch size
-   (processed in chunks of max_batch).  For dims {din <= 16, 256, 256, 256,
+   (processed in chunks of max_batch).  Matrix products use gfx950's
+   16 x 16 x 32 BF16 matrix-core instruction.  For dims {din <= 16, 256, 256, 256,
    dout <= 16} a fused path runs by default: two kernels with a weight matrix
    resident in LDS, the first hidden pair's activations kept in registers and
    only the second hidden layer's BF16 activations stored between them; its

@@ -3,11 +3,11 @@
 // include/pd_mlp.h.
 //
 // Every layer product is one kernel k_gemm: a 256-thread workgroup computes a
-// 64 x 64 tile of C = A B with v_mfma_f32_16x16x16_bf16 (each wavefront owns a
-// 32 x 32 quarter as 2 x 2 matrix-core blocks); A and B are read from FP32
-// arrays through arbitrary strides (so the transposed operands of the
-// backward pass need no copies), rounded to BF16 and staged in LDS 16 columns
-// of K at a time.
+// 64 x 64 tile of C = A B with gfx950's v_mfma_f32_16x16x32_bf16 (each
+// wavefront owns a 32 x 32 quarter as 2 x 2 matrix-core blocks); A and B are
+// read from FP32 arrays through arbitrary strides (so the transposed operands
+// of the backward pass need no copies), rounded to BF16 and staged in LDS 32
+// columns of K at a time.
 
 #include <hip/hip_runtime.h>
 #include <math.h>
@@ -25,10 +25,21 @@
 namespace {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8bf __attribute__((ext_vector_type(8)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 
 constexpr int kTile = 64;
-constexpr int kK = 16;
+constexpr int kK = 32;
+constexpr int kKRow = kK + 8;  // LDS row of a staged tile (bf16): 16-byte aligned, banks staggered
+
+// C += A B on the matrix cores, 16 x 16 x 32 in BF16 with FP32 accumulation.
+// Lane l holds 8 consecutive k of row l % 16 of A (group l / 16) and the same
+// 8 k of column l % 16 of B, so A and B pair each k alike; the result C[4
+// (l / 16) + e][l % 16] lands in element e.
+__device__ __forceinline__ v4f mfma_16x16x32(const v8s& a, const v8s& b, const v4f& c) {
+  return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8bf, a), __builtin_bit_cast(v8bf, b), c, 0, 0, 0);
+}
 
 // FP32 -> BF16, round to nearest even (NaN kept quiet)
 __device__ __forceinline__ short to_bf16(float x) {
@@ -60,8 +71,8 @@ enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
 
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
-  __shared__ short As[kTile][kK];  // As[m][k]
-  __shared__ short Bs[kTile][kK];  // Bs[n][k] (B transposed)
+  __shared__ __align__(16) short As[kTile][kKRow];  // As[m][k]
+  __shared__ __align__(16) short Bs[kTile][kKRow];  // Bs[n][k] (B transposed)
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m0 = (int64_t)blockIdx.y * kTile, n0 = (int64_t)blockIdx.x * kTile;
   const int wm = (wv >> 1) * 32, wn = (wv & 1) * 32;
@@ -70,34 +81,32 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   for (int i = 0; i < 2; ++i)
 #pragma unroll
     for (int j = 0; j < 2; ++j) acc[i][j] = v4f{0.f, 0.f, 0.f, 0.f};
-  const int lr = tid >> 2, lk = (tid & 3) * 4;  // staging: row / column of the tile, 4 k each
+  const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column of the tile, 8 k each
   for (int64_t k0 = 0; k0 < g.K; k0 += kK) {
     {
       const int64_t m = m0 + lr;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 8; ++e) {
         const int64_t k = k0 + lk + e;
         As[lr][lk + e] = to_bf16((m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.0f);
       }
       const int64_t n = n0 + lr;
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
+      for (int e = 0; e < 8; ++e) {
         const int64_t k = k0 + lk + e;
         Bs[lr][lk + e] = to_bf16((n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : 0.0f);
       }
     }
     __syncthreads();
-    // operand layout of the 16x16x16 BF16 matrix core: lane l holds A[l%16][4(l/16)..+3]
-    // and B[4(l/16)..+3][l%16]; the result C[4(l/16)+e][l%16] lands in element e
-    v4s a[2], b[2];
+    v8s a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v4s*>(&As[wm + i * 16 + (lane & 15)][4 * (lane >> 4)]);
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const v8s*>(&As[wm + i * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const v4s*>(&Bs[wn + j * 16 + (lane & 15)][4 * (lane >> 4)]);
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const v8s*>(&Bs[wn + j * 16 + (lane & 15)][8 * (lane >> 4)]);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a[i], b[j], acc[i][j], 0, 0, 0);
+      for (int j = 0; j < 2; ++j) acc[i][j] = mfma_16x16x32(a[i], b[j], acc[i][j]);
     __syncthreads();
   }
 #pragma unroll
@@ -183,8 +192,8 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // ---------------------------------------------------------------------------
 
 constexpr int kH = 256;          // hidden width of the fused path
-constexpr int kWRow = kH + 4;    // LDS row of a transposed weight matrix (bf16), padded
-constexpr int kTRow = 16 + 4;    // per-wavefront transpose tile row (bf16)
+constexpr int kWRow = kH + 8;    // LDS row of a transposed weight matrix (bf16), padded, 16-byte aligned
+constexpr int kTRow = 32 + 8;    // per-wavefront transpose tile row (bf16)
 
 __device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
 
@@ -213,10 +222,10 @@ __global__ void k_pack_t(const float* W, int K, int N, int rows_out, short* out)
 }
 
 __device__ __forceinline__ void stage_weights_t(const short* src, int rows, short* dst) {
-  // rows x kH bf16 (8-byte pieces) into LDS rows of kWRow
-  for (int i = threadIdx.x; i < rows * (kH / 4); i += blockDim.x) {
-    const int r = i / (kH / 4), c = (i % (kH / 4)) * 4;
-    *reinterpret_cast<v4s*>(dst + r * kWRow + c) = *reinterpret_cast<const v4s*>(src + (int64_t)r * kH + c);
+  // rows x kH bf16 (16-byte pieces) into LDS rows of kWRow
+  for (int i = threadIdx.x; i < rows * (kH / 8); i += blockDim.x) {
+    const int r = i / (kH / 8), c = (i % (kH / 8)) * 8;
+    *reinterpret_cast<v8s*>(dst + r * kWRow + c) = *reinterpret_cast<const v8s*>(src + (int64_t)r * kH + c);
   }
 }
 
@@ -249,11 +258,11 @@ __global__ __launch_bounds__(256) void k_infer_a(Infer a) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int kk = 0; kk < 16; ++kk) {
-      v4s A;
+    for (int kk = 0; kk < kH / 32; ++kk) {
+      v8s A;
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int k = kk * 16 + 4 * lg + j;
+      for (int j = 0; j < 8; ++j) {
+        const int k = kk * 32 + 8 * lg + j;
         float z = 0.0f;
 #pragma unroll
         for (int i = 0; i < DINP; ++i) z = fmaf(xv[i], sW1[i * kH + k], z);
@@ -261,8 +270,8 @@ __global__ __launch_bounds__(256) void k_infer_a(Infer a) {
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const v4s b = *reinterpret_cast<const v4s*>(sW + (q * 16 + lr) * kWRow + kk * 16 + 4 * lg);
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b, acc[q], 0, 0, 0);
+        const v8s b = *reinterpret_cast<const v8s*>(sW + (q * 16 + lr) * kWRow + kk * 32 + 8 * lg);
+        acc[q] = mfma_16x16x32(A, b, acc[q]);
       }
     }
 #pragma unroll
@@ -282,6 +291,7 @@ __global__ __launch_bounds__(256) void k_infer_b(Infer a) {
   short* sW = reinterpret_cast<short*>(smem);                  // [kH][kWRow]
   short* sW4 = sW + kH * kWRow;                                // [16][kWRow]
   short* sT = sW4 + 16 * kWRow;                                // [4][16][kTRow]
+  static_assert((kWRow * 2) % 16 == 0 && (kTRow * 2) % 16 == 0, "16-byte LDS rows");
   float* sb3 = reinterpret_cast<float*>(sT + 4 * 16 * kTRow);  // [kH]
   float* sb4 = sb3 + kH;                                       // [16]
   const int tid = threadIdx.x;
@@ -300,26 +310,30 @@ __global__ __launch_bounds__(256) void k_infer_b(Infer a) {
 #pragma unroll
     for (int q = 0; q < 16; ++q) acc[q] = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll 2
-    for (int kk = 0; kk < 16; ++kk) {
-      const v4s A = row < a.M ? *reinterpret_cast<const v4s*>(a.H2 + row * kH + kk * 16 + 4 * lg)
-                              : v4s{0, 0, 0, 0};
+    for (int kk = 0; kk < kH / 32; ++kk) {
+      const v8s A = row < a.M ? *reinterpret_cast<const v8s*>(a.H2 + row * kH + kk * 32 + 8 * lg)
+                              : v8s{0, 0, 0, 0, 0, 0, 0, 0};
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        const v4s b = *reinterpret_cast<const v4s*>(sW + (q * 16 + lr) * kWRow + kk * 16 + 4 * lg);
-        acc[q] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(A, b, acc[q], 0, 0, 0);
+        const v8s b = *reinterpret_cast<const v8s*>(sW + (q * 16 + lr) * kWRow + kk * 32 + 8 * lg);
+        acc[q] = mfma_16x16x32(A, b, acc[q]);
       }
     }
-    // each 16 x 16 tile of layer 3: GELU, then transposed into the A operand of layer 4
+    // each pair of 16 x 16 tiles of layer 3: GELU, then transposed into the
+    // 16 x 32 A operand of layer 4
     v4f acc4 = v4f{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = q * 16 + lr;
+    for (int q2 = 0; q2 < 8; ++q2) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) T[(4 * lg + e) * kTRow + lr] = to_bf16(gelu(acc[q][e] + sb3[col]));
+      for (int h = 0; h < 2; ++h) {
+        const int q = 2 * q2 + h, col = q * 16 + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T[(4 * lg + e) * kTRow + 16 * h + lr] = to_bf16(gelu(acc[q][e] + sb3[col]));
+      }
       __syncthreads();
-      const v4s a4 = *reinterpret_cast<const v4s*>(T + lr * kTRow + 4 * lg);
-      const v4s b4 = *reinterpret_cast<const v4s*>(sW4 + lr * kWRow + q * 16 + 4 * lg);
-      acc4 = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a4, b4, acc4, 0, 0, 0);
+      const v8s a4 = *reinterpret_cast<const v8s*>(T + lr * kTRow + 8 * lg);
+      const v8s b4 = *reinterpret_cast<const v8s*>(sW4 + lr * kWRow + q2 * 32 + 8 * lg);
+      acc4 = mfma_16x16x32(a4, b4, acc4);
       __syncthreads();
     }
 #pragma unroll
@@ -353,6 +367,9 @@ struct pdm_net {
   short *W2t = nullptr, *W3t = nullptr, *W4t = nullptr, *H2 = nullptr;
   int64_t t = 0;
   std::vector<void*> owned;
+  pd_alloc_fn alloc = nullptr;  // caller's device allocator (hipMalloc when none)
+  pd_free_fn free_fn = nullptr;
+  void* alloc_user = nullptr;
 };
 
 namespace {
@@ -377,8 +394,10 @@ pd_status fail(pdm_net* n, pd_status st, const char* fmt, ...) {
 template <typename T>
 pd_status alloc(pdm_net* n, T** p, int64_t count) {
   void* q = nullptr;
-  if (hipMalloc(&q, sizeof(T) * (size_t)(count > 0 ? count : 1)) != hipSuccess)
-    return fail(n, PD_ERR_OOM, "device allocation of %lld elements failed", (long long)count);
+  const size_t bytes = (sizeof(T) * (size_t)(count > 0 ? count : 1) + 255) & ~size_t(255);
+  if (n->alloc) q = n->alloc(bytes, n->alloc_user);
+  else if (hipMalloc(&q, bytes) != hipSuccess) q = nullptr;
+  if (!q) return fail(n, PD_ERR_OOM, "device allocation of %lld elements failed", (long long)count);
   n->owned.push_back(q);
   *p = static_cast<T*>(q);
   return PD_OK;
@@ -494,12 +513,17 @@ pd_status loss_and_grad(pdm_net* n, const float* x, const float* y, int64_t batc
 
 extern "C" {
 
-pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t max_batch, void* stream) {
+pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t max_batch, pd_alloc_fn alloc_fn,
+                     pd_free_fn free_fn, void* alloc_user, void* stream) {
   if (!out) return PD_ERR_INVALID;
   *out = nullptr;
+  if ((alloc_fn == nullptr) != (free_fn == nullptr)) return PD_ERR_INVALID;
   pdm_net* n = new (std::nothrow) pdm_net();
   if (!n) return PD_ERR_OOM;
   *out = n;
+  n->alloc = alloc_fn;
+  n->free_fn = free_fn;
+  n->alloc_user = alloc_user;
   if (!dims || n_dims < 2) return fail(n, PD_ERR_INVALID, "need at least two layer widths");
   for (int k = 0; k < n_dims; ++k)
     if (dims[k] < 1 || dims[k] > 1024) return fail(n, PD_ERR_INVALID, "layer width %d out of [1, 1024]", dims[k]);
@@ -676,7 +700,10 @@ pd_status pdm_train_step(pdm_net* n, const float* x, const float* y, int64_t bat
 void pdm_destroy(pdm_net* n) {
   if (!n) return;
   (void)hipStreamSynchronize(n->stream);
-  for (void* p : n->owned) (void)hipFree(p);
+  for (void* p : n->owned) {
+    if (n->free_fn) n->free_fn(p, n->alloc_user);
+    else (void)hipFree(p);
+  }
   if (n->own_stream) (void)hipStreamDestroy(n->stream);
   delete n;
 }

@@ -71,7 +71,6 @@ struct pd_ctx {
   WallDev* walls = nullptr;
   double* wall_partial = nullptr;
   double* wall_chunk = nullptr;
-  uint32_t* fin_counter = nullptr;
   int64_t* box_chunks = nullptr;
   int32_t n_box_chunks = 0;
   int64_t* step_d = nullptr;
@@ -94,6 +93,7 @@ struct pd_ctx {
   int32_t *bucket_count = nullptr, *bucket_start = nullptr, *bucket_fill = nullptr,
           *cand_ptr = nullptr, *cand = nullptr;
   uint32_t* cellh = nullptr;
+  int64_t* grid = nullptr;  // [8] cell grid of the last rebuild
   double* u_build = nullptr;
   long long* gbox = nullptr;
   int32_t *gpair_count = nullptr, *gpair = nullptr;
@@ -126,7 +126,8 @@ struct pd_ctx {
   double* corner_gl = nullptr;  // Gauss-Legendre nodes and weights on [0, pi] (wall corners)
   uint32_t* corner_w = nullptr;  // [N]
   double* corner_c = nullptr;    // [3N]
-  uint32_t* mask = nullptr;  // [kMaskWords][N]
+  uint64_t* lmask = nullptr;  // [n_tiles * kTS][kTileClasses] lane masks of intact bonds
+  int32_t* slot = nullptr;    // [N] node -> (tile * kTS + wavefront) * 64 + lane
   std::vector<StencilC> stencil_h;  // host copy of the slice-path tables
   std::vector<int> sd_h;            // horizon offsets (dx, dy, dz) of the slice-path classes
   // captured step loop of graph_len steps
@@ -318,7 +319,6 @@ StepArgs step_args(pd_ctx* c) {
   A.walls = c->walls;
   A.wall_partial = c->wall_partial;
   A.wall_chunk = c->wall_chunk;
-  A.finalize_counter = c->fin_counter;
   A.step = c->step_d;
   A.advance = 1;
   A.status = c->status;
@@ -337,7 +337,8 @@ StepArgs step_args(pd_ctx* c) {
   A.tgrain = c->tgrain;
   A.tmap = c->tmap;
   A.ttab = c->ttab;
-  A.mask = c->mask;
+  A.lmask = c->lmask;
+  A.slot = c->slot;
   return A;
 }
 
@@ -368,6 +369,7 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   C.halt = c->halt;
   C.n = c->n;
   C.T = c->T;
+  C.grid = c->grid;
   C.capacity = c->capacity;
   const double cut = c->Rc + c->skin;
   C.inv_cell = 1.0 / (cut * 1.01);
@@ -630,6 +632,7 @@ pd_status build_tiles(pd_ctx* c) {
       koff[(size_t)g][(size_t)q] = (int64_t)kr;
     }
   }
+  std::vector<int32_t> slot_h((size_t)N, -1);
   // the boxes to tile: each grain's, or the shared one
   struct Box {
     int perm, lo[3], hi[3];  // lo/hi on the x, y, z axes of the box's lattice
@@ -702,20 +705,38 @@ pd_status build_tiles(pd_ctx* c) {
     map_total += (int64_t)T.es * T.em * T.ef;
     T.table = table_for(B.perm, B.cls);
     for (int32_t g : B.grains) tg[(size_t)g].table = T.table;
-    // tiles holding at least one node, in (s, m, f) tile order
+    // tiles holding at least one node, in (s, m, f) tile order, and each node's
+    // slot: (tile * kTS + its layer in the tile) * 64 + its lane
     const int nts = (T.es + kTS - 1) / kTS, ntm = (T.em + kTM - 1) / kTM, ntf = (T.ef + kTF - 1) / kTF;
-    std::vector<uint8_t> used((size_t)nts * ntm * ntf, 0);
+    std::vector<int64_t> tid((size_t)nts * ntm * ntf, -1);
+    auto node_cell = [&](int32_t g, int64_t i, int& cs, int& cm, int& cf) {
+      int x[3];
+      for (int q = 0; q < 3; ++q) x[q] = c->ijk_h[q * N + i] + tg[(size_t)g].goff[q];
+      cs = x[P[0]] - T.lo_s;
+      cm = x[P[1]] - T.lo_m;
+      cf = x[P[2]] - T.lo_f;
+    };
     for (int32_t g : B.grains)
       for (int64_t i = c->grain_begin[(size_t)g]; i < c->grain_begin[(size_t)g + 1]; ++i) {
-        int x[3];
-        for (int q = 0; q < 3; ++q) x[q] = c->ijk_h[q * N + i] + tg[(size_t)g].goff[q];
-        const int ts = (x[P[0]] - T.lo_s) / kTS, tm = (x[P[1]] - T.lo_m) / kTM, tf = (x[P[2]] - T.lo_f) / kTF;
-        used[((size_t)ts * ntm + tm) * ntf + tf] = 1;
+        int cs, cm, cf;
+        node_cell(g, i, cs, cm, cf);
+        tid[((size_t)(cs / kTS) * ntm + cm / kTM) * ntf + cf / kTF] = 0;
       }
     for (int ts = 0; ts < nts; ++ts)
       for (int tm = 0; tm < ntm; ++tm)
-        for (int tf = 0; tf < ntf; ++tf)
-          if (used[((size_t)ts * ntm + tm) * ntf + tf]) tiles.push_back(make_int4(r, ts * kTS, tm * kTM, tf * kTF));
+        for (int tf = 0; tf < ntf; ++tf) {
+          int64_t& id = tid[((size_t)ts * ntm + tm) * ntf + tf];
+          if (id < 0) continue;
+          id = (int64_t)tiles.size();
+          tiles.push_back(make_int4(r, ts * kTS, tm * kTM, tf * kTF));
+        }
+    for (int32_t g : B.grains)
+      for (int64_t i = c->grain_begin[(size_t)g]; i < c->grain_begin[(size_t)g + 1]; ++i) {
+        int cs, cm, cf;
+        node_cell(g, i, cs, cm, cf);
+        const int64_t id = tid[((size_t)(cs / kTS) * ntm + cm / kTM) * ntf + cf / kTF];
+        slot_h[(size_t)i] = (int32_t)((id * kTS + cs % kTS) * kWave + (cm % kTM) * kTF + cf % kTF);
+      }
   }
   for (int32_t g = 0; g < G; ++g) {
     rec[(size_t)g].perm = tg[(size_t)g].perm;
@@ -765,7 +786,11 @@ pd_status build_tiles(pd_ctx* c) {
   TRY(alloc_n(c, &c->tmap, std::max<int64_t>(map_total, 1), "tile cell map"));
   TRY(alloc_n(c, &c->ttab, std::max<int64_t>((int64_t)ttab.size(), 1), "tile bond tables"));
   TRY(alloc_n(c, &c->ctob, std::max<int64_t>((int64_t)ctob.size(), 1), "class to mask bit"));
-  TRY(alloc_n(c, &c->mask, std::max<int64_t>((int64_t)kMaskWords * N, 1), "class masks"));
+  if ((int64_t)tiles.size() * kTS * kWave >= ((int64_t)1 << 31))
+    return fail(c, PD_ERR_UNSUPPORTED, "%lld tiles exceed the 31-bit node slots", (long long)tiles.size());
+  TRY(alloc_n(c, &c->lmask, std::max<int64_t>((int64_t)tiles.size() * kTS * kTileClasses, 1), "lane masks"));
+  TRY(alloc_n(c, &c->slot, std::max<int64_t>(N, 1), "node slots"));
+  if (N) HIPCHK(c, hipMemcpyAsync(c->slot, slot_h.data(), sizeof(int32_t) * N, hipMemcpyHostToDevice, s));
   if (c->n_tiles)
     HIPCHK(c, hipMemcpyAsync(c->tiles, tiles.data(), sizeof(int4) * tiles.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->tgrain, rec.data(), sizeof(TileGrain) * rec.size(), hipMemcpyHostToDevice, s));
@@ -1024,7 +1049,6 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->step_d, 1, "step"));
   TRY(alloc_n(c, &c->status, 1, "status"));
   TRY(alloc_n(c, &c->halt, 1, "halt"));
-  TRY(alloc_n(c, &c->fin_counter, 1, "finalize counter"));
   if (mesh->fixed) TRY(alloc_n(c, &c->fixed, N, "fixed"));
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(c->X, mesh->X, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
@@ -1037,7 +1061,6 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   HIPCHK(c, hipMemsetAsync(c->step_d, 0, sizeof(int64_t), s));
   HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), s));
   HIPCHK(c, hipMemsetAsync(c->halt, 0, sizeof(uint32_t), s));
-  HIPCHK(c, hipMemsetAsync(c->fin_counter, 0, sizeof(uint32_t), s));
   if (mesh->v0)
     HIPCHK(c, hipMemcpyAsync(c->v, mesh->v0, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
   else
@@ -1238,6 +1261,7 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   TRY(alloc_n(c, &c->srec, N, "binned records"));
   TRY(alloc_n(c, &c->cand_scratch, (int64_t)c->scratch_w * N, "candidate scratch rows"));
   TRY(alloc_n(c, &c->cellh, N, "cell hashes"));
+  TRY(alloc_n(c, &c->grid, 8, "cell grid"));
   TRY(alloc_n(c, &c->bucket_count, T, "bucket counts"));
   TRY(alloc_n(c, &c->bucket_start, (int64_t)T + 1, "bucket starts"));
   TRY(alloc_n(c, &c->bucket_fill, T, "bucket fill"));

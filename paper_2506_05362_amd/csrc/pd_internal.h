@@ -59,8 +59,10 @@ constexpr int kCornerGL = 32;  // Gauss-Legendre points per piece of a wall-corn
 // ---- tiled bond loop (horizon factor 3): a workgroup owns a tile of
 // kTS x kTM x kTF lattice cells of one grain, in the grain's node-ordering axes
 // (s slowest, m, f fastest), and stages u of the tile plus a kTileR-cell halo in
-// LDS; the bond memory is a per-node bit mask over the 122 horizon classes in
-// lexicographic (ds, dm, df) order, the order of ascending neighbour index.
+// LDS.  The 122 horizon classes run in lexicographic (ds, dm, df) order, the
+// order of ascending neighbour index.  The bond memory is one 64-bit lane mask
+// per (wavefront of a tile, class): bit l says the bond of class K of the node
+// in lane l is intact, so the kernel tests and updates it in scalar registers.
 constexpr int kTileR = 3;
 #ifndef PD_TILE_LAYERS
 #define PD_TILE_LAYERS 8
@@ -69,7 +71,6 @@ constexpr int kTS = PD_TILE_LAYERS, kTM = 4, kTF = 16;  // one s-layer of 4 x 16
 constexpr int kHS = kTS + 2 * kTileR, kHM = kTM + 2 * kTileR, kHF = kTF + 2 * kTileR;
 constexpr int kHalo = kHS * kHM * kHF;      // 3080 cells, 73920 B of FP64 planes (8 layers)
 constexpr int kTileClasses = 122;           // 0 < |d|^2 <= 9
-constexpr int kMaskWords = 4;
 
 // A tile box: a grain's own lattice box, or (lattice mode) one box over every
 // grain when all of them share one lattice, spacing, bond table and node order.
@@ -144,7 +145,6 @@ struct StepArgs {
   WallDev* walls;
   double* wall_partial;  // [n_walls][3][partial_stride]: one column per slice (component-major)
   double* wall_chunk;    // [n_walls][3][chunks]: sums of 1024-column chunks of wall_partial
-  uint32_t* finalize_counter;  // arrivals at the wall finalize (zero between launches)
   int64_t* step;         // device step counter
   int32_t advance;       // 1 when this evaluation completes a step, 0 for the initial one
   uint32_t* status;
@@ -171,13 +171,14 @@ struct StepArgs {
   int32_t xcd_remap;     // 1: workgroup -> XCD-contiguous slice ranges
   // tiled bond loop (launch_step_tile): tile records (grain, s0, m0, f0), the
   // per-grain boxes and cell maps, bond tables and per-node class masks
-  // ([kMaskWords][n]); the tile kernel's wall partials use column kTS t + wave
+  // (lane masks); the tile kernel's wall partials use column kTS t + wave
   const int4* tiles;
   int64_t n_tiles;
   const TileGrain* tgrain;
   const int32_t* tmap;
   const StencilC* ttab;
-  uint32_t* mask;
+  uint64_t* lmask;        // [n_tiles * kTS][kTileClasses] lane masks of intact bonds
+  const int32_t* slot;    // [n]: node -> (tile * kTS + wavefront) * 64 + lane, or -1
   // self-contact inside a grain (Sec. 5): a same-grain candidate pair is
   // skipped while its bond is intact, found in the built column words (rows
   // sorted by neighbour) and, on the tiled path, the class masks through ctob
@@ -247,6 +248,12 @@ struct ContactArgs {
   const uint32_t* halt;   // nonzero: an earlier step raised a flag; leave the positions at rebuild alone
   int64_t n;
   uint32_t T;             // power of two
+  // cell grid of this rebuild (k_grid_setup): [0] 1 when the cells of the box
+  // around all nodes fit in T buckets, which are then the cells themselves in
+  // lexicographic order (neighbouring cells sit next to each other in memory);
+  // otherwise cells are hashed into the T buckets.  [1..3] the box's first
+  // cell, [4..6] its extent in cells.
+  int64_t* grid;
   int64_t capacity;
   double inv_cell;
   double cut2;            // (R_c + skin)^2

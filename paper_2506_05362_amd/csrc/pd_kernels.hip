@@ -499,8 +499,9 @@ __device__ __forceinline__ NodeVA load_va(const StepArgs& A, int64_t i, bool val
 // breaks?  The node's built entries are sorted by neighbour index, so a binary
 // search finds j's entry; a pair with no entry (outside the horizon, or cut)
 // has no bond.  The bond memory is the live column word on the slice path
-// (perm < 0) and, on the tiled path, the class-mask bit of the grain's axis
-// order perm (the tile kernel stores a node's masks before its tail).
+// (perm < 0) and, on the tiled path, the node's lane bit in the lane mask of
+// its class in the grain's axis order perm (the tile kernel stores a class's
+// mask as soon as a bond of it breaks, before any node's tail).
 __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j, int perm) {
   const uint32_t node_mask = (1u << A.node_bits) - 1u;
   const int64_t base = A.slice_off[i >> 6] + (i & 63);
@@ -517,7 +518,8 @@ __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j,
     } else {
       if (perm < 0) return A.colE[at] == wo;
       const int b = A.ctob[perm * A.n_stencil + (int)(wo >> A.node_bits)];
-      return ((A.mask[(int64_t)(b >> 5) * A.n + i] >> (b & 31)) & 1u) != 0u;
+      const int32_t sl = A.slot[i];
+      return ((A.lmask[(int64_t)(sl >> 6) * kTileClasses + b] >> (sl & 63)) & 1ull) != 0ull;
     }
   }
   return false;
@@ -848,7 +850,6 @@ constexpr int tile_class_off(int k) {
 }
 static_assert(tile_class_off(kTileClasses - 1) >= 0 && tile_class_off(kTileClasses) < 0,
               "horizon factor 3 has 122 classes");
-static_assert(kMaskWords * 32 >= kTileClasses, "class mask too short");
 static_assert((kHalo + tile_class_off(kTileClasses - 1)) * sizeof(double) <= 65535,
               "plane and class offsets must fit the LDS immediate offset");
 
@@ -863,11 +864,16 @@ typedef const __attribute__((address_space(4))) StencilC* TileTab;
 struct TileIn {
   double ux, uy, uz;
   double hx, hy, hz, thr, inv, civ;
+  uint64_t live;       // lanes whose bond of this class is intact
+  uint64_t live_next;  // the same for the next class, loaded a class earlier still
   const StencilC* rowp;
 };
 
+typedef const __attribute__((address_space(4))) uint64_t* MaskTab;
+
 template <int K>
-__device__ __forceinline__ void tile_load(const double* L, const double* Lz, const StencilC* tabp, TileIn& in) {
+__device__ __forceinline__ void tile_load(const double* L, const double* Lz, const StencilC* tabp,
+                                          const uint64_t* mrow, TileIn& in) {
   constexpr int off = tile_class_off(K);
   const StencilC* rowp = tabp + K;
   asm volatile("" : "+s"(rowp));
@@ -881,63 +887,90 @@ __device__ __forceinline__ void tile_load(const double* L, const double* Lz, con
   in.thr = row->thr_d;
   in.inv = row->inv_l0sq;
   in.civ = row->civ;
+  // lane masks travel two classes ahead: a wait for this class's operands then
+  // never waits for the mask as well
+  in.live = in.live_next;
+  if constexpr (K + 1 < kTileClasses) {
+    const uint64_t* mp = mrow + (K + 1);
+    asm volatile("" : "+s"(mp));
+    in.live_next = *(MaskTab)mp;
+  }
   in.rowp = rowp;
+}
+
+// a lane's x where its bit of the scalar lane mask m is set, else +0.0
+__device__ __forceinline__ double lanes_select(uint64_t m, double x) {
+  const uint64_t b = (uint64_t)__double_as_longlong(x);
+  uint32_t lo = (uint32_t)b, hi = (uint32_t)(b >> 32);
+  asm("v_cndmask_b32_e64 %0, 0, %0, %1" : "+v"(lo) : "s"(m));
+  asm("v_cndmask_b32_e64 %0, 0, %0, %1" : "+v"(hi) : "s"(m));
+  return __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
 }
 
 // One horizon class of the lane's node: the same arithmetic, in the same order,
 // as an entry of the slice path, so the two paths agree bitwise.  A class with
-// no bond (outside the grain, cut, or broken) adds an exact zero.  The
-// operands of class K arrived during class K - 1; once the first of them is
-// used (which waits for all of them) class K + 1's loads are issued, so that
-// they travel while class K computes.
+// no bond (outside the grain, another grain, cut, or broken) adds an exact
+// zero.  The operands of class K arrived during class K - 1; once the first of
+// them is used (which waits for all of them) class K + 1's loads are issued, so
+// that they travel while class K computes.  The class's lane mask of intact
+// bonds decides in scalar registers which lanes add a force, and loses the
+// lanes whose bond breaks now; a wavefront in which one breaks stores the mask
+// (lane 0) and counts the breaks per lane.
 template <int K, bool ABS>
-__device__ __forceinline__ void tile_bond(const double* L, const double* Lz, const StencilC* tabp, TileIn& in,
-                                          const PolyG& PG, double uix, double uiy, double uiz, double abs_ratio,
-                                          uint32_t (&mask)[kMaskWords], double& fx, double& fy, double& fz) {
-  constexpr int wd = K / 32;
-  constexpr uint32_t bit = 1u << (K % 32);
+__device__ __forceinline__ void tile_bond(const double* L, const double* Lz, const StencilC* tabp,
+                                          const uint64_t* mrow, uint64_t* mrow_w, TileIn& in, const PolyG& PG,
+                                          double uix, double uiy, double uiz, double abs_ratio, int& nbroke,
+                                          double& fx, double& fy, double& fz) {
   const double ex = in.ux - uix, ey = in.uy - uiy, ez = in.uz - uiz;
   const double hx = in.hx, hy = in.hy, hz = in.hz;
   const double yx = hx + ex, yy = hy + ey, yz = hz + ez;
   const double thr = in.thr, inv = in.inv, civ = in.civ;
+  const uint64_t live = in.live;
   const TileTab row = (TileTab)in.rowp;
   __builtin_amdgcn_sched_barrier(0);
-  if constexpr (K + 1 < kTileClasses) tile_load<K + 1>(L, Lz, tabp, in);
+  if constexpr (K + 1 < kTileClasses) tile_load<K + 1>(L, Lz, tabp, mrow, in);
   const double d = fma(ex, yx + hx, fma(ey, yy + hy, ez * (yz + hz)));
   bool over = d > thr;
   if (ABS) over = over || d < -abs_ratio * thr;
   const double x = d * inv;
   // the per-lane choice of the slice path (series, or the exact form past
-  // kPolyRange), the exact form computed only when some lane needs it
+  // kPolyRange), the exact form computed only when a lane with an intact bond
+  // needs it
   double g = x * one_minus_rsqrt1p_over_x(x, PG);
   const bool exact = !(fabs(x) <= kPolyRange);
-  if (__any(exact)) {
+  if ((__ballot(exact) & live) != 0ull) {
     const double lsq = row->l0sq + d;
     const double l = lsq * rsqrt_full(lsq);
     const double ge = d * rcp_full(fma(l, row->l0, lsq));
     g = exact ? ge : g;
   }
-  // a live bond within its limit adds its force, the others an exact zero (as
-  // in the slice path); a bond past its limit stays broken from now on
-  const bool live = (mask[wd] & bit) != 0u;
-  const double coef = (over || !live) ? 0.0 : civ * g;
+  // an intact bond within its limit adds its force, the others an exact zero
+  // (as in the slice path); a bond past its limit stays broken from now on
+  const uint64_t ov = __ballot(over);
+  const double coef = lanes_select(live & ~ov, civ * g);
   fx = fma(coef, yx, fx);
   fy = fma(coef, yy, fy);
   fz = fma(coef, yz, fz);
-  mask[wd] = over ? (mask[wd] & ~bit) : mask[wd];
+  const uint64_t brk = live & ov;
+  if (brk != 0ull) {
+    const int lane = __lane_id();
+    if (lane == 0) mrow_w[K] = live & ~ov;
+    nbroke += (int)((brk >> lane) & 1ull);
+  }
   // materialise the running sums here: left alone, the compiler sinks every
   // class's accumulation to the end and keeps all 122 classes' terms live
-  asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz), "+v"(mask[wd]));
+  asm volatile("" : "+v"(fx), "+v"(fy), "+v"(fz));
 }
 
 template <bool ABS, int... K>
 __device__ __forceinline__ void tile_bonds(std::integer_sequence<int, K...>, const double* L, const double* Lz,
-                                           const StencilC* tab, const PolyG& PG, double uix, double uiy, double uiz,
-                                           double abs_ratio, uint32_t (&mask)[kMaskWords], double& fx, double& fy,
-                                           double& fz) {
+                                           const StencilC* tab, const uint64_t* mrow, uint64_t* mrow_w,
+                                           const PolyG& PG, double uix, double uiy, double uiz, double abs_ratio,
+                                           int& nbroke, double& fx, double& fy, double& fz) {
   TileIn in;
-  tile_load<0>(L, Lz, tab, in);
-  (tile_bond<K, ABS>(L, Lz, tab, in, PG, uix, uiy, uiz, abs_ratio, mask, fx, fy, fz), ...);
+  in.live_next = *(MaskTab)mrow;
+  tile_load<0>(L, Lz, tab, mrow, in);
+  (tile_bond<K, ABS>(L, Lz, tab, mrow, mrow_w, in, PG, uix, uiy, uiz, abs_ratio, nbroke, fx, fy, fz), ...);
 }
 
 __device__ __forceinline__ int64_t tile_cell(const TileGrain& TG, int s, int m, int f) {
@@ -980,12 +1013,12 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   }
   const bool valid = i >= 0;
   double4 ui = make_double4(0.0, 0.0, 0.0, 0.0);
-  uint32_t mask[kMaskWords] = {0u, 0u, 0u, 0u};
-  if (valid) {
-    ui = A.ucur[i];
-#pragma unroll
-    for (int w = 0; w < kMaskWords; ++w) mask[w] = A.mask[(int64_t)w * A.n + i];
-  }
+  if (valid) ui = A.ucur[i];
+  // bring this wavefront's lane masks (122 x 8 B) into the L2 with the other
+  // prologue loads, so that the class loop's scalar loads of them hit there
+  const uint64_t* mrow_r = A.lmask + ((int64_t)t * kTS + wid) * kTileClasses;
+  uint4 mpre = make_uint4(0u, 0u, 0u, 0u);
+  if (lane < kTileClasses / 2) mpre = reinterpret_cast<const uint4*>(mrow_r)[lane];
   double hx_[kFill], hy_[kFill], hz_[kFill];
 #pragma unroll
   for (int r = 0; r < kFill; ++r) {
@@ -1015,18 +1048,14 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   const double* Lz = L + 2 * kHalo;  // own base: plane and class offsets must fit the 16-bit immediate
   double fx = 0.0, fy = 0.0, fz = 0.0;
   const StencilC* tab = A.ttab + (int64_t)TG.table * kTileClasses;
+  // this wavefront's lane masks, one per class
+  uint64_t* mrow_w = A.lmask + ((int64_t)t * kTS + wid) * kTileClasses;
   const PolyG PG = poly_in_registers();
-  int nbroke = 0;
-#pragma unroll
-  for (int w = 0; w < kMaskWords; ++w) nbroke += __popc(mask[w]);
-  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, PG, ui.x, ui.y, ui.z,
-                  G->abs_ratio, mask, fx, fy, fz);
-#pragma unroll
-  for (int w = 0; w < kMaskWords; ++w) nbroke -= __popc(mask[w]);  // bonds broken in this step
-  if (valid && nbroke) {
-#pragma unroll
-    for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = mask[w];
-  }
+  int nbroke = 0;  // bonds of this lane's node broken in this step
+  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, mrow_r, mrow_w, PG, ui.x, ui.y,
+                  ui.z, G->abs_ratio, nbroke, fx, fy, fz);
+  // the prefetch's data is not needed; consuming it keeps the load
+  asm volatile("" ::"v"(mpre.x ^ mpre.y ^ mpre.z ^ mpre.w));
   node_tail<MODE_STEP, EXTRA>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke,
                               true,
                        (int64_t)kTS * t + wid, load_va(A, i, valid), TG.perm);
@@ -1054,44 +1083,47 @@ __global__ void k_tile_map_fill(StepArgs A) {
   const_cast<int32_t*>(A.tmap)[tile_cell(B, s, m, f)] = (int32_t)i;
 }
 
-// node i's slice-path entries: bit ctob[perm][class] of the mask is set for
-// every built bond whose live column word is still the built one
+// node i's slice-path entries: its lane bit in the lane mask of tile class
+// ctob[perm][class] is set for every built bond whose live column word is still
+// the built one (the lane masks are cleared before)
 __global__ void k_cols_to_mask(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  const int64_t sl = i / kWave, lane = i % kWave;
-  const int64_t off = A.slice_off[sl];
-  const int W = (int)((A.slice_off[sl + 1] - off) / kWave);
+  const int32_t sl = A.slot[i];
+  if (sl < 0) return;
+  const int64_t sc = i / kWave, lane = i % kWave;
+  const int64_t off = A.slice_off[sc];
+  const int W = (int)((A.slice_off[sc + 1] - off) / kWave);
   const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
-  uint32_t m[kMaskWords] = {0u, 0u, 0u, 0u};
+  uint64_t* rowm = A.lmask + (int64_t)(sl >> 6) * kTileClasses;
+  const unsigned long long bit = 1ull << (sl & 63);
   for (int e = 0; e < W; ++e) {
     const int64_t at = off + (int64_t)e * kWave + lane;
     const uint32_t wo = colOrig[at];
     const int cls = (int)(wo >> A.node_bits);
     if (cls >= A.n_stencil || A.colE[at] != wo) continue;
-    const int b = ctob[perm * A.n_stencil + cls];
-    m[b >> 5] |= 1u << (b & 31);
+    atomicOr(reinterpret_cast<unsigned long long*>(rowm + ctob[perm * A.n_stencil + cls]), bit);
   }
-  for (int w = 0; w < kMaskWords; ++w) A.mask[(int64_t)w * A.n + i] = m[w];
 }
 
-// the inverse: an entry whose class bit is clear becomes a broken column word
+// the inverse: an entry whose lane bit is clear becomes a broken column word
 __global__ void k_mask_to_cols(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= A.n) return;
-  const int64_t sl = i / kWave, lane = i % kWave;
-  const int64_t off = A.slice_off[sl];
-  const int W = (int)((A.slice_off[sl + 1] - off) / kWave);
+  const int32_t sl = A.slot[i];
+  if (sl < 0) return;
+  const int64_t sc = i / kWave, lane = i % kWave;
+  const int64_t off = A.slice_off[sc];
+  const int W = (int)((A.slice_off[sc + 1] - off) / kWave);
   const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
-  uint32_t m[kMaskWords];
-  for (int w = 0; w < kMaskWords; ++w) m[w] = A.mask[(int64_t)w * A.n + i];
+  const uint64_t* rowm = A.lmask + (int64_t)(sl >> 6) * kTileClasses;
   for (int e = 0; e < W; ++e) {
     const int64_t at = off + (int64_t)e * kWave + lane;
     const uint32_t wo = colOrig[at];
     const int cls = (int)(wo >> A.node_bits);
     if (cls >= A.n_stencil) continue;
-    const int b = ctob[perm * A.n_stencil + cls];
-    A.colE[at] = ((m[b >> 5] >> (b & 31)) & 1u) ? wo : ((uint32_t)i | A.sentinel_hi);
+    const uint64_t m = rowm[ctob[perm * A.n_stencil + cls]];
+    A.colE[at] = ((m >> (sl & 63)) & 1ull) ? wo : ((uint32_t)i | A.sentinel_hi);
   }
 }
 
@@ -1195,36 +1227,28 @@ __device__ __forceinline__ void finalize_level2(const StepArgs& A, double (*red)
   }
 }
 
-// One wavefront per (component, chunk) pair computes level (1); the last one to
-// finish (device-scope counter) runs level (2) and the wall update, then resets
-// the counter.  The fences make the chunk sums of every XCD visible to it.
-__global__ __launch_bounds__(kWave) void k_wall_finalize(StepArgs A, uint32_t* counter) {
+// Level (1): one wavefront per (component, chunk) pair.  Level (2) and the
+// wall update run in the next kernel, whose start sees every chunk sum (a
+// kernel boundary instead of a device-scope fence per workgroup).
+__global__ __launch_bounds__(kWave) void k_wall_chunks(StepArgs A) {
+  const int nc = 3 * A.n_walls;
+  const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
+  if ((int64_t)blockIdx.x >= (int64_t)nc * nq) return;
+  const int c = (int)(blockIdx.x / nq);
+  const int64_t q = blockIdx.x % nq;
+  const double t = chunk_sum(A, c, q);
+  if (threadIdx.x == 0) A.wall_chunk[(int64_t)c * nq + q] = t;
+}
+
+__global__ __launch_bounds__(kWave) void k_wall_finalize(StepArgs A) {
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
-  __shared__ uint32_t last;
-  const int nc = 3 * A.n_walls;
-  const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
-  const int64_t pairs = (int64_t)nc * nq;
-  if ((int64_t)blockIdx.x < pairs) {
-    const int c = (int)(blockIdx.x / nq);
-    const int64_t q = blockIdx.x % nq;
-    const double t = chunk_sum(A, c, q);
-    if (threadIdx.x == 0) A.wall_chunk[(int64_t)c * nq + q] = t;
-  }
-  if (threadIdx.x == 0) {
-    __threadfence();
-    last = atomicAdd(counter, 1u) == gridDim.x - 1u ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!last) return;
-  __threadfence();
   finalize_level2<kWave>(A, red, tot, &s_step);
   if (threadIdx.x == 0) {
     // the last kernel of the step: the next step halts if this one raised a flag
     __hip_atomic_store(A.halt, __hip_atomic_load(A.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                        __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    atomicExch(counter, 0u);
   }
 }
 
@@ -1509,6 +1533,48 @@ __global__ void k_active(ContactArgs c, double cut) {
   c.active[i] = act;
 }
 
+// The cell grid of this rebuild: the box around every node's position (the
+// union of the grain boxes), in cells; dense when its cell count fits the
+// buckets.  One wavefront.
+__global__ __launch_bounds__(kWave) void k_grid_setup(ContactArgs c) {
+  const int lane = threadIdx.x;
+  double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+  for (int g = lane; g < c.n_grains; g += kWave)
+    for (int q = 0; q < 3; ++q) {
+      const double a = ord_val(c.gbox[6 * g + q]), b = ord_val(c.gbox[6 * g + 3 + q]);
+      if (a <= b) {  // grains without nodes keep an empty box
+        lo[q] = fmin(lo[q], a);
+        hi[q] = fmax(hi[q], b);
+      }
+    }
+  for (int q = 0; q < 3; ++q)
+    for (int o = 32; o > 0; o >>= 1) {
+      lo[q] = fmin(lo[q], __shfl_xor(lo[q], o, kWave));
+      hi[q] = fmax(hi[q], __shfl_xor(hi[q], o, kWave));
+    }
+  if (lane != 0) return;
+  int64_t dense = 1, cells = 1, o[3], e[3];
+  for (int q = 0; q < 3; ++q) {
+    if (!(lo[q] <= hi[q])) dense = 0;
+    o[q] = dense ? cell_coord(lo[q], c.inv_cell) : 0;
+    e[q] = dense ? cell_coord(hi[q], c.inv_cell) - o[q] + 1 : 1;
+    cells *= e[q];
+  }
+  if (cells > (int64_t)c.T) dense = 0;
+  c.grid[0] = dense;
+  for (int q = 0; q < 3; ++q) {
+    c.grid[1 + q] = o[q];
+    c.grid[4 + q] = e[q];
+  }
+}
+
+// bucket of a cell: its lexicographic index in the dense grid, else its hash
+__device__ __forceinline__ uint32_t cell_bucket(const ContactArgs& c, bool dense, int cx, int cy, int cz) {
+  if (dense)
+    return (uint32_t)(((int64_t)(cx - c.grid[1]) * c.grid[5] + (cy - c.grid[2])) * c.grid[6] + (cz - c.grid[3]));
+  return cell_hash(cx, cy, cz, c.T);
+}
+
 __global__ void k_bin(ContactArgs c) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= c.n || !c.active[i]) return;
@@ -1517,7 +1583,7 @@ __global__ void k_bin(ContactArgs c) {
   const int cy = cell_coord(c.X[c.n + i] + u.y, c.inv_cell);
   const int cz = cell_coord(c.X[2 * c.n + i] + u.z, c.inv_cell);
   c.cellkey[i] = cell_key(cx, cy, cz);
-  const uint32_t hsh = cell_hash(cx, cy, cz, c.T);
+  const uint32_t hsh = cell_bucket(c, c.grid[0] != 0, cx, cy, cz);
   c.cellh[i] = hsh;
   atomicAdd(c.bucket_count + hsh, 1);
 }
@@ -1535,9 +1601,26 @@ __global__ void k_scatter(ContactArgs c) {
 // load (node, grain, cell key); records of other cells sharing the bucket and
 // of the node's own grain are skipped before any position is read.  Threads
 // walk the binned nodes in bucket order, so the nodes of one cell sit in
-// neighbouring lanes and read the same buckets.  Hits go to a fixed-width
-// scratch row; counts beyond the width raise the overflow flag.  Rows of
-// nodes that were not binned stay at zero (cleared before the launch).
+// neighbouring lanes and read the same buckets.  In a dense grid the three
+// cells of a z-run are consecutive buckets, read as one range (and hold no
+// other cells).  Hits go to a fixed-width scratch row; counts beyond the width
+// raise the overflow flag.  Rows of nodes that were not binned stay at zero
+// (cleared before the launch).
+__device__ __forceinline__ void cand_consider(const ContactArgs& c, const int4& r, int64_t i, int gi, double Xx,
+                                              double Xy, double Xz, const double4& ui, int32_t* row, int& cnt) {
+  // with self-contact the node's own grain counts too (whether a pair is
+  // bonded is decided at the force, from the bond memory)
+  if (r.y == gi && (!c.self_contact || r.x == i)) return;
+  const int j = r.x;
+  const double4 uj = c.u[j];
+  double yx, yy, yz;
+  const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y, c.X[2 * c.n + j], Xz, uj.z,
+                               ui.z, yx, yy, yz);
+  if (!(d2 < c.cut2)) return;
+  if (cnt < c.scratch_w) row[cnt] = j;
+  ++cnt;
+}
+
 __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
   const int64_t e0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e0 >= c.bucket_start[c.T]) return;
@@ -1552,25 +1635,29 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
   const double Xx = c.X[i], Xy = c.X[c.n + i], Xz = c.X[2 * c.n + i];
   int32_t* row = c.cand_scratch + i * (int64_t)c.scratch_w;
   int cnt = 0;
-  for (int d = 0; d < kCellDirs; ++d) {
-    const int nx = cx + d % 3 - 1, ny = cy + (d / 3) % 3 - 1, nz = cz + d / 9 - 1;
-    const long long nkey = cell_key(nx, ny, nz);
-    const int klo = (int)(nkey & 0xffffffffll), khi = (int)(nkey >> 32);
-    const uint32_t hsh = cell_hash(nx, ny, nz, c.T);
-    const int e1 = c.bucket_start[hsh + 1];
-    for (int e = c.bucket_start[hsh]; e < e1; ++e) {
-      const int4 r = c.srec[e];
-      // with self-contact the node's own grain counts too (whether a pair is
-      // bonded is decided at the force, from the bond memory)
-      if (r.z != klo || r.w != khi || (r.y == gi && (!c.self_contact || r.x == i))) continue;
-      const int j = r.x;
-      const double4 uj = c.u[j];
-      double yx, yy, yz;
-      const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y,
-                                   c.X[2 * c.n + j], Xz, uj.z, ui.z, yx, yy, yz);
-      if (!(d2 < c.cut2)) continue;
-      if (cnt < c.scratch_w) row[cnt] = j;
-      ++cnt;
+  if (c.grid[0]) {
+    const int64_t ex = c.grid[4], ey = c.grid[5], ez = c.grid[6];
+    const int64_t lx = cx - c.grid[1], ly = cy - c.grid[2], lz = cz - c.grid[3];
+    const int64_t z0 = lz > 0 ? lz - 1 : 0, z1 = lz + 1 < ez ? lz + 1 : ez - 1;
+    for (int d = 0; d < 9; ++d) {
+      const int64_t nx = lx + d / 3 - 1, ny = ly + d % 3 - 1;
+      if (nx < 0 || ny < 0 || nx >= ex || ny >= ey) continue;
+      const int64_t b = (nx * ey + ny) * ez;
+      const int e1 = c.bucket_start[b + z1 + 1];
+      for (int e = c.bucket_start[b + z0]; e < e1; ++e) cand_consider(c, c.srec[e], i, gi, Xx, Xy, Xz, ui, row, cnt);
+    }
+  } else {
+    for (int d = 0; d < kCellDirs; ++d) {
+      const int nx = cx + d % 3 - 1, ny = cy + (d / 3) % 3 - 1, nz = cz + d / 9 - 1;
+      const long long nkey = cell_key(nx, ny, nz);
+      const int klo = (int)(nkey & 0xffffffffll), khi = (int)(nkey >> 32);
+      const uint32_t hsh = cell_hash(nx, ny, nz, c.T);
+      const int e1 = c.bucket_start[hsh + 1];
+      for (int e = c.bucket_start[hsh]; e < e1; ++e) {
+        const int4 r = c.srec[e];
+        if (r.z != klo || r.w != khi) continue;  // another cell in the same bucket
+        cand_consider(c, r, i, gi, Xx, Xy, Xz, ui, row, cnt);
+      }
     }
   }
   if (cnt > c.scratch_w) {
@@ -1769,8 +1856,9 @@ int32_t step_grid_blocks(int64_t nslices) { return step_blocks_spb(nslices, kSli
 
 hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s) {
   const int64_t nq = (a.partial_stride + kChunk - 1) / kChunk;
-  const int64_t pairs = std::max<int64_t>((int64_t)(3 * a.n_walls) * nq, 1);
-  hipLaunchKernelGGL(k_wall_finalize, dim3((unsigned)pairs), dim3(kWave), 0, s, a, a.finalize_counter);
+  const int64_t pairs = (int64_t)(3 * a.n_walls) * nq;
+  if (pairs > 0) hipLaunchKernelGGL(k_wall_chunks, dim3((unsigned)pairs), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(kWave), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1856,6 +1944,7 @@ hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStrea
   if ((e = scan_i32(c.gpair_count, c.gpair_count, c.n_grains, c.scan_scratch, s)) != hipSuccess) return e;
   hipLaunchKernelGGL(k_box_pairs<true>, dim3(gg), dim3(kWave), 0, s, c, cut);
   hipLaunchKernelGGL(k_active, dim3(g), dim3(256), 0, s, c, cut);
+  hipLaunchKernelGGL(k_grid_setup, dim3(1), dim3(kWave), 0, s, c);
   hipLaunchKernelGGL(k_bin, dim3(g), dim3(256), 0, s, c);
   if ((e = scan_i32(c.bucket_count, c.bucket_start, (int64_t)c.T, c.scan_scratch, s)) != hipSuccess)
     return e;
@@ -1909,6 +1998,8 @@ hipError_t launch_tile_map_fill(const StepArgs& a, hipStream_t s) {
 
 hipError_t launch_cols_to_mask(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig, hipStream_t s) {
   if (a.n == 0) return hipSuccess;
+  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(a.lmask), 0, 2 * a.n_tiles * kTS * kTileClasses, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_cols_to_mask, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, ctob, colOrig);
   return hipGetLastError();
 }

@@ -25,7 +25,8 @@ def load_library(path: str = _LIB_PATH) -> C.CDLL:
         raise RuntimeError(f"HIP library {path} is not built; run __graft_entry__.build()")
     import torch  # noqa: F401  (bind to PyTorch's HIP runtime, see pd.py)
     L = C.CDLL(path)
-    L.pdm_create.argtypes = [C.POINTER(P), P, C.c_int32, C.c_int64, P]
+    from .pd import ALLOC_FN, FREE_FN
+    L.pdm_create.argtypes = [C.POINTER(P), P, C.c_int32, C.c_int64, ALLOC_FN, FREE_FN, P, P]
     L.pdm_param_count.argtypes = [P]
     L.pdm_param_count.restype = C.c_int64
     L.pdm_set_params.argtypes = [P, P, C.c_int64]
@@ -80,8 +81,24 @@ class Net:
         self.stream = stream if stream is not None else torch.cuda.Stream()
         d = np.array(self.dims, dtype=np.int32)
         h = P()
+        # device buffers come from PyTorch's caching allocator, on this network's stream
+        from .pd import ALLOC_FN, FREE_FN
+        dev = torch.cuda.current_device()
+
+        def _alloc(nbytes, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, self.stream)
+            except Exception:  # out of memory -> NULL -> PD_ERR_OOM
+                return None
+
+        def _free(ptr, user):
+            cuda = getattr(torch, "cuda", None)
+            if cuda is not None:
+                cuda.caching_allocator_delete(int(ptr))
+
+        self._alloc, self._free = ALLOC_FN(_alloc), FREE_FN(_free)
         st = lib().pdm_create(C.byref(h), d.ctypes.data_as(P), len(self.dims), int(max_batch),
-                              P(self.stream.cuda_stream))
+                              self._alloc, self._free, None, P(self.stream.cuda_stream))
         self.h = h
         _LIVE.add(self)
         self.max_batch = int(max_batch)

@@ -371,9 +371,12 @@ def time_inference(sur: Surrogate, paths: np.ndarray, reps: int = 3) -> Dict:
 # contact damping at about half the critical value of a node pair (h = 70 um)
 # lets grain rattling decay, so the logged stress is a quasi-static response.
 # The servo gain caps the lateral walls' speed near the platen's (gain * 20 MPa
-# = 1 m/s) and candidate lists are rebuilt every 10 steps.
+# = 1 m/s).  Paths run to 5% axial strain, well past the peak; candidate lists
+# are rebuilt every 10 steps with a skin of h/2, so a node may move at up to
+# 250 m/s between rebuilds (past the peak single detached nodes are thrown off
+# faster than the 125 m/s an h/4 skin allows).
 RVE_DEFAULTS = dict(platen_speed=1.0, contact_damping=2.8e22, servo_gain=5e-8, rebuild_every=10,
-                    axial_strain=0.025)
+                    axial_strain=0.05, skin_factor=0.5)
 
 
 def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int = 4000,
