@@ -37,6 +37,9 @@ from . import inputs as I
 DIMS = [6, 256, 256, 256, 7]
 OUT_NAMES = ["s_xx", "s_yy", "s_zz", "s_yz", "s_xz", "s_xy", "damage"]
 AXIAL = 2  # index of s_zz
+# Contact candidates per node the simulations reserve: past the peak, crushed
+# grains pack fragments within R_c + skin of a node from several sides.
+SIM_CAPACITY = 48
 
 
 @dataclasses.dataclass
@@ -69,7 +72,7 @@ def _axis_walls(wl) -> List[tuple]:
     return pairs
 
 
-def simulate_path(wl, n_log: int = 400, log=None) -> Dict[str, np.ndarray]:
+def simulate_path(wl, n_log: int = 400, log=None, capacity: int = SIM_CAPACITY) -> Dict[str, np.ndarray]:
     """Run a confined-compression workload and log strain, stress and damage.
 
     Returns strain (T, 6), target (T, 7) = stress and damage, t (T,), the
@@ -85,7 +88,11 @@ def simulate_path(wl, n_log: int = 400, log=None) -> Dict[str, np.ndarray]:
     normals = np.array([w.normal for w in wl.walls], dtype=np.float64)
     areas = np.array([w.area for w in wl.walls], dtype=np.float64)
     t0 = time.perf_counter()
-    sim = pd.Sim(wl)
+    sim = pd.Sim(wl, candidate_capacity_per_node=capacity)
+    try:  # the tessellated volume shares one lattice: the tiled bond loop covers it in one box
+        sim.set_launch(bond_path=pd.BONDS_TILES)
+    except pd.PDError:
+        pass
     nnz = sim.info()["nnz"]
     dmg = torch.empty(wl.n_nodes, dtype=torch.float64, device="cuda")
     off0 = sim.get("wall_offset")
