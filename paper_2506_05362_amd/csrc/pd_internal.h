@@ -67,7 +67,14 @@ constexpr int kTileR = 3;
 #ifndef PD_TILE_LAYERS
 #define PD_TILE_LAYERS 8
 #endif
-constexpr int kTS = PD_TILE_LAYERS, kTM = 4, kTF = 16;  // one s-layer of 4 x 16 cells per wavefront
+#ifndef PD_TILE_M
+#define PD_TILE_M 4
+#endif
+#ifndef PD_TILE_F
+#define PD_TILE_F 16
+#endif
+constexpr int kTS = PD_TILE_LAYERS, kTM = PD_TILE_M, kTF = PD_TILE_F;  // one s-layer of kTM x kTF cells per wavefront
+static_assert(kTM * kTF == kWave, "a wavefront holds one layer of a tile");
 constexpr int kHS = kTS + 2 * kTileR, kHM = kTM + 2 * kTileR, kHF = kTF + 2 * kTileR;
 constexpr int kHalo = kHS * kHM * kHF;      // 3080 cells, 73920 B of FP64 planes (8 layers)
 constexpr int kTileClasses = 122;           // 0 < |d|^2 <= 9

@@ -1030,9 +1030,6 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
       hz_[r] = u.z;
     }
   }
-  // the node's velocity and acceleration, needed only by the tail: issued
-  // behind the halo's loads, so that they travel with them
-  const NodeVA va = load_va(A, i, valid);
 #pragma unroll
   for (int r = 0; r < kFill; ++r) {
     const int c = tid + r * kNT;
@@ -1045,9 +1042,6 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   // the lane's own grain (in lattice mode a tile holds nodes of several grains)
   const GrainC* G = A.grains + (valid ? packed_grain(ui.w) : 0);
   const int pi = packed_ijk(ui.w);
-  // v and a arrived with the halo; holding them here keeps the compiler from
-  // moving their loads behind the bond loop
-  asm volatile("" ::"v"(va.vx), "v"(va.vy), "v"(va.vz), "v"(va.ax), "v"(va.ay), "v"(va.az));
   __syncthreads();
 
   const double* L = s_u + (wid * kHM + lm) * kHF + lf;
@@ -1063,7 +1057,7 @@ __global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
   // the prefetch's data is not needed; consuming it keeps the load
   asm volatile("" ::"v"(mpre.x ^ mpre.y ^ mpre.z ^ mpre.w));
   node_tail<MODE_STEP, EXTRA>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke,
-                              true, (int64_t)kTS * t + wid, va, TG.perm);
+                              true, (int64_t)kTS * t + wid, load_va(A, i, valid), TG.perm);
 }
 
 // the six orders of the lattice axes (slowest first)
