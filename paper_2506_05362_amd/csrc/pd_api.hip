@@ -113,6 +113,9 @@ struct pd_ctx {
   int64_t pg_cols = 0;  // wall-partial columns of the per-grain launches (shared slices twice)
   int64_t partial_cols = 0;  // columns allocated in wall_partial
   uint32_t* barrier = nullptr;  // [2]: arrival count, generation
+  std::vector<int64_t> slice_off_h;  // host copy of the padded slot offsets of the slices
+  int64_t* pers_ranges = nullptr;    // [pers_ranges_n + 1] 4-slice block runs of the persistent workgroups
+  int32_t pers_ranges_n = 0;
   // tiled bond loop (PD_BONDS_TILES): available when the horizon factor is 3
   // and every grain's nodes are in lexicographic order of some axis order
   int tile_ok = 0;
@@ -435,9 +438,27 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
   const int32_t maxb = persistent_max_blocks(A);
   if (maxb <= 0) return fail(c, PD_ERR_HIP, "no resident workgroups for the persistent step kernel");
   const int32_t nb = c->launch.persistent_blocks > 0 ? std::min(c->launch.persistent_blocks, maxb) : maxb;
+  if (c->pers_ranges_n != nb) {
+    // merge-path over the padded slots: workgroup r starts at the first 4-slice
+    // block whose slots before it reach r / nb of the total
+    const int64_t nv = (c->nslices + 3) / 4, total = c->slice_off_h[(size_t)c->nslices];
+    std::vector<int64_t> rr((size_t)nb + 1);
+    int64_t vb = 0;
+    for (int32_t r = 0; r <= nb; ++r) {
+      const int64_t target = r == nb ? total + 1 : (int64_t)((__int128)total * r / nb);
+      while (vb < nv && c->slice_off_h[(size_t)std::min<int64_t>(4 * vb, c->nslices)] < target) ++vb;
+      rr[(size_t)r] = r == nb ? nv : vb;
+    }
+    if (c->pers_ranges) dev_free(c, c->pers_ranges);
+    c->pers_ranges = nullptr;
+    TRY(alloc_n(c, &c->pers_ranges, (int64_t)nb + 1, "persistent ranges"));
+    HIPCHK(c, hipMemcpyAsync(c->pers_ranges, rr.data(), sizeof(int64_t) * rr.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->pers_ranges_n = nb;
+  }
   BarrierArgs B{c->barrier, c->barrier + 1, 1u << 24};
   if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
-  HIPCHK(c, launch_step_persistent(A, k, nb, B, c->stream));
+  HIPCHK(c, launch_step_persistent(A, k, nb, c->pers_ranges, B, c->stream));
   if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
   if ((k - 1) & 1) c->cur ^= 1;  // the kernel flipped the buffers k - 1 more times
   *done = k;
@@ -1226,8 +1247,11 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   HIPCHK(c, launch_bond_count(B, s));
   HIPCHK(c, launch_slice_width(B, s));
   HIPCHK(c, scan_i64(c->slice_off, c->slice_off, c->nslices, scan_scratch64, s));
-  HIPCHK(c, hipMemcpyAsync(&c->padded, c->slice_off + c->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  c->slice_off_h.assign((size_t)c->nslices + 1, 0);
+  HIPCHK(c, hipMemcpyAsync(c->slice_off_h.data(), c->slice_off, sizeof(int64_t) * (c->nslices + 1),
+                           hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
+  c->padded = c->slice_off_h[(size_t)c->nslices];
   TRY(alloc_n(c, &c->colE, c->padded, "bond columns"));
   TRY(alloc_n(c, &c->colOrig, c->padded, "bond columns as built"));
   B.colE = c->colE;

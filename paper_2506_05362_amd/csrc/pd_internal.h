@@ -282,9 +282,10 @@ hipError_t launch_wall_corners(const StepArgs& a, int force_only, hipStream_t s)
 hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 // nsteps steps with no rebuild in between, one cooperative launch of nblocks
-// workgroups (4 slices each) that loop over the slices with a grid barrier
-// between steps
-hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks,
+// workgroups; workgroup r (in XCD order) runs the 4-slice blocks
+// [ranges[r], ranges[r + 1]), cut so that each run holds about the same number
+// of padded bond slots
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const int64_t* ranges,
                                   const BarrierArgs& b, hipStream_t s);
 // workgroups of the persistent kernel that fit on the device at once
 int32_t persistent_max_blocks(const StepArgs& a);

@@ -1082,26 +1082,39 @@ __global__ void k_tile_map_fill(StepArgs A) {
   const_cast<int32_t*>(A.tmap)[tile_cell(B, s, m, f)] = (int32_t)i;
 }
 
-// node i's slice-path entries: its lane bit in the lane mask of tile class
-// ctob[perm][class] is set for every built bond whose live column word is still
-// the built one (the lane masks are cleared before)
-__global__ void k_cols_to_mask(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= A.n) return;
-  const int32_t sl = A.slot[i];
-  if (sl < 0) return;
-  const int64_t sc = i / kWave, lane = i % kWave;
-  const int64_t off = A.slice_off[sc];
-  const int W = (int)((A.slice_off[sc + 1] - off) / kWave);
-  const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
-  uint64_t* rowm = A.lmask + (int64_t)(sl >> 6) * kTileClasses;
-  const unsigned long long bit = 1ull << (sl & 63);
-  for (int e = 0; e < W; ++e) {
-    const int64_t at = off + (int64_t)e * kWave + lane;
-    const uint32_t wo = colOrig[at];
-    const int cls = (int)(wo >> A.node_bits);
-    if (cls >= A.n_stencil || A.colE[at] != wo) continue;
-    atomicOr(reinterpret_cast<unsigned long long*>(rowm + ctob[perm * A.n_stencil + cls]), bit);
+// Lane masks from the column words: one wavefront per layer of a tile, lane l
+// on the cell it owns in the step kernel.  Each lane gathers its node's live
+// built bonds as tile-class bits (class ctob[perm][slice class]); a ballot per
+// class forms the wavefront's mask.
+__global__ __launch_bounds__(256) void k_cols_to_mask(StepArgs A, const int16_t* ctob, const uint32_t* colOrig) {
+  const int64_t wv = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  if (wv >= A.n_tiles * kTS) return;  // whole wavefronts leave together
+  const int lane = threadIdx.x & 63;
+  const int64_t t = wv / kTS;
+  const int w = (int)(wv % kTS);
+  const int4 T = A.tiles[t];
+  const TileGrain TG = A.tgrain[T.x];
+  const int cs = T.y + w, cm = T.z + lane / kTF, cf = T.w + lane % kTF;
+  const int64_t i = (cs < TG.es && cm < TG.em && cf < TG.ef) ? (int64_t)A.tmap[tile_cell(TG, cs, cm, cf)] : -1;
+  uint32_t m[4] = {0u, 0u, 0u, 0u};
+  if (i >= 0) {
+    const int64_t sc = i / kWave, sl = i % kWave;
+    const int64_t off = A.slice_off[sc];
+    const int W = (int)((A.slice_off[sc + 1] - off) / kWave);
+    const int perm = A.tgrain[packed_grain(A.ucur[i].w)].perm;
+    for (int e = 0; e < W; ++e) {
+      const int64_t at = off + (int64_t)e * kWave + sl;
+      const uint32_t wo = colOrig[at];
+      const int cls = (int)(wo >> A.node_bits);
+      if (cls >= A.n_stencil || A.colE[at] != wo) continue;
+      const int b = ctob[perm * A.n_stencil + cls];
+      m[b >> 5] |= 1u << (b & 31);
+    }
+  }
+  uint64_t* row = A.lmask + wv * kTileClasses;
+  for (int K = 0; K < kTileClasses; ++K) {
+    const uint64_t bits = __ballot(((m[K >> 5] >> (K & 31)) & 1u) != 0u);
+    if (lane == 0) row[K] = bits;
   }
 }
 
@@ -1239,11 +1252,13 @@ __global__ __launch_bounds__(kWave) void k_wall_chunks(StepArgs A) {
   if (threadIdx.x == 0) A.wall_chunk[(int64_t)c * nq + q] = t;
 }
 
-__global__ __launch_bounds__(kWave) void k_wall_finalize(StepArgs A) {
+// 1024 threads: level (2) is written for 1024 virtual threads, so each takes
+// one of them (the sums are the same for any workgroup size)
+__global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A) {
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
-  finalize_level2<kWave>(A, red, tot, &s_step);
+  finalize_level2<1024>(A, red, tot, &s_step);
   if (threadIdx.x == 0) {
     // the last kernel of the step: the next step halts if this one raised a flag
     __hip_atomic_store(A.halt, __hip_atomic_load(A.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
@@ -1285,18 +1300,19 @@ __device__ __forceinline__ void grid_barrier(const BarrierArgs& B, uint32_t nblo
 
 template <bool ABS>
 __global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(kUnroll > 4 ? 3 : 4)))
-void k_step_persistent(StepArgs A, int64_t nsteps, int64_t nvblocks, BarrierArgs B) {
+void k_step_persistent(StepArgs A, int64_t nsteps, const int64_t* ranges, BarrierArgs B) {
   extern __shared__ StencilC s_st[];
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
   if (halted(A.halt)) return;
   stage_stencil(A, s_st);
+  // this workgroup's run of 4-slice blocks, cut at equal padded-slot counts;
+  // with the XCD order, neighbouring runs go to one XCD
+  const int64_t r = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+  const int64_t vb0 = ranges[r], vb1 = ranges[r + 1];
   for (int64_t k = 0; k < nsteps; ++k) {
-    for (int64_t vb = blockIdx.x; vb < nvblocks; vb += gridDim.x) {
-      const int64_t blk = A.xcd_remap ? xcd_remap(vb, nvblocks) : vb;
-      step_body<MODE_STEP, ABS, 4>(A, s_st, blk);
-    }
+    for (int64_t vb = vb0; vb < vb1; ++vb) step_body<MODE_STEP, ABS, 4>(A, s_st, vb);
     grid_barrier(B, gridDim.x, A.status);
     if (blockIdx.x == 0) {
       // level (1) by this workgroup's wavefronts, then level (2)
@@ -1857,7 +1873,7 @@ hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s) {
   const int64_t nq = (a.partial_stride + kChunk - 1) / kChunk;
   const int64_t pairs = (int64_t)(3 * a.n_walls) * nq;
   if (pairs > 0) hipLaunchKernelGGL(k_wall_chunks, dim3((unsigned)pairs), dim3(kWave), 0, s, a);
-  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(kWave), 0, s, a);
+  hipLaunchKernelGGL(k_wall_finalize, dim3(1), dim3(1024), 0, s, a);
   return hipGetLastError();
 }
 
@@ -1911,14 +1927,14 @@ int32_t persistent_max_blocks(const StepArgs& a) {
   return per_cu * cus;
 }
 
-hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks,
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const int64_t* ranges,
                                   const BarrierArgs& b, hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
-  int64_t nv = step_blocks_spb(a.slice_end - a.slice_base, 4);
-  if (nv == 0) return hipSuccess;
+  if (step_blocks_spb(a.slice_end - a.slice_base, 4) == 0) return hipSuccess;
   StepArgs aa = a;
   BarrierArgs bb = b;
-  void* args[] = {&aa, &nsteps, &nv, &bb};
+  const int64_t* rr = ranges;
+  void* args[] = {&aa, &nsteps, &rr, &bb};
   const void* fn = a.abs_stretch ? reinterpret_cast<const void*>(&k_step_persistent<true>)
                                  : reinterpret_cast<const void*>(&k_step_persistent<false>);
   // a cooperative launch fails rather than start more workgroups than can be
@@ -1996,10 +2012,8 @@ hipError_t launch_tile_map_fill(const StepArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_cols_to_mask(const StepArgs& a, const int16_t* ctob, const uint32_t* colOrig, hipStream_t s) {
-  if (a.n == 0) return hipSuccess;
-  hipError_t e = launch_fill_i32(reinterpret_cast<int32_t*>(a.lmask), 0, 2 * a.n_tiles * kTS * kTileClasses, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(k_cols_to_mask, dim3(grid_for(a.n, 256)), dim3(256), 0, s, a, ctob, colOrig);
+  if (a.n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_cols_to_mask, dim3(grid_for(a.n_tiles * kTS * kWave, 256)), dim3(256), 0, s, a, ctob, colOrig);
   return hipGetLastError();
 }
 
