@@ -31,6 +31,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E
+BF16_PEAK_TFLOPS = 2500.0  # MI355X dense BF16 matrix cores
 KERNEL_SRC = os.path.join(ROOT, "paper_2506_05362_amd", "csrc", "pd_kernels.hip")
 PROFILES = os.path.join(ROOT, "profiles")
 
@@ -235,6 +236,24 @@ def copy_probe():
     return {"bytes": 16 * n, "best_ms": best, "GB_per_s": 16 * n / (best / 1e3) / 1e9}
 
 
+def surrogate_inference(n_paths: int = 100000, T: int = 100):
+    """Throughput of the surrogate network's fused inference kernels (weights do
+    not change the work: seeded random ones), on strain paths resident in HBM."""
+    import numpy as np
+    from paper_2506_05362_amd import surrogate as S
+    rng = np.random.default_rng(0)
+    sur = S.Surrogate()
+    sur.xs = S.Scaler(np.zeros(6), np.ones(6))
+    sur.ys = S.Scaler(np.zeros(7), np.ones(7))
+    paths = rng.normal(size=(n_paths, T, 6)).astype(np.float32)
+    r = S.time_inference(sur, paths)
+    return {"metric": "surrogate inference samples/s", "value": r["samples"] / r["seconds"],
+            "unit": "samples/s", "samples": r["samples"], "seconds": r["seconds"],
+            "dims": list(sur.dims), "dtype": "bf16 matrix cores, fp32 accumulate",
+            "roofline": {"bound": "mfma", "achieved": r["tflops"], "peak": BF16_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": r["tflops"] / BF16_PEAK_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -248,6 +267,8 @@ def main():
     ap.add_argument("--no-copy-probe", action="store_true")
     ap.add_argument("--bond-path", choices=["auto", "slices", "tiles"], default="auto",
                     help="bond loop: LDS tiles where the mesh allows (auto), or force one")
+    ap.add_argument("--no-surrogate-inference", action="store_true",
+                    help="skip the timing of the surrogate network's inference kernels")
     ap.add_argument("--surrogate", action="store_true",
                     help="also run the representative-volume surrogate pipeline (64 simulated "
                          "paths, training, held-out error, inference speed; many minutes)")
@@ -287,6 +308,10 @@ def main():
         sec, _ = time_workload(args.secondary, args.steps, args.warmup, args.bond_path)
         out["secondary"] = {"workload": args.secondary, "value": sec["value"], "ms_per_step": sec["ms_per_step"],
                             "config": sec["config"], "roofline": sec["roofline"]}
+    if not args.no_surrogate_inference:
+        out["surrogate_inference"] = surrogate_inference()
+        print(f"[bench] surrogate inference: {out['surrogate_inference']['value']:.3g} samples/s, "
+              f"{out['surrogate_inference']['roofline']['achieved']:.1f} TFLOP/s", file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(wl, head["config"]["bonds"], args.cpu_budget)
     if args.surrogate:

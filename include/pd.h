@@ -279,8 +279,10 @@ pd_status pd_loop_counts(pd_ctx* ctx, int64_t* out5);
                          replay one captured HIP graph (default);
      PD_LOOP_DIRECT      the same launches, issued one by one;
      PD_LOOP_PERSISTENT  one cooperative launch per run of steps between candidate
-                         rebuilds: workgroups stay resident and meet at a grid
-                         barrier between steps;
+                         rebuilds: workgroups stay resident, share out the
+                         slices evenly (those of one XCD side by side), and meet
+                         at one grid barrier per step, where the last to arrive
+                         reduces the wall reactions;
      PD_LOOP_PER_GRAIN   unbatched reference: one launch per grain per step.
    slices_per_block: 64-node slices (wavefronts) per workgroup, 1, 2, 4 or 8
    (GRAPH and DIRECT; the others use 4).  xcd_remap: 1 maps consecutive

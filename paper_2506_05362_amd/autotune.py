@@ -1,9 +1,9 @@
 """Launch autotuner of the step loop (libpd_mi355x's pd_set_launch).
 
 For one simulation context it times every candidate launch configuration -
-step-loop mode (captured graph, persistent cooperative kernel), 64-node slices
-per workgroup, the XCD-aware workgroup order and the bond path (sliced rows or
-LDS tiles) - on the context's own state, keeps the fastest and restores the
+step-loop mode (captured graph, persistent cooperative kernel at full
+residency or one workgroup per compute unit), 64-node slices per workgroup,
+the XCD-aware workgroup order and the bond path (sliced rows or LDS tiles) - on the context's own state, keeps the fastest and restores the
 state it started from, so tuning changes nothing but speed (every candidate
 computes bitwise the same node state; the tile path is left out when a wall is
 servo-controlled, since its wall reactions, and through them the servo, agree
@@ -26,6 +26,8 @@ import numpy as np
 
 from . import inputs as I
 from . import pd
+
+PERSISTENT_ONE_PER_CU = 256  # MI355X compute units
 
 DEFAULT = dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=1, persistent_blocks=0,
                bond_path=pd.BONDS_SLICES)
@@ -50,8 +52,9 @@ def candidates(persistent: bool = True, tiles: bool = True) -> List[Dict[str, in
     out = [dict(loop=pd.LOOP_GRAPH, slices_per_block=spb, xcd_remap=x, persistent_blocks=0,
                 bond_path=pd.BONDS_SLICES) for spb in (1, 2, 4, 8) for x in (1, 0)]
     if persistent:
-        out.append(dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=1, persistent_blocks=0,
-                        bond_path=pd.BONDS_SLICES))
+        # as many workgroups as fit at once (0), or one per compute unit
+        out += [dict(loop=pd.LOOP_PERSISTENT, slices_per_block=4, xcd_remap=x, persistent_blocks=nb,
+                     bond_path=pd.BONDS_SLICES) for nb in (0, PERSISTENT_ONE_PER_CU) for x in (1, 0)]
     if tiles:
         out += [dict(loop=pd.LOOP_GRAPH, slices_per_block=4, xcd_remap=x, persistent_blocks=0,
                      bond_path=pd.BONDS_TILES) for x in (1, 0)]
@@ -60,6 +63,8 @@ def candidates(persistent: bool = True, tiles: bool = True) -> List[Dict[str, in
 
 def name_of(cfg: Dict[str, int]) -> str:
     base = f"{pd.LOOP_NAMES[cfg['loop']]}/spb{cfg['slices_per_block']}/xcd{cfg['xcd_remap']}"
+    if cfg["loop"] == pd.LOOP_PERSISTENT and cfg.get("persistent_blocks", 0):
+        base += f"/wg{cfg['persistent_blocks']}"
     return base + "/tiles" if cfg.get("bond_path", pd.BONDS_SLICES) == pd.BONDS_TILES else base
 
 

@@ -62,6 +62,7 @@ struct pd_ctx {
   double4* u4[2] = {nullptr, nullptr};
   double4* vh[2] = {nullptr, nullptr};  // mid-step velocities, indexed like u4 (beta or mu > 0)
   double *v = nullptr, *a = nullptr, *X = nullptr, *F = nullptr;
+  double4* X4 = nullptr;
   uint8_t* fixed = nullptr;
   GrainC* grains = nullptr;
   StencilC* stencil = nullptr;
@@ -113,9 +114,6 @@ struct pd_ctx {
   int64_t pg_cols = 0;  // wall-partial columns of the per-grain launches (shared slices twice)
   int64_t partial_cols = 0;  // columns allocated in wall_partial
   uint32_t* barrier = nullptr;  // [2]: arrival count, generation
-  std::vector<int64_t> slice_off_h;  // host copy of the padded slot offsets of the slices
-  int64_t* pers_ranges = nullptr;    // [pers_ranges_n + 1] 4-slice block runs of the persistent workgroups
-  int32_t pers_ranges_n = 0;
   // tiled bond loop (PD_BONDS_TILES): available when the horizon factor is 3
   // and every grain's nodes are in lexicographic order of some axis order
   int tile_ok = 0;
@@ -318,6 +316,7 @@ StepArgs step_args(pd_ctx* c) {
   A.cand = c->cand;
   A.cand_capacity = c->capacity;
   A.X = c->X;
+  A.X4 = c->X4;
   A.Kn = c->Kn;
   A.walls = c->walls;
   A.wall_partial = c->wall_partial;
@@ -433,32 +432,15 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
   }
   if (!c->barrier) TRY(alloc_n(c, &c->barrier, 2, "grid barrier"));
   HIPCHK(c, launch_fill_i32(reinterpret_cast<int32_t*>(c->barrier), 0, 2, c->stream));
-  c->cur ^= 1;
-  StepArgs A = step_args(c);
-  const int32_t maxb = persistent_max_blocks(A);
+  // (occupancy depends on the kernel and its LDS only, not on the buffer parity)
+  const int32_t maxb = persistent_max_blocks(step_args(c));
   if (maxb <= 0) return fail(c, PD_ERR_HIP, "no resident workgroups for the persistent step kernel");
   const int32_t nb = c->launch.persistent_blocks > 0 ? std::min(c->launch.persistent_blocks, maxb) : maxb;
-  if (c->pers_ranges_n != nb) {
-    // merge-path over the padded slots: workgroup r starts at the first 4-slice
-    // block whose slots before it reach r / nb of the total
-    const int64_t nv = (c->nslices + 3) / 4, total = c->slice_off_h[(size_t)c->nslices];
-    std::vector<int64_t> rr((size_t)nb + 1);
-    int64_t vb = 0;
-    for (int32_t r = 0; r <= nb; ++r) {
-      const int64_t target = r == nb ? total + 1 : (int64_t)((__int128)total * r / nb);
-      while (vb < nv && c->slice_off_h[(size_t)std::min<int64_t>(4 * vb, c->nslices)] < target) ++vb;
-      rr[(size_t)r] = r == nb ? nv : vb;
-    }
-    if (c->pers_ranges) dev_free(c, c->pers_ranges);
-    c->pers_ranges = nullptr;
-    TRY(alloc_n(c, &c->pers_ranges, (int64_t)nb + 1, "persistent ranges"));
-    HIPCHK(c, hipMemcpyAsync(c->pers_ranges, rr.data(), sizeof(int64_t) * rr.size(), hipMemcpyHostToDevice, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->pers_ranges_n = nb;
-  }
+  c->cur ^= 1;
+  StepArgs A = step_args(c);
   BarrierArgs B{c->barrier, c->barrier + 1, 1u << 24};
   if (ev0) HIPCHK(c, hipEventRecord(ev0, c->stream));
-  HIPCHK(c, launch_step_persistent(A, k, nb, c->pers_ranges, B, c->stream));
+  HIPCHK(c, launch_step_persistent(A, k, nb, B, c->stream));
   if (ev1) HIPCHK(c, hipEventRecord(ev1, c->stream));
   if ((k - 1) & 1) c->cur ^= 1;  // the kernel flipped the buffers k - 1 more times
   *done = k;
@@ -1055,6 +1037,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   TRY(alloc_n(c, &c->v, 3 * N, "v"));
   TRY(alloc_n(c, &c->a, 3 * N, "a"));
   TRY(alloc_n(c, &c->X, 3 * N, "X"));
+  TRY(alloc_n(c, &c->X4, std::max<int64_t>(N, 1), "X as double4"));
   TRY(alloc_n(c, &c->grains, G, "grain constants"));
   TRY(alloc_n(c, &c->stencil, (int64_t)st.size(), "stencil tables"));
   TRY(alloc_n(c, &c->Kn, (int64_t)n_mat * n_mat, "K_n"));
@@ -1073,6 +1056,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (mesh->fixed) TRY(alloc_n(c, &c->fixed, N, "fixed"));
   hipStream_t s = c->stream;
   HIPCHK(c, hipMemcpyAsync(c->X, mesh->X, sizeof(double) * 3 * N, hipMemcpyHostToDevice, s));
+  HIPCHK(c, launch_pack_x4(c->X, c->X4, N, s));
   HIPCHK(c, hipMemcpyAsync(c->grains, c->grains_h.data(), sizeof(GrainC) * G, hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->stencil, st.data(), sizeof(StencilC) * st.size(), hipMemcpyHostToDevice, s));
   HIPCHK(c, hipMemcpyAsync(c->Kn, kn.data(), sizeof(double) * kn.size(), hipMemcpyHostToDevice, s));
@@ -1247,11 +1231,8 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   HIPCHK(c, launch_bond_count(B, s));
   HIPCHK(c, launch_slice_width(B, s));
   HIPCHK(c, scan_i64(c->slice_off, c->slice_off, c->nslices, scan_scratch64, s));
-  c->slice_off_h.assign((size_t)c->nslices + 1, 0);
-  HIPCHK(c, hipMemcpyAsync(c->slice_off_h.data(), c->slice_off, sizeof(int64_t) * (c->nslices + 1),
-                           hipMemcpyDeviceToHost, s));
+  HIPCHK(c, hipMemcpyAsync(&c->padded, c->slice_off + c->nslices, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   HIPCHK(c, hipStreamSynchronize(s));
-  c->padded = c->slice_off_h[(size_t)c->nslices];
   TRY(alloc_n(c, &c->colE, c->padded, "bond columns"));
   TRY(alloc_n(c, &c->colOrig, c->padded, "bond columns as built"));
   B.colE = c->colE;

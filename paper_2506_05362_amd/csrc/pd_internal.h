@@ -20,6 +20,7 @@ constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
 constexpr int kChunk = 1024;        // wall-partial columns reduced by one workgroup
+constexpr int kContactBatch = 2;    // contact candidates whose gathers a lane issues together
 #ifndef PD_BOND_UNROLL
 #define PD_BOND_UNROLL 8
 #endif
@@ -148,6 +149,7 @@ struct StepArgs {
   const int32_t* cand;
   int64_t cand_capacity;
   const double* X;      // SoA, contact path only
+  const double4* X4;    // the same as (x, y, z, 0) per node: one load per contact candidate
   const double* Kn;     // [n_mat * n_mat]
   WallDev* walls;
   double* wall_partial;  // [n_walls][3][partial_stride]: one column per slice (component-major)
@@ -282,11 +284,10 @@ hipError_t launch_wall_corners(const StepArgs& a, int force_only, hipStream_t s)
 hipError_t launch_step_spb(const StepArgs& a, int slices_per_block, hipStream_t s, hipEvent_t e0 = nullptr,
                            hipEvent_t e1 = nullptr);
 // nsteps steps with no rebuild in between, one cooperative launch of nblocks
-// workgroups; workgroup r (in XCD order) runs the 4-slice blocks
-// [ranges[r], ranges[r + 1]), cut so that each run holds about the same number
-// of padded bond slots
-hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const int64_t* ranges,
-                                  const BarrierArgs& b, hipStream_t s);
+// workgroups that share out the 4-slice blocks of every step and meet at one
+// grid barrier per step
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const BarrierArgs& b,
+                                  hipStream_t s);
 // workgroups of the persistent kernel that fit on the device at once
 int32_t persistent_max_blocks(const StepArgs& a);
 int32_t step_blocks_spb(int64_t nslices, int slices_per_block);
@@ -305,6 +306,8 @@ hipError_t scan_i64(const int64_t* in, int64_t* out, int64_t n, int64_t* scratch
 hipError_t scan_i32(const int32_t* in, int32_t* out, int64_t n, int32_t* scratch, hipStream_t s);
 int32_t step_grid_blocks(int64_t nslices);
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s);
+// X4[i] = (X[i], X[n + i], X[2n + i], 0)
+hipError_t launch_pack_x4(const double* X, double4* X4, int64_t n, hipStream_t s);
 // tiled bond loop: MODE_STEP over all tiles (events as for launch_step_spb)
 hipError_t launch_step_tile(const StepArgs& a, hipStream_t s, hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr);
 // per-node cell map of the tile grains: tmap[map_off + (s em + m) ef + f] = node

@@ -530,15 +530,14 @@ __device__ __forceinline__ bool bond_intact(const StepArgs& A, int64_t i, int j,
 // between nodes of one grain without an intact bond (Sec. 5, where c_w / R_c
 // is the same K_n; self-contact needs R_c below the lattice spacing, so the
 // repulsive-only bond of pairs shorter than R_c never arises).
+// uj and Xj are the partner's displacement and reference position.
 template <bool EXTRA>
-__device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j, double Xx, double Xy, double Xz,
-                                             const double4& ui, const double4& vhi, int mi, double rho_i,
-                                             bool damp, bool fric, int perm, double& fx, double& fy,
-                                             double& fz) {
-  const double4 uj = A.ucur[j];
+__device__ __forceinline__ void contact_pair(const StepArgs& A, int64_t i, int j, const double4& uj,
+                                             const double4& Xj, const double4& Xi, const double4& ui,
+                                             const double4& vhi, int mi, double rho_i, bool damp, bool fric,
+                                             int perm, double& fx, double& fy, double& fz) {
   double yx, yy, yz;
-  const double d2 = contact_d2(A.X[j], Xx, uj.x, ui.x, A.X[A.n + j], Xy, uj.y, ui.y,
-                               A.X[2 * A.n + j], Xz, uj.z, ui.z, yx, yy, yz);
+  const double d2 = contact_d2(Xj.x, Xi.x, uj.x, ui.x, Xj.y, Xi.y, uj.y, ui.y, Xj.z, Xi.z, uj.z, ui.z, yx, yy, yz);
   if (d2 < A.Rc2 && d2 > 0.0) {
     // a node of the same grain repels only while no intact bond joins the two
     if (EXTRA && A.self_contact && packed_grain(uj.w) == packed_grain(ui.w) && bond_intact(A, i, j, perm))
@@ -591,9 +590,32 @@ __device__ __forceinline__ void node_tail(const StepArgs& A, int64_t i, bool val
     const int32_t c0 = (int32_t)min((int64_t)A.cand_ptr[i], A.cand_capacity);
     const int32_t c1 = (int32_t)min((int64_t)A.cand_ptr[i + 1], A.cand_capacity);
     if (c1 > c0) {
-      const double Xx = A.X[i], Xy = A.X[A.n + i], Xz = A.X[2 * A.n + i];
-      for (int32_t e = c0; e < c1; ++e)
-        contact_pair<EXTRA>(A, i, A.cand[e], Xx, Xy, Xz, ui, vhi, G->mat, rho_i, damp, fric, perm, fx, fy, fz);
+      // keep the candidate gathers here: hoisted above the bond loop they
+      // would hold their registers through it
+      asm volatile("" ::: "memory");
+      const double4 Xi = A.X4[i];
+      // kContactBatch candidates at a time: their indices, then their u and
+      // reference positions, are all in flight before the first pair is
+      // evaluated; the pairs are still added in row order
+      for (int32_t e = c0; e < c1; e += kContactBatch) {
+        int jj[kContactBatch];
+        double4 uj[kContactBatch], Xj[kContactBatch];
+#pragma unroll
+        for (int k = 0; k < kContactBatch; ++k) jj[k] = e + k < c1 ? A.cand[e + k] : -1;
+#pragma unroll
+        for (int k = 0; k < kContactBatch; ++k) {
+          if (jj[k] >= 0) {
+            uj[k] = A.ucur[jj[k]];
+            const double* xp = reinterpret_cast<const double*>(A.X4 + jj[k]);
+            Xj[k] = make_double4(xp[0], xp[1], xp[2], 0.0);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kContactBatch; ++k)
+          if (jj[k] >= 0)
+            contact_pair<EXTRA>(A, i, jj[k], uj[k], Xj[k], Xi, ui, vhi, G->mat, rho_i, damp, fric, perm, fx, fy,
+                                fz);
+      }
     }
   }
 
@@ -982,7 +1004,7 @@ __device__ __forceinline__ int64_t tile_cell(const TileGrain& TG, int s, int m, 
 // lane's cell from LDS, then the node tail of the slice path.  Lane l of
 // wavefront w owns cell (s0 + w, m0 + l / 16, f0 + l % 16).
 template <bool ABS, bool EXTRA>
-__global__ __launch_bounds__(kTS * kWave) void k_step_tile(StepArgs A) {
+__global__ __launch_bounds__(kTS * kWave) __attribute__((amdgpu_waves_per_eu(4))) void k_step_tile(StepArgs A) {
   // x, y and z planes of the halo box
   __shared__ double s_u[3 * kHalo];
   constexpr int kNT = kTS * kWave;
@@ -1268,22 +1290,25 @@ __global__ __launch_bounds__(1024) void k_wall_finalize(StepArgs A) {
 
 // ---------------------------------------------------------------------------
 // persistent step loop: nsteps steps (no candidate rebuild among them) in one
-// cooperative launch.  Workgroups walk the slice blocks of each step, meet at
-// a grid barrier, workgroup 0 reduces the wall reactions, and all meet again
-// before the next step reads the drifted positions.  Every wait has a spin
+// cooperative launch.  Workgroups walk their slice blocks of a step and meet at
+// one grid barrier per step; the workgroup that arrives last reduces the wall
+// reactions (in the order the launched wall kernels use, so the result is the
+// same bit for bit) and writes the halt word before it releases the others,
+// who then read the new wall state and the halt word.  Every wait has a spin
 // limit, so each wave exits even if a barrier were never completed.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ void grid_barrier(const BarrierArgs& B, uint32_t nblocks, uint32_t* status) {
+// Arrive at the grid barrier; returns (uniformly over the workgroup) whether
+// this workgroup arrived last.  The last one must call grid_release after its
+// serial work; the others have already waited for that release on return.
+__device__ __forceinline__ bool grid_arrive(const BarrierArgs& B, uint32_t nblocks, uint32_t* status,
+                                            uint32_t* s_flag) {
   __syncthreads();
   if (threadIdx.x == 0) {
     __threadfence();  // release this workgroup's writes to every XCD
     const uint32_t g = __hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
-    if (atomicAdd(B.count, 1u) == nblocks - 1u) {
-      atomicExch(B.count, 0u);
-      __threadfence();
-      atomicAdd(B.gen, 1u);
-    } else {
+    const bool last = atomicAdd(B.count, 1u) == nblocks - 1u;
+    if (!last) {
       uint32_t spins = 0;
       while (__hip_atomic_load(B.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
         __builtin_amdgcn_s_sleep(1);
@@ -1294,27 +1319,54 @@ __device__ __forceinline__ void grid_barrier(const BarrierArgs& B, uint32_t nblo
       }
     }
     __threadfence();  // acquire the other workgroups' writes
+    *s_flag = last ? 1u : 0u;
+  }
+  __syncthreads();
+  return *s_flag != 0u;
+}
+
+__device__ __forceinline__ void grid_release(const BarrierArgs& B) {
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    atomicExch(B.count, 0u);
+    __threadfence();  // release the serial work before the generation moves
+    atomicAdd(B.gen, 1u);
   }
   __syncthreads();
 }
 
 template <bool ABS>
 __global__ __launch_bounds__(4 * kWave) __attribute__((amdgpu_waves_per_eu(kUnroll > 4 ? 3 : 4)))
-void k_step_persistent(StepArgs A, int64_t nsteps, const int64_t* ranges, BarrierArgs B) {
+void k_step_persistent(StepArgs A, int64_t nsteps, BarrierArgs B) {
   extern __shared__ StencilC s_st[];
   __shared__ double red[kMaxWalls * 3][1024 / kWave];
   __shared__ double tot[kMaxWalls * 3];
   __shared__ int64_t s_step;
+  __shared__ uint32_t s_last;
   if (halted(A.halt)) return;
   stage_stencil(A, s_st);
-  // this workgroup's run of 4-slice blocks, cut at equal padded-slot counts;
-  // with the XCD order, neighbouring runs go to one XCD
-  const int64_t r = A.xcd_remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-  const int64_t vb0 = ranges[r], vb1 = ranges[r + 1];
+  // the nv 4-slice blocks are cut evenly into rounds x gridDim runs (of 0 or
+  // 1 blocks mostly).  In dispatch order workgroup b takes run q gridDim + b in
+  // round q; in XCD order (gridDim a multiple of 8) the nx = gridDim / 8
+  // workgroups of XCD x walk the x-th eighth of the runs side by side, so each
+  // XCD's L2 serves one contiguous eighth of the mesh.  An even cut by blocks
+  // measured faster than one by padded bond slots: the per-node work of a
+  // slice (contact, walls, Verlet) does not scale with its bonds.
+  const int64_t nv = (A.slice_end - A.slice_base + 3) / 4;
+  const int64_t nb = gridDim.x, rounds = (nv + nb - 1) / nb, np = rounds * nb;
+  int64_t p0 = blockIdx.x, pstep = nb;
+  if (A.xcd_remap && (gridDim.x & 7u) == 0u) {
+    const int64_t nx = nb >> 3;
+    p0 = (int64_t)(blockIdx.x & 7u) * rounds * nx + (blockIdx.x >> 3);
+    pstep = nx;
+  }
   for (int64_t k = 0; k < nsteps; ++k) {
-    for (int64_t vb = vb0; vb < vb1; ++vb) step_body<MODE_STEP, ABS, 4>(A, s_st, vb);
-    grid_barrier(B, gridDim.x, A.status);
-    if (blockIdx.x == 0) {
+    for (int64_t q = 0; q < rounds; ++q) {
+      const int64_t p = p0 + q * pstep;
+      const int64_t vb1 = nv * (p + 1) / np;
+      for (int64_t vb = nv * p / np; vb < vb1; ++vb) step_body<MODE_STEP, ABS, 4>(A, s_st, vb);
+    }
+    if (grid_arrive(B, gridDim.x, A.status, &s_last)) {
       // level (1) by this workgroup's wavefronts, then level (2)
       const int64_t nq = (A.partial_stride + kChunk - 1) / kChunk;
       for (int64_t pq = threadIdx.x >> 6; pq < (int64_t)(3 * A.n_walls) * nq; pq += 4) {
@@ -1327,9 +1379,8 @@ void k_step_persistent(StepArgs A, int64_t nsteps, const int64_t* ranges, Barrie
       if (threadIdx.x == 0)
         __hip_atomic_store(A.halt, __hip_atomic_load(A.status, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      grid_release(B);
     }
-    grid_barrier(B, gridDim.x, A.status);
-    // every workgroup reads the halt word workgroup 0 wrote before this barrier
     if (halted(A.halt)) break;
     // the drift just written is the next step's position; mid-step velocities likewise
     const double4* uc = A.ucur;
@@ -1796,6 +1847,11 @@ __global__ __launch_bounds__(kScanThreads) void k_scan_add(T* out, int64_t n, co
     if (base + k < n) out[base + k] += add;
 }
 
+__global__ void k_pack_x4(const double* X, double4* X4, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) X4[i] = make_double4(X[i], X[n + i], X[2 * n + i], 0.0);
+}
+
 __global__ void k_fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -1804,6 +1860,12 @@ __global__ void k_fill_i32_kernel(int32_t* p, int32_t v, int64_t n) {
 hipError_t launch_fill_i32(int32_t* p, int32_t v, int64_t n, hipStream_t s) {
   if (n <= 0) return hipSuccess;
   hipLaunchKernelGGL(k_fill_i32_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_pack_x4(const double* X, double4* X4, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_pack_x4, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, X, X4, n);
   return hipGetLastError();
 }
 
@@ -1927,14 +1989,13 @@ int32_t persistent_max_blocks(const StepArgs& a) {
   return per_cu * cus;
 }
 
-hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const int64_t* ranges,
-                                  const BarrierArgs& b, hipStream_t s) {
+hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nblocks, const BarrierArgs& b,
+                                  hipStream_t s) {
   if (nsteps <= 0) return hipSuccess;
   if (step_blocks_spb(a.slice_end - a.slice_base, 4) == 0) return hipSuccess;
   StepArgs aa = a;
   BarrierArgs bb = b;
-  const int64_t* rr = ranges;
-  void* args[] = {&aa, &nsteps, &rr, &bb};
+  void* args[] = {&aa, &nsteps, &bb};
   const void* fn = a.abs_stretch ? reinterpret_cast<const void*>(&k_step_persistent<true>)
                                  : reinterpret_cast<const void*>(&k_step_persistent<false>);
   // a cooperative launch fails rather than start more workgroups than can be

@@ -157,10 +157,11 @@ class Net:
             self.h = None
         _LIVE.discard(self)
 
-    def __del__(self):
+    def __del__(self, _finalizing=sys.is_finalizing):
         # during interpreter teardown the HIP runtime may already be gone: the
-        # exit hook closed every context that was still open before that
-        if sys.is_finalizing():
+        # exit hook closed every context that was still open before that (the
+        # check is bound at definition, since module globals may be cleared by then)
+        if _finalizing():
             return
         try:
             self.close()

@@ -27,6 +27,7 @@ import argparse
 import dataclasses
 import json
 import math
+import os
 import time
 from typing import Dict, List, Optional
 
@@ -304,10 +305,23 @@ def interpolation_baseline(Xtr: np.ndarray, ytr: np.ndarray, Xq: np.ndarray) -> 
     return out
 
 
-def evaluate(sur: "Surrogate", data, held: np.ndarray, train: np.ndarray) -> Dict:
+def ensemble_prediction(data, p: int, train: np.ndarray, k: int = 4) -> np.ndarray:
+    """Axial stress of path p predicted as the mean of the k training paths whose
+    confinement is nearest, each interpolated along the axial strain: what the
+    loading parameters alone fix, without the held-out aggregate's own scatter."""
+    conf = np.asarray(data["confinement"])
+    e = path(data, p, "strain")[:, AXIAL]
+    near = train[np.argsort(np.abs(conf[train] - conf[p]), kind="stable")[:k]]
+    return np.mean([np.interp(e, path(data, int(q), "strain")[:, AXIAL], path(data, int(q), "target")[:, AXIAL])
+                    for q in near], axis=0)
+
+
+def evaluate(sur: "Surrogate", data, held: np.ndarray, train: np.ndarray, prepeak_strain: float = 0.025) -> Dict:
     """Per held-out path: relative L2 error of the axial stress along the path,
-    for the network and for the interpolation baseline."""
-    errs, errs_lat, errs_dmg, base = [], [], [], []
+    for the network, the interpolation baseline and the confinement ensemble
+    (the scatter between aggregates loaded alike), over the whole path and up to
+    prepeak_strain axial strain."""
+    errs, errs_lat, errs_dmg, base, ens, errs_pre, base_pre = [], [], [], [], [], [], []
     Xtr = samples(data, train, "strain")
     ytr = samples(data, train, "target")
     for p in held:
@@ -319,11 +333,19 @@ def evaluate(sur: "Surrogate", data, held: np.ndarray, train: np.ndarray) -> Dic
         errs_dmg.append(float(np.abs(P[:, 6] - Y[:, 6]).max()))
         B = interpolation_baseline(Xtr, ytr[:, AXIAL], X)
         base.append(rel_l2(B, Y[:, AXIAL]))
+        ens.append(rel_l2(ensemble_prediction(data, int(p), train), Y[:, AXIAL]))
+        pre = X[:, AXIAL] <= prepeak_strain
+        errs_pre.append(rel_l2(P[pre, AXIAL], Y[pre, AXIAL]))
+        base_pre.append(rel_l2(B[pre], Y[pre, AXIAL]))
     return {"axial_rel_l2": errs, "axial_rel_l2_mean": float(np.mean(errs)),
             "axial_rel_l2_max": float(np.max(errs)),
             "lateral_rel_l2_mean": float(np.mean(errs_lat)),
             "damage_abs_max": float(np.max(errs_dmg)),
-            "interp_axial_rel_l2": base, "interp_axial_rel_l2_mean": float(np.mean(base))}
+            "interp_axial_rel_l2": base, "interp_axial_rel_l2_mean": float(np.mean(base)),
+            "ensemble_axial_rel_l2": ens, "ensemble_axial_rel_l2_mean": float(np.mean(ens)),
+            "prepeak_strain": prepeak_strain,
+            "axial_rel_l2_prepeak": errs_pre, "axial_rel_l2_prepeak_mean": float(np.mean(errs_pre)),
+            "interp_axial_rel_l2_prepeak_mean": float(np.mean(base_pre))}
 
 
 def inference_paths(data, train: np.ndarray, n_paths: int, T: int = 100, seed: int = 7) -> np.ndarray:
@@ -388,11 +410,15 @@ RVE_DEFAULTS = dict(platen_speed=1.0, contact_damping=2.8e22, servo_gain=5e-8, r
 
 def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int = 4000,
         infer_paths: int = 100000, infer_T: int = 100, seed: int = 0, out: Optional[str] = None,
-        log=print, **rve_kw) -> Dict:
-    specs = path_specs(n_paths, seed=seed)
+        log=print, data_file: Optional[str] = None, **rve_kw) -> Dict:
     rve_kw = {**RVE_DEFAULTS, **rve_kw}
     t0 = time.perf_counter()
-    data = generate(specs, n_log=n_log, log=log, **rve_kw)
+    if data_file:
+        # paths generated earlier (the _data.npz an earlier run wrote beside its JSON)
+        with np.load(data_file) as f:
+            data = {k: f[k] for k in f.files}
+    else:
+        data = generate(path_specs(n_paths, seed=seed), n_log=n_log, log=log, **rve_kw)
     gen_s = time.perf_counter() - t0
     n_ok = len(data["offsets"]) - 1
     held = np.arange(n_ok - n_held, n_ok)
@@ -422,10 +448,13 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
         "speedup_per_path": sim_per_path / inf["seconds_per_path"],
         "paths_simulated_in_inference_time": inf["seconds"] / sim_per_path,
     }
+    if data_file:
+        res["data_file"] = os.path.basename(data_file)
     if out:
         with open(out, "w") as f:
             json.dump(res, f, indent=1)
-        np.savez_compressed(out.replace(".json", "_data.npz"), **data)
+        if not data_file:
+            np.savez_compressed(out.replace(".json", "_data.npz"), **data)
     return res
 
 
@@ -440,6 +469,8 @@ def main(argv=None):
     ap.add_argument("--grains", type=int, default=200)
     ap.add_argument("--nodes-per-grain", type=float, default=1850.0)
     ap.add_argument("--out", default=None)
+    ap.add_argument("--data", default=None, metavar="NPZ",
+                    help="train and evaluate on paths an earlier run saved (its _data.npz) instead of simulating")
     ap.add_argument("--time-path", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps (after as many warm-up steps) of path 1 and exit")
     ap.add_argument("--time-inference", type=int, default=0, metavar="PATHS",
@@ -474,7 +505,7 @@ def main(argv=None):
     res = run(n_paths=a.paths, n_held=a.held, n_log=a.log_every, train_steps=a.train_steps,
               infer_paths=a.infer_paths, out=a.out, n_grains=a.grains,
               nodes_per_grain=a.nodes_per_grain, platen_speed=a.platen_speed,
-              log=lambda s: print(s, flush=True))
+              log=lambda s: print(s, flush=True), data_file=a.data)
     print(json.dumps({k: v for k, v in res.items() if not isinstance(v, list)}), flush=True)
 
 
