@@ -20,7 +20,10 @@ constexpr int kMaxHorizon = 6;      // m <= 6 keeps |d|^2 <= 36 and rows <= 925
 constexpr int kMaxD2 = kMaxHorizon * kMaxHorizon;
 constexpr int kCellDirs = 27;
 constexpr int kChunk = 1024;        // wall-partial columns reduced by one workgroup
-constexpr int kContactBatch = 2;    // contact candidates whose gathers a lane issues together
+#ifndef PD_CONTACT_BATCH
+#define PD_CONTACT_BATCH 2
+#endif
+constexpr int kContactBatch = PD_CONTACT_BATCH;  // contact candidates whose gathers a lane issues together
 #ifndef PD_BOND_UNROLL
 #define PD_BOND_UNROLL 8
 #endif
