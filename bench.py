@@ -40,6 +40,12 @@ PROFILES = os.path.join(ROOT, "profiles")
 #   per node          : 128 B (read u, X, v; write u, v; 8 B damage/intact)
 BYTES_PER_BOND = 4.125
 BYTES_PER_NODE = 128.0
+# FP64 operations of the bond law per directed bond (eta 3, y 3, 2 xi + eta 3,
+# |y|^2 - |xi|^2 3, x 1, series 8 + 1, break test 1, c V/|xi| g 1, force 3)
+# against the FP64 vector issue rate: 256 CUs x 4 SIMDs x 16 FP64 lanes x 2.4 GHz
+# (an FMA counted as one operation; 78.6 TFLOP/s counting it as two)
+FP64_OPS_PER_BOND = 27
+FP64_LANE_OPS_PEAK = 256 * 4 * 16 * 2.4e9
 
 
 def kernel_hash() -> str:
@@ -193,6 +199,7 @@ def time_workload(name: str, steps: int, warmup: int, bond_path_arg: str):
     kernel = "k_step_tile" if bond_path == pd.BONDS_TILES else "k_step"
     bytes_launch = nnz * BYTES_PER_BOND + N * BYTES_PER_NODE
     achieved = bytes_launch / avg_kernel_s / 1e9
+    traffic = traffic_record(name, kernel)
     out = {
         "value": nnz * steps / (total_ms / 1e3),
         "ms_per_step": total_ms / steps,
@@ -205,11 +212,19 @@ def time_workload(name: str, steps: int, warmup: int, bond_path_arg: str):
                    "timed_steps": [warmup + align + steps + 1, warmup + align + 2 * steps],
                    "build_s": round(build_s, 3)},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic_record(name, kernel),
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     # the counted HBM bytes over the same kernel time (null without a record
+                     # taken on this kernel source): what the memory system actually carried
+                     "traffic_GBps": traffic / avg_kernel_s / 1e9 if traffic else None,
                      "kernel": kernel, "avg_launch_us": avg_kernel_s * 1e6, "launches": launches,
                      "algorithmic_bytes_per_launch": bytes_launch,
                      "bytes_model": f"{BYTES_PER_BOND} B per directed bond + {BYTES_PER_NODE} B per node",
                      "kernel_bond_updates_per_s": nnz / avg_kernel_s},
+        # the same kernel against the FP64 vector units, by the bond law's operation count
+        "roofline_alu": {"bound": "alu", "achieved": nnz * FP64_OPS_PER_BOND / avg_kernel_s,
+                         "peak": FP64_LANE_OPS_PEAK, "unit": "FP64 op/s",
+                         "frac": nnz * FP64_OPS_PER_BOND / avg_kernel_s / FP64_LANE_OPS_PEAK,
+                         "ops_model": f"{FP64_OPS_PER_BOND} FP64 operations per directed bond"},
     }
     sim.close()
     return out, wl
@@ -300,6 +315,7 @@ def main():
         "data": "synthetic",
         "config": head["config"],
         "roofline": head["roofline"],
+        "roofline_alu": head["roofline_alu"],
     }
     if probe:
         out["roofline"]["attainable_copy_GBps"] = probe["GB_per_s"]
@@ -307,7 +323,8 @@ def main():
     if args.secondary:
         sec, _ = time_workload(args.secondary, args.steps, args.warmup, args.bond_path)
         out["secondary"] = {"workload": args.secondary, "value": sec["value"], "ms_per_step": sec["ms_per_step"],
-                            "config": sec["config"], "roofline": sec["roofline"]}
+                            "config": sec["config"], "roofline": sec["roofline"],
+                            "roofline_alu": sec["roofline_alu"]}
     if not args.no_surrogate_inference:
         out["surrogate_inference"] = surrogate_inference()
         print(f"[bench] surrogate inference: {out['surrogate_inference']['value']:.3g} samples/s, "

@@ -69,6 +69,26 @@ struct Gemm {
 
 enum { EPI_STORE = 0, EPI_BIAS = 1, EPI_BIAS_GELU = 2, EPI_GELU_GRAD = 3 };
 
+// Eight consecutive k of one row (or column) of an operand, rounded to BF16:
+// X(k) = p[k * sk] for k0 <= k < k0 + 8, zero past K or where ok is false.
+// A contiguous, 16-byte aligned run inside K is read as two float4.
+__device__ __forceinline__ v8s load8_bf16(const float* p, int64_t sk, int64_t k0, int64_t K, bool ok) {
+  v8s r;
+  if (ok && sk == 1 && k0 + 8 <= K && ((reinterpret_cast<uintptr_t>(p + k0) & 15u) == 0)) {
+    const float4 x = *reinterpret_cast<const float4*>(p + k0);
+    const float4 y = *reinterpret_cast<const float4*>(p + k0 + 4);
+    r = v8s{to_bf16(x.x), to_bf16(x.y), to_bf16(x.z), to_bf16(x.w), to_bf16(y.x), to_bf16(y.y), to_bf16(y.z),
+            to_bf16(y.w)};
+  } else {
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+      const int64_t k = k0 + e;
+      r[e] = to_bf16((ok && k < K) ? p[k * sk] : 0.0f);
+    }
+  }
+  return r;
+}
+
 template <int EPI>
 __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   __shared__ __align__(16) short As[kTile][kKRow];  // As[m][k]
@@ -84,18 +104,10 @@ __global__ __launch_bounds__(256) void k_gemm(Gemm g) {
   const int lr = tid >> 2, lk = (tid & 3) * 8;  // staging: row / column of the tile, 8 k each
   for (int64_t k0 = 0; k0 < g.K; k0 += kK) {
     {
-      const int64_t m = m0 + lr;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + lk + e;
-        As[lr][lk + e] = to_bf16((m < g.M && k < g.K) ? g.A[m * g.sam + k * g.sak] : 0.0f);
-      }
-      const int64_t n = n0 + lr;
-#pragma unroll
-      for (int e = 0; e < 8; ++e) {
-        const int64_t k = k0 + lk + e;
-        Bs[lr][lk + e] = to_bf16((n < g.N && k < g.K) ? g.B[k * g.sbk + n * g.sbn] : 0.0f);
-      }
+      // one 16-byte LDS store per operand and thread
+      const int64_t m = m0 + lr, n = n0 + lr;
+      *reinterpret_cast<v8s*>(&As[lr][lk]) = load8_bf16(g.A + (m < g.M ? m * g.sam : 0), g.sak, k0 + lk, g.K, m < g.M);
+      *reinterpret_cast<v8s*>(&Bs[lr][lk]) = load8_bf16(g.B + (n < g.N ? n * g.sbn : 0), g.sbk, k0 + lk, g.K, n < g.N);
     }
     __syncthreads();
     v8s a[2], b[2];
