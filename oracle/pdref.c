@@ -522,7 +522,7 @@ static void build_bonds(pdref* s) {
             }
             col[nnz++] = (int32_t)j;
           }
-      qsort(col + s->row_ptr[i], (size_t)(nnz - s->row_ptr[i]), sizeof(int32_t), cmp_i32);
+      if (nnz > s->row_ptr[i]) qsort(col + s->row_ptr[i], (size_t)(nnz - s->row_ptr[i]), sizeof(int32_t), cmp_i32);
       s->n0[i] = (int32_t)(nnz - s->row_ptr[i]);
     }
     free(map);
@@ -626,7 +626,7 @@ static void build_candidates(pdref* s) {
               if (pair_dist2(s, i, j, y) < cut2) ivec_push(&out, (int32_t)j);
             }
           }
-      qsort(out.v + start, (size_t)(out.len - start), sizeof(int32_t), cmp_i32);
+      if (out.len > start) qsort(out.v + start, (size_t)(out.len - start), sizeof(int32_t), cmp_i32);
     }
     free(head);
     free(next);

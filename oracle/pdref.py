@@ -26,6 +26,18 @@ CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", 
           "-shared", "-Wall"]
 
 
+SANITIZE_FLAGS = ["-O1", "-g", "-fno-omit-frame-pointer", "-fsanitize=address,undefined",
+                  "-fno-sanitize-recover=all", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99",
+                  "-fPIC", "-shared", "-Wall"]
+
+
+def build_sanitized(out: str) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer (any
+    finding aborts), for a process that preloads the ASan runtime."""
+    subprocess.check_call(["gcc", *SANITIZE_FLAGS, SRC, "-o", out, "-lm"])
+    return out
+
+
 def build(force: bool = True) -> str:
     """Compile the oracle with gcc (plain C, no FMA contraction)."""
     if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
@@ -41,9 +53,11 @@ _lib = None
 def lib():
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB):
+        # PDREF_LIB: another build of the same source (the sanitizer test's)
+        path = os.environ.get("PDREF_LIB", LIB)
+        if path == LIB and not os.path.exists(LIB):
             build()
-        L = C.CDLL(LIB)
+        L = C.CDLL(path)
         P = C.c_void_p
         L.pdref_create.restype = P
         L.pdref_create.argtypes = [C.c_int64, P, P, P, P, P, C.c_int32, P, P, P, C.c_int32, P, P,
