@@ -19,6 +19,10 @@ LIBS = {
     "libpd_mi355x.so": ["pd_kernels.hip", "pd_api.hip"],
     "libpd_mlp.so": ["mlp.hip"],
 }
+# roctx ranges around the host-side phases of a step (shown by rocprofv3 --marker-trace)
+LINK = {
+    "libpd_mi355x.so": ["-L/opt/rocm/lib", "-Wl,-rpath,/opt/rocm/lib", "-lrocprofiler-sdk-roctx"],
+}
 
 
 def build(verbose: bool = False) -> list:
@@ -26,7 +30,7 @@ def build(verbose: bool = False) -> list:
     for lib, srcs in LIBS.items():
         target = os.path.join(PKG, lib)
         tmp = target + ".tmp"
-        cmd = ["hipcc", *HIPFLAGS, *[os.path.join(CSRC, s) for s in srcs], "-o", tmp]
+        cmd = ["hipcc", *HIPFLAGS, *[os.path.join(CSRC, s) for s in srcs], *LINK.get(lib, []), "-o", tmp]
         if verbose:
             print(" ".join(cmd), flush=True)
         subprocess.check_call(cmd)

@@ -13,11 +13,22 @@
 #include <string>
 #include <vector>
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include "pd_internal.h"
 
 using namespace pdk;
 
 namespace {
+
+// A roctx range over a host-side phase (enqueueing work, not its run time on
+// the device), visible in rocprofv3 --marker-trace next to the kernels.
+struct Range {
+  explicit Range(const char* name) { roctxRangePushA(name); }
+  ~Range() { roctxRangePop(); }
+  Range(const Range&) = delete;
+  Range& operator=(const Range&) = delete;
+};
 
 constexpr double kPi = 3.14159265358979323846;
 constexpr uint64_t kMagic = 0x3130536b4450554dull;  // checkpoint magic
@@ -384,8 +395,10 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
 // one step on the device: rebuild on cadence, force+Verlet, walls.
 // ev0/ev1 (optional) bracket the step kernel.
 pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) {
+  Range r("pd step: enqueue one step");
   const int nxt = c->cur ^ 1;
   if (s % c->rebuild_every == 0) {
+    Range rr("pd step: contact rebuild");
     ContactArgs C = contact_args(c, nxt);
     HIPCHK(c, launch_contact_rebuild(C, skin_guard(c), c->stream));
   }
@@ -423,6 +436,7 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
 // that no candidate rebuild falls inside (a rebuild due at the first step runs
 // before the launch).
 pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t ev0, hipEvent_t ev1) {
+  Range r("pd step: persistent run");
   const int64_t s = c->step + 1;
   const int64_t R = c->rebuild_every;
   const int64_t k = std::min<int64_t>(left, (s / R + 1) * R - s);
@@ -450,6 +464,7 @@ pd_status enqueue_persistent(pd_ctx* c, int64_t left, int64_t* done, hipEvent_t 
 // capture graph_len steps starting at a multiple of graph_len (buffer parity 0)
 pd_status capture_graph(pd_ctx* c) {
   if (c->graph_exec) return PD_OK;
+  Range r("pd step: capture the step graph");
   const int cur0 = c->cur;
   HIPCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
   pd_status st = PD_OK;
@@ -1113,6 +1128,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
 
 pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
   if (!c) return PD_ERR_INVALID;
+  Range r("pd_build_bonds");
   if (c->built) return fail(c, PD_ERR_STATE, "bonds already built");
   if (c->grains_h.empty()) return fail(c, PD_ERR_STATE, "context not initialised");
   if (n_cuts < 0 || (n_cuts > 0 && !cuts)) return fail(c, PD_ERR_INVALID, "bad cut array");
@@ -1326,6 +1342,7 @@ pd_status pd_build_bonds(pd_ctx* c, const pd_cut* cuts, int32_t n_cuts) {
 
 pd_status pd_step(pd_ctx* c, int64_t n_steps) {
   if (!c) return PD_ERR_INVALID;
+  Range r("pd_step");
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   if (n_steps < 0) return fail(c, PD_ERR_INVALID, "n_steps < 0");
   int64_t left = n_steps;
@@ -1345,6 +1362,7 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
                          c->step % c->graph_len == 0 && left >= c->graph_len;
     if (aligned) {
       TRY(capture_graph(c));
+      Range rg("pd step: graph replay");
       HIPCHK(c, hipGraphLaunch(c->graph_exec, c->stream));
       c->step += c->graph_len;
       left -= c->graph_len;
@@ -1656,6 +1674,7 @@ pd_status pd_set_wall(pd_ctx* c, int32_t w, const pd_wall* wall) {
 // then u4[cur], u4[cur^1], v, a, live column words, intact, u_build, walls,
 // [vh[cur], vh[cur^1] when damping or friction is on], crc32
 pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
+  Range r("pd_get_state");
   if (!c || !bytes) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   const int64_t N = c->n;
@@ -1700,6 +1719,7 @@ pd_status pd_get_state(pd_ctx* c, void* blob, int64_t* bytes) {
 }
 
 pd_status pd_set_state(pd_ctx* c, const void* blob, int64_t bytes) {
+  Range r("pd_set_state");
   if (!c || !blob) return PD_ERR_INVALID;
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   const uint8_t* p = static_cast<const uint8_t*>(blob);

@@ -8,7 +8,7 @@ start, logging the platen stress, the mean damage and the kinetic energy every
 100 steps, until the requested axial strain or the time budget.  Prints JSON.
 
     python -m paper_2506_05362_amd.scale_bench [--steps 200] [--strain 0.05] [--budget 120]
-        [--self-contact 0] [--wall-corners 0]
+        [--self-contact 0] [--wall-corners 0] [--jsonl FILE]
 """
 from __future__ import annotations
 
@@ -53,9 +53,19 @@ def main(argv=None):
                          "also hold the own grain's neighbours)")
     ap.add_argument("--self-contact", type=int, default=0, choices=(0, 1),
                     help="contact between fragments of one grain (Sec. 5)")
+    ap.add_argument("--jsonl", default=None, metavar="FILE",
+                    help="also write every record (setup, each bond path's timing, each log point, the "
+                         "result) as one JSON line to FILE, flushed as it is produced")
     ap.add_argument("--wall-corners", type=int, default=0, choices=(0, 1),
                     help="inclusion-exclusion of the box's walls at its edges and corners (Sec. 4.1.1)")
     a = ap.parse_args(argv)
+    jl = open(a.jsonl, "w") if a.jsonl else None
+
+    def record(kind, obj):
+        if jl:
+            jl.write(json.dumps({"kind": kind, **obj}) + "\n")
+            jl.flush()
+
     if a.capacity <= 0:
         a.capacity = 48 if a.self_contact else 32
     import torch
@@ -83,6 +93,7 @@ def main(argv=None):
            "platen_speed": wl.walls[1].velocity,
            "device_bytes": int(torch.cuda.memory_allocated())}
     print(json.dumps(out), flush=True)
+    record("setup", out)
 
     start = sim.get_state()
     paths = {}
@@ -98,6 +109,7 @@ def main(argv=None):
         paths[name] = {"ms_per_step": wall * 1e3, "step_kernel_ms": kern_ms,
                        "bond_updates_per_s": info["nnz"] / wall, "bitwise_equal_to_slices": same}
         print(name, json.dumps(paths[name]), flush=True)
+        record("bond_path", {"bond_path": name, **paths[name]})
     out["paths"] = paths
     best = min((p for p in paths if "ms_per_step" in paths[p]), key=lambda p: paths[p]["ms_per_step"])
     out["bond_path"] = best
@@ -127,6 +139,7 @@ def main(argv=None):
                     "mean_damage": float(dmg.mean()),
                     "kinetic_energy_j": float(0.5 * mass * np.sum(v * v))})
         print(json.dumps(log[-1]), flush=True)
+        record("log", log[-1])
         if time.perf_counter() - t0 > a.budget:
             status = "time budget"
             break
@@ -134,6 +147,10 @@ def main(argv=None):
                           "ms_per_step": 1e3 * (time.perf_counter() - t0) / max(done, 1), "log": log}
     sim.close()
     print(json.dumps(out), flush=True)
+    record("result", {k: v for k, v in out.items() if k != "compression"} |
+           {"compression": {k: v for k, v in out["compression"].items() if k != "log"}})
+    if jl:
+        jl.close()
 
 
 if __name__ == "__main__":
