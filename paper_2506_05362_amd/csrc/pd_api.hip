@@ -359,6 +359,7 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
   ContactArgs C{};
   C.u = c->u4[buf];
   C.X = c->X;
+  C.X4 = c->X4;
   C.cellkey = c->cellkey;
   C.srec = c->srec;
   C.cand_scratch = c->cand_scratch;

@@ -237,6 +237,7 @@ struct BuildArgs {
 struct ContactArgs {
   const double4* u;
   const double* X;
+  const double4* X4;  // (x, y, z, 0) per node: one load per candidate position
   long long* cellkey;    // [N] packed cell coordinates of each binned node
   uint32_t* cellh;       // [N]
   int32_t* bucket_count;  // [T]

@@ -1679,9 +1679,9 @@ __device__ __forceinline__ void cand_consider(const ContactArgs& c, const int4& 
   if (r.y == gi && (!c.self_contact || r.x == i)) return;
   const int j = r.x;
   const double4 uj = c.u[j];
+  const double* xp = reinterpret_cast<const double*>(c.X4 + j);
   double yx, yy, yz;
-  const double d2 = contact_d2(c.X[j], Xx, uj.x, ui.x, c.X[c.n + j], Xy, uj.y, ui.y, c.X[2 * c.n + j], Xz, uj.z,
-                               ui.z, yx, yy, yz);
+  const double d2 = contact_d2(xp[0], Xx, uj.x, ui.x, xp[1], Xy, uj.y, ui.y, xp[2], Xz, uj.z, ui.z, yx, yy, yz);
   if (!(d2 < c.cut2)) return;
   if (cnt < c.scratch_w) row[cnt] = j;
   ++cnt;
@@ -1698,7 +1698,8 @@ __global__ __launch_bounds__(256) void k_cand_search(ContactArgs c) {
   const int cx = (int)((key >> 42) & 0x1fffff) - (1 << 20);
   const int cy = (int)((key >> 21) & 0x1fffff) - (1 << 20);
   const int cz = (int)(key & 0x1fffff) - (1 << 20);
-  const double Xx = c.X[i], Xy = c.X[c.n + i], Xz = c.X[2 * c.n + i];
+  const double4 Xi = c.X4[i];
+  const double Xx = Xi.x, Xy = Xi.y, Xz = Xi.z;
   int32_t* row = c.cand_scratch + i * (int64_t)c.scratch_w;
   int cnt = 0;
   if (c.grid[0]) {
