@@ -408,15 +408,43 @@ RVE_DEFAULTS = dict(platen_speed=1.0, contact_damping=2.8e22, servo_gain=5e-8, r
                     axial_strain=0.05, skin_factor=0.5)
 
 
+def load_data(files: List[str]) -> Dict[str, np.ndarray]:
+    """Paths saved by earlier runs (their _data.npz), joined in the given order."""
+    parts = []
+    for fn in files:
+        with np.load(fn) as f:
+            parts.append({k: f[k] for k in f.files})
+    if len(parts) == 1:
+        return parts[0]
+    flat = ("strain", "target", "t")
+    per_path = ("seconds", "steps_run", "steps", "truncated", "nodes", "bonds", "confinement", "seed")
+    out = {k: np.concatenate([d[k] for d in parts]) for k in flat + per_path}
+    lens = np.concatenate([np.diff(d["offsets"]) for d in parts])
+    out["offsets"] = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    out["dropped"] = np.concatenate([d["dropped"] for d in parts]).astype(np.int64)
+    return out
+
+
 def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int = 4000,
         infer_paths: int = 100000, infer_T: int = 100, seed: int = 0, out: Optional[str] = None,
-        log=print, data_file: Optional[str] = None, **rve_kw) -> Dict:
+        log=print, data_file: Optional[str] = None, only: Optional[tuple] = None, **rve_kw) -> Dict:
+    """The whole study; with only = (a, b), just simulate paths a..b-1 of the
+    n_paths path set and save them (to join later with data_file)."""
     rve_kw = {**RVE_DEFAULTS, **rve_kw}
     t0 = time.perf_counter()
+    if only is not None:
+        data = generate(path_specs(n_paths, seed=seed)[only[0]:only[1]], n_log=n_log, log=log, **rve_kw)
+        res = {"paths": f"{only[0]}:{only[1]} of {n_paths}", "rve": dict(rve_kw),
+               "generate_seconds": time.perf_counter() - t0, "paths_used": len(data["offsets"]) - 1,
+               "paths_truncated": int(np.sum(data["truncated"]))}
+        if out:
+            with open(out, "w") as f:
+                json.dump(res, f, indent=1)
+            np.savez_compressed(out.replace(".json", "_data.npz"), **data)
+        return res
     if data_file:
-        # paths generated earlier (the _data.npz an earlier run wrote beside its JSON)
-        with np.load(data_file) as f:
-            data = {k: f[k] for k in f.files}
+        # paths generated earlier (the _data.npz files earlier runs wrote), comma-separated
+        data = load_data(data_file.split(","))
     else:
         data = generate(path_specs(n_paths, seed=seed), n_log=n_log, log=log, **rve_kw)
     gen_s = time.perf_counter() - t0
@@ -469,8 +497,11 @@ def main(argv=None):
     ap.add_argument("--grains", type=int, default=200)
     ap.add_argument("--nodes-per-grain", type=float, default=1850.0)
     ap.add_argument("--out", default=None)
-    ap.add_argument("--data", default=None, metavar="NPZ",
-                    help="train and evaluate on paths an earlier run saved (its _data.npz) instead of simulating")
+    ap.add_argument("--data", default=None, metavar="NPZ[,NPZ...]",
+                    help="train and evaluate on paths earlier runs saved (their _data.npz, joined in order) "
+                         "instead of simulating")
+    ap.add_argument("--only", default=None, metavar="A:B",
+                    help="only simulate paths A..B-1 of the --paths set and save them (no training)")
     ap.add_argument("--time-path", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps (after as many warm-up steps) of path 1 and exit")
     ap.add_argument("--time-inference", type=int, default=0, metavar="PATHS",
@@ -505,7 +536,8 @@ def main(argv=None):
     res = run(n_paths=a.paths, n_held=a.held, n_log=a.log_every, train_steps=a.train_steps,
               infer_paths=a.infer_paths, out=a.out, n_grains=a.grains,
               nodes_per_grain=a.nodes_per_grain, platen_speed=a.platen_speed,
-              log=lambda s: print(s, flush=True), data_file=a.data)
+              log=lambda s: print(s, flush=True), data_file=a.data,
+              only=tuple(int(v) for v in a.only.split(":")) if a.only else None)
     print(json.dumps({k: v for k, v in res.items() if not isinstance(v, list)}), flush=True)
 
 
