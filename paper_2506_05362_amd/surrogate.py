@@ -477,7 +477,7 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
         "paths_simulated_in_inference_time": inf["seconds"] / sim_per_path,
     }
     if data_file:
-        res["data_file"] = os.path.basename(data_file)
+        res["data_file"] = ",".join(os.path.basename(f) for f in data_file.split(","))
     if out:
         with open(out, "w") as f:
             json.dump(res, f, indent=1)
