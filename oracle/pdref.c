@@ -46,6 +46,13 @@
  *      damping and friction of R15/R17 on top.  The paper's assumption
  *      eps <= R_c is not needed for this case split and is not made.  With
  *      self-contact the skin guard applies to a single grain as well.
+ *   R12 contact pairs (Sec. 3.2) are found among candidates within R_c + skin,
+ *      rebuilt every rebuild_every steps; a node that moved more than skin/2
+ *      since the last rebuild may have missed a pair, which the guard reports.
+ *      PDREF_ADAPTIVE_REBUILD instead rebuilds before any evaluation at which
+ *      that happened: the forces do not depend on when the candidates were
+ *      built as long as they hold every pair within R_c, so the result is that
+ *      of a rebuild before every evaluation.
  *   R19 several walls (Sec. 4.1.1, PDREF_WALL_CORNERS): inclusion-exclusion
  *      over the walls a node touches, pairs counted once (the printed sum over
  *      i != j would count each twice) and the triple term without the stray
@@ -113,6 +120,7 @@ struct pdref {
   int32_t* cand;
   double* u_at_build;
   int64_t step;
+  int64_t early_rebuilds; /* PDREF_ADAPTIVE_REBUILD rebuilds between the cadence ones */
   double* margin; /* [nnz] min over the bond's evaluations of its break margin */
   double min_margin;
   int built;
@@ -962,11 +970,16 @@ int32_t pdref_step(pdref* s, int64_t nsteps) {
     }
     s->step += 1;
     advance_walls(s);
+    /* the skin guard protects contact pairs; a single grain without
+       self-contact has none to miss */
+    const int contacts = s->n_grains > 1 || (s->flags & PDREF_SELF_CONTACT);
+    const int adaptive = (s->flags & PDREF_ADAPTIVE_REBUILD) != 0;
     if (s->step % s->rebuild_every == 0) {
-      /* the skin guard protects contact pairs; a single grain without
-         self-contact has none to miss */
-      if ((s->n_grains > 1 || (s->flags & PDREF_SELF_CONTACT)) && skin_exceeded(s)) bad = 1;
+      if (contacts && !adaptive && skin_exceeded(s)) bad = 1;
       build_candidates(s);
+    } else if (contacts && adaptive && skin_exceeded(s)) {
+      build_candidates(s); /* the list may miss a pair within R_c at these positions */
+      s->early_rebuilds += 1;
     }
     /* new accelerations at the new positions, then the velocity update; the
        damping law sees the mid-step velocity v_n + dt/2 a_n */
@@ -1109,6 +1122,7 @@ void pdref_bond_margin(const pdref* s, double* out) {
 }
 
 int32_t pdref_skin_exceeded(const pdref* s) { return skin_exceeded(s); }
+int64_t pdref_early_rebuilds(const pdref* s) { return s->early_rebuilds; }
 
 void pdref_set_u(pdref* s, const double* u) {
   memcpy(s->u, u, sizeof(double) * (size_t)(3 * s->n));

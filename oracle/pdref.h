@@ -42,6 +42,8 @@ extern "C" {
 #define PDREF_CONIC 8         /* conic micromodulus c0 (1 - |xi|/delta) instead of a constant one */
 #define PDREF_SELF_CONTACT 16 /* contact between nodes of one grain with no intact bond (Sec. 5) */
 #define PDREF_WALL_CORNERS 32 /* inclusion-exclusion of orthogonal walls at a corner (Sec. 4.1.1) */
+#define PDREF_ADAPTIVE_REBUILD 64 /* rebuild the contact candidates before any evaluation at which a
+                                     node has moved more than skin/2 since the last rebuild */
 
 /* packed wall record (15 doubles):
  *   nx ny nz offset velocity lox loy loz hix hiy hiz mode target_stress servo_gain area */
@@ -98,8 +100,11 @@ void pdref_energy(const pdref* s, double* out4);
 double pdref_min_margin(const pdref* s);
 void pdref_bond_margin(const pdref* s, double* out);
 /* 1 when some node moved more than skin/2 since the last candidate rebuild
-   (the guard pdref_step applies at each rebuild when contacts can exist) */
+   (the guard pdref_step applies at each rebuild when contacts can exist, or
+   before every evaluation with PDREF_ADAPTIVE_REBUILD, which rebuilds then) */
 int32_t pdref_skin_exceeded(const pdref* s);
+/* candidate rebuilds PDREF_ADAPTIVE_REBUILD added between the cadence ones */
+int64_t pdref_early_rebuilds(const pdref* s);
 /* overwrite u (tests compare lists on identical positions) and rebuild candidates */
 void pdref_set_u(pdref* s, const double* u);
 /* recompute the candidate list from the current u */

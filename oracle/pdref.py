@@ -21,6 +21,7 @@ CELL_LIST = 4
 CONIC = 8
 SELF_CONTACT = 16
 WALL_CORNERS = 32
+ADAPTIVE_REBUILD = 64
 
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-fopenmp", "-std=c99", "-fPIC",
           "-shared", "-Wall"]
@@ -86,6 +87,8 @@ def lib():
         L.pdref_bond_margin.argtypes = [P, P]
         L.pdref_skin_exceeded.argtypes = [P]
         L.pdref_skin_exceeded.restype = C.c_int32
+        L.pdref_early_rebuilds.argtypes = [P]
+        L.pdref_early_rebuilds.restype = C.c_int64
         L.pdref_set_u.argtypes = [P, P]
         L.pdref_rebuild_candidates.argtypes = [P]
         L.pdref_energy_density.argtypes = [P, P]
@@ -155,6 +158,8 @@ class Oracle:
             flags |= SELF_CONTACT
         if getattr(wl.params, "wall_corners", False):
             flags |= WALL_CORNERS
+        if getattr(wl.params, "adaptive_rebuild", False):
+            flags |= ADAPTIVE_REBUILD
         self.wl = wl
         self.n = wl.n_nodes
         p = wl.params
@@ -267,6 +272,9 @@ class Oracle:
 
     def skin_exceeded(self) -> bool:
         return bool(lib().pdref_skin_exceeded(self.h))
+
+    def early_rebuilds(self) -> int:
+        return int(lib().pdref_early_rebuilds(self.h))
 
     def set_u(self, u):
         u = np.ascontiguousarray(u, dtype=np.float64)

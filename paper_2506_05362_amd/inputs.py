@@ -78,6 +78,7 @@ class Params:
     micromodulus: str = "constant"  # "constant" or "conic" (c0 (1 - |xi|/delta))
     self_contact: bool = False  # contact between nodes of one grain with no intact bond
     wall_corners: bool = False  # inclusion-exclusion of orthogonal walls at box corners
+    adaptive_rebuild: bool = False  # rebuild the candidates early once a node moved skin/2
 
 
 @dataclasses.dataclass

@@ -169,6 +169,54 @@ def test_skin_guard_needs_a_contact_partner(oracle_lib):
     assert o.step(wl.params.rebuild_every) == -5
 
 
+def test_adaptive_rebuild_counts_the_drift(oracle_lib):
+    """With early rebuilds the drift of 0.12 skin/2 per step never stops the
+    run: the list is rebuilt at the ninth step after each rebuild (1.08 skin/2;
+    the eighth is at 0.96), so once in every cadence of ten steps."""
+    wl = _drifting_node(1.2)
+    wl.params.adaptive_rebuild = True
+    o = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST)
+    assert o.step(100) == 0
+    assert o.early_rebuilds() == 10
+    assert not o.skin_exceeded()  # step 100 is a cadence rebuild
+    u = o.state()["u"]
+    assert u[1, -1] == pytest.approx(100 * 0.12 * 0.5 * wl.params.skin, rel=1e-12)
+
+
+def _fast_collision(rebuild_every, adaptive):
+    # the closest pair starts 1.2 skins beyond R_c: out of the first list
+    wl = I.two_spheres(radius_cells=4, speed=50.0, gap=0.3 * H, rebuild_every=rebuild_every)
+    wl.params.adaptive_rebuild = adaptive
+    return wl
+
+
+def test_adaptive_rebuild_equals_a_rebuild_before_every_evaluation(oracle_lib):
+    """Two balls closing at 50 m/s move skin/2 in 25 steps.  A rebuild every
+    100 steps alone misses the pairs that come within R_c after the first list
+    (the velocities differ by metres per second at step 100, where the guard
+    stops the run); with early rebuilds the state is bitwise that of a rebuild
+    before every evaluation: each list holds every pair within R_c, sorted, and
+    the contact sum only takes those."""
+    steps = 300
+    plain = oracle_lib.Oracle(_fast_collision(100, False), flags=oracle_lib.CELL_LIST, threads=2)
+    every = oracle_lib.Oracle(_fast_collision(1, False), flags=oracle_lib.CELL_LIST, threads=2)
+    assert plain.step(steps) == -5
+    assert plain.step_count == 100  # it stops after the step whose rebuild found the drift
+    assert every.step(100) == 0
+    assert np.abs(plain.state()["v"] - every.state()["v"]).max() > 1.0
+    early = oracle_lib.Oracle(_fast_collision(100, True), flags=oracle_lib.CELL_LIST, threads=2)
+    assert early.step(steps) == 0 and every.step(steps - 100) == 0
+    assert early.early_rebuilds() >= steps // 25 - 4
+    assert every.early_rebuilds() == 0
+    se, s1 = early.state(), every.state()
+    for k in ("u", "v", "a"):
+        assert np.array_equal(se[k], s1[k]), k
+    assert np.array_equal(early.bonds()[2], every.bonds()[2])
+    # the balls met: the struck one moves along -x
+    nA = int(early.wl.grain_begin[1])
+    assert se["v"][0, :nA].mean() < -1.0
+
+
 # ---------------------------------------------------------------------------
 # gravity potential of the energy diagnostic (Sec. 5.1 body force)
 # ---------------------------------------------------------------------------
