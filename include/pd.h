@@ -102,7 +102,7 @@ enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 
                                      lattice spacing (so no pair is shorter than R_c), else
                                      PD_ERR_INVALID; the skin guard then applies to a single grain
                                      too */
-       PD_FLAG_WALL_CORNERS = 32  /* several walls (Sec. 4.1.1): a node touching two or three mutually
+       PD_FLAG_WALL_CORNERS = 32, /* several walls (Sec. 4.1.1): a node touching two or three mutually
                                      orthogonal walls (a box edge or corner) gets the inclusion-exclusion
                                      sum F_l + F_l' - F_ll' (+ ...) of terms -K_n (R_c - |c_S - p|) |S| e_S
                                      over the parts S of its contact ball beyond the walls, volumes and
@@ -110,7 +110,16 @@ enum { PD_FLAG_TABLE_LITERAL = 1, /* use the printed 3-D table row for c and s0 
                                      corrections' components along its normal.  Damping and friction stay
                                      per wall; walls that are not orthogonal are summed.  A small pass
                                      before each evaluation finds the corner nodes; PD_LOOP_PERSISTENT
-                                     is then refused (PD_ERR_UNSUPPORTED) */ };
+                                     is then refused (PD_ERR_UNSUPPORTED) */
+       PD_FLAG_ADAPTIVE_REBUILD = 64 /* early candidate rebuilds (contact set, Sec. 3.2): before every
+                                     evaluation between cadence rebuilds a pass checks every node's
+                                     displacement since the last rebuild; once one exceeds skin/2
+                                     that step is not taken, the candidates are rebuilt at those
+                                     positions and pd_step goes on from the same step, so the skin
+                                     error never arises and the result is that of a rebuild before
+                                     every evaluation.  Costs one pass per step (56 bytes per node)
+                                     and a status read after each captured run of steps;
+                                     PD_LOOP_PERSISTENT is refused (PD_ERR_UNSUPPORTED) */ };
 
 typedef struct {
   int32_t horizon_factor;  /* m: horizon delta = m h; bonds are same-grain pairs with
@@ -214,7 +223,10 @@ pd_status pd_build_bonds(pd_ctx* ctx, const pd_cut* cuts, int32_t n_cuts);
    after it change nothing, and the context is left at that step (PD_STEP and
    every field report it); the flag is cleared once reported.  Chunks of
    rebuild_every steps (doubled when odd) that start on a multiple of that
-   length replay one captured HIP graph; the rest launch kernels directly. */
+   length replay one captured HIP graph; the rest launch kernels directly.
+   With PD_FLAG_ADAPTIVE_REBUILD the status is read after every such chunk
+   (and every run of direct steps up to the next multiple), and an early
+   rebuild is not an error. */
 pd_status pd_step(pd_ctx* ctx, int64_t n_steps);
 
 /* Bytes a field occupies (for sizing dst). */
@@ -263,10 +275,11 @@ pd_status pd_info(pd_ctx* ctx, int64_t* out5);
    every grain on one lattice with one spacing, bond table and node order). */
 pd_status pd_tile_info(pd_ctx* ctx, int64_t* n_tiles, int32_t* lattice);
 
-/* How the steps of this context were launched so far: out5 = graph replays,
+/* How the steps of this context were launched so far: out6 = graph replays,
    steps run inside them, steps launched directly, persistent launches, steps
-   run inside those. */
-pd_status pd_loop_counts(pd_ctx* ctx, int64_t* out5);
+   run inside those (steps halted by a flag included), and early candidate
+   rebuilds (PD_FLAG_ADAPTIVE_REBUILD). */
+pd_status pd_loop_counts(pd_ctx* ctx, int64_t* out6);
 
 /* How pd_step launches the step.  GRAPH, DIRECT and PERSISTENT, with any
    slices_per_block and xcd_remap, compute bitwise the same node state and wall

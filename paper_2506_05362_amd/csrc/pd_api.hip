@@ -148,8 +148,9 @@ struct pd_ctx {
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
   // how the steps of this context were launched: graph replays, steps in them,
-  // directly launched steps, persistent launches and the steps in them
-  int64_t counts[5] = {0, 0, 0, 0, 0};
+  // directly launched steps, persistent launches and the steps in them, early
+  // candidate rebuilds
+  int64_t counts[6] = {0, 0, 0, 0, 0, 0};
 };
 
 namespace {
@@ -286,6 +287,11 @@ int skin_guard(const pd_ctx* c) {
   return (c->n_grains > 1 || (c->flags & PD_FLAG_SELF_CONTACT)) ? 1 : 0;
 }
 
+// PD_FLAG_ADAPTIVE_REBUILD, where contact pairs can exist
+bool early_rebuilds(const pd_ctx* c) {
+  return (c->flags & PD_FLAG_ADAPTIVE_REBUILD) && skin_guard(c);
+}
+
 StepArgs step_args(pd_ctx* c) {
   StepArgs A{};
   A.ucur = c->u4[c->cur];
@@ -398,10 +404,14 @@ ContactArgs contact_args(pd_ctx* c, int buf) {
 pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) {
   Range r("pd step: enqueue one step");
   const int nxt = c->cur ^ 1;
+  const bool watch = early_rebuilds(c);
   if (s % c->rebuild_every == 0) {
     Range rr("pd step: contact rebuild");
     ContactArgs C = contact_args(c, nxt);
-    HIPCHK(c, launch_contact_rebuild(C, skin_guard(c), c->stream));
+    // with the watch every evaluation since the last rebuild was checked
+    HIPCHK(c, launch_contact_rebuild(C, watch ? 0 : skin_guard(c), c->stream));
+  } else if (watch) {
+    HIPCHK(c, launch_skin_watch(contact_args(c, nxt), c->halt, c->stream));
   }
   c->cur = nxt;  // the drifted positions are the current ones now
   StepArgs A = step_args(c);
@@ -430,6 +440,24 @@ pd_status enqueue_step_ev(pd_ctx* c, int64_t s, hipEvent_t ev0, hipEvent_t ev1) 
     HIPCHK(c, launch_step_spb(A, c->launch.slices_per_block, c->stream, ev0, ev1));
   }
   HIPCHK(c, launch_wall_finalize(A, c->stream));
+  return PD_OK;
+}
+
+// PD_FLAG_ADAPTIVE_REBUILD: the watch halted step done + 1 before its
+// evaluation; rebuild the list at the positions that evaluation uses (the ones
+// the watch saw), clear the flags, and let pd_step go on from there
+pd_status early_rebuild(pd_ctx* c) {
+  Range r("pd step: early contact rebuild");
+  int64_t done = 0;
+  HIPCHK(c, hipMemcpyAsync(&done, c->step_d, sizeof(int64_t), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemsetAsync(c->status, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipMemsetAsync(c->halt, 0, sizeof(uint32_t), c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  c->step = done;
+  c->cur = (int)(done & 1);  // u4[step % 2] holds u_step, the other buffer the next positions
+  ContactArgs C = contact_args(c, c->cur ^ 1);
+  HIPCHK(c, launch_contact_rebuild(C, 0, c->stream));
+  c->counts[5] += 1;
   return PD_OK;
 }
 
@@ -550,6 +578,7 @@ pd_status report_status(pd_ctx* c) {
   if (st & ST_SKIN) why += " displacement since the last candidate rebuild exceeded skin/2;";
   if (st & ST_CAND_OVERFLOW) why += " contact candidate capacity exceeded;";
   if (st & ST_BARRIER) why += " a grid barrier of the persistent step loop timed out;";
+  if (st & ST_REBUILD) why += " an early candidate rebuild was pending;";
   return fail(c, PD_ERR_UNSTABLE, "instability flagged:%s", why.c_str());
 }
 
@@ -928,7 +957,7 @@ pd_status pd_init(pd_ctx** out, const pd_grains* grains, const pd_mesh* mesh,
   if (!(P.friction >= 0) || !isfinite(P.friction))
     return fail(c, PD_ERR_INVALID, "friction must be finite and >= 0");
   if (P.flags & ~(PD_FLAG_TABLE_LITERAL | PD_FLAG_ABS_STRETCH | PD_FLAG_NO_GRAPH | PD_FLAG_CONIC |
-                  PD_FLAG_SELF_CONTACT | PD_FLAG_WALL_CORNERS))
+                  PD_FLAG_SELF_CONTACT | PD_FLAG_WALL_CORNERS | PD_FLAG_ADAPTIVE_REBUILD))
     return fail(c, PD_ERR_INVALID, "unknown flag bits 0x%x", P.flags);
   for (int32_t w = 0; w < n_walls; ++w) TRY(check_wall(c, walls[w], w));
 
@@ -1347,6 +1376,8 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
   if (!c->built) return fail(c, PD_ERR_STATE, "pd_build_bonds must come first");
   if (n_steps < 0) return fail(c, PD_ERR_INVALID, "n_steps < 0");
   int64_t left = n_steps;
+  const int64_t step0 = c->step;
+  const bool watch = early_rebuilds(c);
   while (left > 0 && c->launch.loop == PD_LOOP_PERSISTENT) {
     hipEvent_t e0, e1;
     TRY(next_events(c, &e0, &e1));
@@ -1375,6 +1406,18 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
       left -= 1;
       c->counts[2] += 1;
     }
+    // the watch's flag is read once per captured run (or run of direct steps
+    // up to the next multiple of its length)
+    if (watch && (aligned || c->step % c->graph_len == 0 || left == 0)) {
+      uint32_t st = 0;
+      TRY(read_status(c, &st));
+      if (st == ST_REBUILD) {
+        TRY(early_rebuild(c));
+        left = n_steps - (c->step - step0);
+      } else if (st) {
+        break;
+      }
+    }
   }
   return report_status(c);
 }
@@ -1385,6 +1428,8 @@ pd_status pd_set_launch(pd_ctx* c, const pd_launch* l) {
     return fail(c, PD_ERR_INVALID, "unknown step loop %d", l->loop);
   if (l->loop == PD_LOOP_PERSISTENT && (c->flags & PD_FLAG_WALL_CORNERS))
     return fail(c, PD_ERR_UNSUPPORTED, "wall corners need the per-evaluation corner pass: no persistent loop");
+  if (l->loop == PD_LOOP_PERSISTENT && (c->flags & PD_FLAG_ADAPTIVE_REBUILD))
+    return fail(c, PD_ERR_UNSUPPORTED, "early candidate rebuilds need a host decision between steps: no persistent loop");
   const int spb = l->slices_per_block;
   if (!(spb == 1 || spb == 2 || spb == 4 || spb == 8))
     return fail(c, PD_ERR_INVALID, "slices_per_block must be 1, 2, 4 or 8");
@@ -1450,9 +1495,9 @@ pd_status pd_tile_info(pd_ctx* c, int64_t* n_tiles, int32_t* lattice) {
   return PD_OK;
 }
 
-pd_status pd_loop_counts(pd_ctx* c, int64_t* out5) {
-  if (!c || !out5) return PD_ERR_INVALID;
-  for (int k = 0; k < 5; ++k) out5[k] = c->counts[k];
+pd_status pd_loop_counts(pd_ctx* c, int64_t* out6) {
+  if (!c || !out6) return PD_ERR_INVALID;
+  for (int k = 0; k < 6; ++k) out6[k] = c->counts[k];
   return PD_OK;
 }
 

@@ -124,6 +124,7 @@ enum : uint32_t {
   ST_SKIN = 4u,
   ST_CAND_OVERFLOW = 8u,
   ST_BARRIER = 16u,  // a grid-barrier wait of the persistent kernel gave up
+  ST_REBUILD = 32u,  // early-rebuild watch: a node moved skin/2; the step was not taken
 };
 
 enum ForceMode { MODE_FIRST = 0, MODE_STEP = 1, MODE_FORCE_ONLY = 2 };
@@ -299,6 +300,7 @@ int32_t step_blocks_spb(int64_t nslices, int slices_per_block);
 hipError_t launch_wall_finalize(const StepArgs& a, hipStream_t s);
 
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s);
+hipError_t launch_skin_watch(const ContactArgs& c, uint32_t* halt, hipStream_t s);
 hipError_t launch_energy(const StepArgs& a, double* partial4, int32_t nblocks, hipStream_t s);
 hipError_t launch_reduce_energy(const double* partial4, int32_t nblocks, double* out4,
                                 hipStream_t s);

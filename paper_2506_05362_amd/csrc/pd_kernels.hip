@@ -2005,6 +2005,28 @@ hipError_t launch_step_persistent(const StepArgs& a, int64_t nsteps, int32_t nbl
                                     (unsigned)step_lds(a), s);
 }
 
+// early-rebuild watch, before an evaluation between cadence rebuilds: a node
+// beyond skin/2 of where the list was built may have a partner within R_c
+// that the list lacks.  The flag halts this step and the ones after it (the
+// step kernel and the wall pass see the halt word), so the host can rebuild
+// the list at these positions and go on from the same step.
+__global__ void k_skin_watch(ContactArgs c, uint32_t* halt) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= c.n || halted(c.halt)) return;
+  const double4 u = c.u[i];
+  const double dx = u.x - c.u_build[i], dy = u.y - c.u_build[c.n + i], dz = u.z - c.u_build[2 * c.n + i];
+  if (dx * dx + dy * dy + dz * dz > c.skin_half2) {
+    atomicOr(c.status, ST_REBUILD);
+    atomicOr(halt, ST_REBUILD);
+  }
+}
+
+hipError_t launch_skin_watch(const ContactArgs& c, uint32_t* halt, hipStream_t s) {
+  if (c.n == 0) return hipSuccess;
+  hipLaunchKernelGGL(k_skin_watch, dim3(grid_for(c.n, 256)), dim3(256), 0, s, c, halt);
+  return hipGetLastError();
+}
+
 hipError_t launch_contact_rebuild(const ContactArgs& c, int check_skin, hipStream_t s) {
   if (c.n == 0) return hipSuccess;
   const unsigned g = grid_for(c.n, 256);

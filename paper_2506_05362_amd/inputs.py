@@ -443,7 +443,8 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
                   platen_speed: float = 10.0, axial_strain: float = 0.05,
                   servo_gain: float = 5e-7, gap_factor: float = 0.0, material: Material = SAND,
                   rebuild_every: int = 20, min_grain_nodes: int = 20,
-                  contact_damping: float = 0.0, friction: float = 0.0, skin_factor: float = 0.25) -> Workload:
+                  contact_damping: float = 0.0, friction: float = 0.0, skin_factor: float = 0.25,
+                  adaptive_rebuild: bool = False) -> Workload:
     """A dense aggregate of polyhedral grains filling a box, confined by six walls.
 
     The grains are the cells of a Voronoi tessellation of hard-core random
@@ -463,6 +464,7 @@ def rve_aggregate(seed: int = 0, n_grains: int = 200, nodes_per_grain: float = 1
     params.contact_damping = contact_damping
     params.friction = friction
     params.skin = skin_factor * h
+    params.adaptive_rebuild = adaptive_rebuild
     Rc = params.contact_radius
     g = gap_factor * Rc
     n_side = int(math.ceil((n_grains * nodes_per_grain) ** (1.0 / 3.0)))

@@ -24,6 +24,7 @@ PD_OK, PD_ERR_INVALID, PD_ERR_STATE, PD_ERR_OOM, PD_ERR_HIP, PD_ERR_UNSTABLE = 0
 PD_ERR_UNSUPPORTED, PD_ERR_CORRUPT = -6, -7
 FLAG_TABLE_LITERAL, FLAG_ABS_STRETCH, FLAG_NO_GRAPH, FLAG_CONIC, FLAG_SELF_CONTACT = 1, 2, 4, 8, 16
 FLAG_WALL_CORNERS = 32
+FLAG_ADAPTIVE_REBUILD = 64
 
 FIELDS = dict(displacement=0, velocity=1, accel=2, force_density=3, damage=4, intact_count=5,
               initial_count=6, bond_rowptr=7, bond_col=8, bond_broken=9, contact_rowptr=10,
@@ -260,6 +261,8 @@ class Sim:
             prm.flags |= FLAG_SELF_CONTACT
         if getattr(p, "wall_corners", False):
             prm.flags |= FLAG_WALL_CORNERS
+        if getattr(p, "adaptive_rebuild", False):
+            prm.flags |= FLAG_ADAPTIVE_REBUILD
         prm.contact_radius = p.contact_radius
         prm.contact_horizon = p.contact_horizon
         prm.skin = p.skin
@@ -344,10 +347,10 @@ class Sim:
         return dict(tiles=n.value, lattice=bool(lat.value))
 
     def loop_counts(self) -> dict:
-        o = np.zeros(5, dtype=np.int64)
+        o = np.zeros(6, dtype=np.int64)
         self._check(lib().pd_loop_counts(self.h, _ptr(o)))
         return dict(graph_replays=int(o[0]), graph_steps=int(o[1]), direct_steps=int(o[2]),
-                    persistent_launches=int(o[3]), persistent_steps=int(o[4]))
+                    persistent_launches=int(o[3]), persistent_steps=int(o[4]), early_rebuilds=int(o[5]))
 
     def set_launch(self, loop: int = LOOP_GRAPH, slices_per_block: int = 4, xcd_remap: int = 1,
                    persistent_blocks: int = 0, bond_path: int = BONDS_SLICES):

@@ -39,8 +39,9 @@ DIMS = [6, 256, 256, 256, 7]
 OUT_NAMES = ["s_xx", "s_yy", "s_zz", "s_yz", "s_xz", "s_xy", "damage"]
 AXIAL = 2  # index of s_zz
 # Contact candidates per node the simulations reserve: past the peak, crushed
-# grains pack fragments within R_c + skin of a node from several sides.
-SIM_CAPACITY = 48
+# grains pack fragments within R_c + skin of a node from several sides (at
+# 48, four of 64 paths at 15-20 MPa filled the list between 3.5% and 4.9%).
+SIM_CAPACITY = 96
 
 
 @dataclasses.dataclass
@@ -78,10 +79,11 @@ def simulate_path(wl, n_log: int = 400, log=None, capacity: int = SIM_CAPACITY) 
 
     Returns strain (T, 6), target (T, 7) = stress and damage, t (T,), the
     wall-clock seconds of the whole simulation (context set up, bonds built,
-    every step run and logged) and the steps run.  When the simulator flags a
-    step chunk (past the peak the brittle aggregate can shatter and single
-    nodes outrun the contact skin), the path ends at the last good log point
-    and is marked truncated.
+    every step run and logged), the steps run and the early candidate
+    rebuilds.  When the simulator flags a step chunk (a non-finite force, a
+    node through a wall, a full candidate list, or without early rebuilds a
+    node that outran the contact skin), the path ends at the last good log
+    point and is marked truncated.
     """
     import torch
     from . import pd
@@ -127,10 +129,11 @@ def simulate_path(wl, n_log: int = 400, log=None, capacity: int = SIM_CAPACITY) 
         target.append(s)
         times.append(done * wl.params.dt)
     seconds = time.perf_counter() - t0
+    early = sim.loop_counts()["early_rebuilds"]
     sim.close()
     return {"strain": np.array(strain).reshape(-1, 6), "target": np.array(target).reshape(-1, 7),
             "t": np.array(times), "seconds": seconds, "nodes": wl.n_nodes, "bonds": nnz,
-            "steps_run": done, "steps": wl.steps, "truncated": truncated}
+            "steps_run": done, "steps": wl.steps, "truncated": truncated, "early_rebuilds": early}
 
 
 def _make_rve(args):
@@ -156,7 +159,8 @@ def generate(specs: List[PathSpec], n_log: int = 400, log=print, workers: int = 
             last = (f"e_zz {r['strain'][-1, AXIAL] * 100:.2f} % s_zz {r['target'][-1, AXIAL] / 1e6:.2f} MPa "
                     f"D {r['target'][-1, 6]:.4f}") if len(r["t"]) else "no samples"
             log(f"path {k}: seed {sp.seed} conf {sp.confinement / 1e6:.2f} MPa nodes {wl.n_nodes} "
-                f"bonds {r['bonds']} steps {r['steps_run']}/{r['steps']} {tag} sim {r['seconds']:.2f} s; "
+                f"bonds {r['bonds']} steps {r['steps_run']}/{r['steps']} {tag} "
+                f"early rebuilds {r['early_rebuilds']} sim {r['seconds']:.2f} s; "
                 f"end {last}")
             if len(r["t"]) >= 2:
                 res.append(r)
@@ -171,6 +175,7 @@ def generate(specs: List[PathSpec], n_log: int = 400, log=print, workers: int = 
             "steps_run": np.array([r["steps_run"] for r in res]),
             "steps": np.array([r["steps"] for r in res]),
             "truncated": np.array([r["truncated"] for r in res]),
+            "early_rebuilds": np.array([r["early_rebuilds"] for r in res], dtype=np.int64),
             "nodes": np.array([r["nodes"] for r in res]), "bonds": np.array([r["bonds"] for r in res]),
             "confinement": np.array([sp.confinement for sp in kept]),
             "seed": np.array([sp.seed for sp in kept]),
@@ -402,10 +407,10 @@ def time_inference(sur: Surrogate, paths: np.ndarray, reps: int = 3) -> Dict:
 # The servo gain caps the lateral walls' speed near the platen's (gain * 20 MPa
 # = 1 m/s).  Paths run to 5% axial strain, well past the peak; candidate lists
 # are rebuilt every 10 steps with a skin of h/2, so a node may move at up to
-# 250 m/s between rebuilds (past the peak single detached nodes are thrown off
-# faster than the 125 m/s an h/4 skin allows).
+# 250 m/s between rebuilds, and earlier for the single detached nodes thrown
+# off faster than that past the peak (a rebuild as soon as one has moved h/4).
 RVE_DEFAULTS = dict(platen_speed=1.0, contact_damping=2.8e22, servo_gain=5e-8, rebuild_every=10,
-                    axial_strain=0.05, skin_factor=0.5)
+                    axial_strain=0.05, skin_factor=0.5, adaptive_rebuild=True)
 
 
 def load_data(files: List[str]) -> Dict[str, np.ndarray]:
@@ -417,8 +422,9 @@ def load_data(files: List[str]) -> Dict[str, np.ndarray]:
     if len(parts) == 1:
         return parts[0]
     flat = ("strain", "target", "t")
-    per_path = ("seconds", "steps_run", "steps", "truncated", "nodes", "bonds", "confinement", "seed")
-    out = {k: np.concatenate([d[k] for d in parts]) for k in flat + per_path}
+    per_path = ("seconds", "steps_run", "steps", "truncated", "nodes", "bonds", "confinement", "seed",
+                "early_rebuilds")
+    out = {k: np.concatenate([d[k] for d in parts]) for k in flat + per_path if all(k in d for d in parts)}
     lens = np.concatenate([np.diff(d["offsets"]) for d in parts])
     out["offsets"] = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
     out["dropped"] = np.concatenate([d["dropped"] for d in parts]).astype(np.int64)
@@ -436,7 +442,8 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
         data = generate(path_specs(n_paths, seed=seed)[only[0]:only[1]], n_log=n_log, log=log, **rve_kw)
         res = {"paths": f"{only[0]}:{only[1]} of {n_paths}", "rve": dict(rve_kw),
                "generate_seconds": time.perf_counter() - t0, "paths_used": len(data["offsets"]) - 1,
-               "paths_truncated": int(np.sum(data["truncated"]))}
+               "paths_truncated": int(np.sum(data["truncated"])),
+               "early_rebuilds": int(np.sum(data["early_rebuilds"]))}
         if out:
             with open(out, "w") as f:
                 json.dump(res, f, indent=1)
@@ -467,6 +474,7 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
     res = {
         "paths": n_paths, "paths_used": n_ok, "paths_dropped": data["dropped"].tolist(),
         "paths_truncated": int(np.sum(data["truncated"])), "held_out": n_held,
+        "early_rebuilds": int(np.sum(data["early_rebuilds"])) if "early_rebuilds" in data else None,
         "samples": int(len(data["t"])), "rve": {k: v for k, v in rve_kw.items()},
         "nodes_mean": float(np.mean(data["nodes"])), "bonds_mean": float(np.mean(data["bonds"])),
         "steps_per_path": int(np.max(data["steps"])),

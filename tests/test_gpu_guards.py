@@ -1,6 +1,7 @@
 """GPU tests of the library's guard paths and the remaining state paths: the
 instability flags (Verlet skin, candidate capacity, non-finite force) halt the
-run at the step that raised them, fixed nodes, and pd_get into device memory."""
+run at the step that raised them, early candidate rebuilds in their place,
+fixed nodes, and pd_get into device memory."""
 import zlib
 
 import numpy as np
@@ -8,7 +9,7 @@ import pytest
 
 from paper_2506_05362_amd import inputs as I
 from test_gpu_parity import assert_state_close, rel_inf
-from test_oracle_margins_guards import _drifting_node
+from test_oracle_margins_guards import _drifting_node, _fast_collision
 
 pytestmark = pytest.mark.gpu
 
@@ -43,6 +44,57 @@ def test_skin_guard_halts_at_the_flagged_step(oracle_lib, frac):
     assert_state_close(sim, ora, what=f"skin {frac}")
     # the flag was cleared when reported: stepping on is allowed again
     assert sim.step_status(1) in (pd.PD_OK, pd.PD_ERR_UNSTABLE)
+    sim.close()
+
+
+@pytest.mark.parametrize("loop,bond_path", [(0, 0), (1, 0), (3, 0), (0, 1), (1, 1)])
+def test_early_rebuilds_match_the_oracle(oracle_lib, loop, bond_path):
+    """Two balls closing at 50 m/s (skin/2 in 25 steps) with a cadence of 100
+    steps: without early rebuilds the call stops at step 100 on the skin
+    guard; with them all 300 steps run, in every step loop and bond path, and
+    the state matches the oracle taking the same early rebuilds."""
+    from paper_2506_05362_amd import pd
+    plain = gpu_sim(_fast_collision(100, False))
+    plain.set_launch(loop=loop, bond_path=bond_path)
+    assert plain.step_status(300) == pd.PD_ERR_UNSTABLE
+    assert plain.info()["step"] == 100
+    plain.close()
+    wl = _fast_collision(100, True)
+    sim = gpu_sim(wl)
+    sim.set_launch(loop=loop, bond_path=bond_path)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=8)
+    for _ in range(3):
+        sim.step(100)
+        assert ora.step(100) == 0
+    assert sim.info()["step"] == 300
+    assert_state_close(sim, ora, what=f"early rebuilds, loop {loop}, bonds {bond_path}")
+    n = sim.loop_counts()["early_rebuilds"]
+    # a displacement within rounding of skin/2 may be decided either way; one
+    # rebuild more or less does not change the forces
+    assert n > 0 and abs(n - ora.early_rebuilds()) <= 1, (n, ora.early_rebuilds())
+    sim.close()
+
+
+def test_early_rebuilds_equal_a_rebuild_every_step_bitwise():
+    """The forces do not depend on when the candidates were built, only on
+    their holding every pair within R_c: early rebuilds give bitwise the state
+    of a rebuild before every evaluation."""
+    early = gpu_sim(_fast_collision(100, True))
+    every = gpu_sim(_fast_collision(1, False))
+    early.step(300)
+    every.step(300)
+    assert early.loop_counts()["early_rebuilds"] > 0 and every.loop_counts()["early_rebuilds"] == 0
+    for name in ("displacement", "velocity", "accel", "force_density", "damage"):
+        assert np.array_equal(early.get(name), every.get(name)), name
+    early.close()
+    every.close()
+
+
+def test_early_rebuilds_refuse_the_persistent_loop():
+    from paper_2506_05362_amd import pd
+    sim = gpu_sim(_fast_collision(100, True))
+    with pytest.raises(pd.PDError, match="persistent"):
+        sim.set_launch(loop=pd.LOOP_PERSISTENT)
     sim.close()
 
 
