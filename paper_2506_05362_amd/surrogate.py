@@ -321,6 +321,31 @@ def ensemble_prediction(data, p: int, train: np.ndarray, k: int = 4) -> np.ndarr
                     for q in near], axis=0)
 
 
+def pair_scatter(data, paths: np.ndarray) -> Dict:
+    """The scatter between aggregates loaded alike, from the simulated paths
+    alone: sorted by confinement, each neighbouring pair's relative L2
+    difference of the axial stress along their common axial strains (the norm
+    of the difference over the root mean square of the two paths' norms).  If
+    every path deviates independently from one function of strain and
+    confinement, one path lies about 1/sqrt(2) of that difference from it: an
+    error no predictor of the loading alone gets below."""
+    conf = np.asarray(data["confinement"])
+    paths = np.asarray(paths)
+    order = paths[np.argsort(conf[paths], kind="stable")]
+    diffs, gaps = [], []
+    for p, q in zip(order[:-1], order[1:]):
+        ea, a = path(data, int(p), "strain")[:, AXIAL], path(data, int(p), "target")[:, AXIAL]
+        eb, b = path(data, int(q), "strain")[:, AXIAL], path(data, int(q), "target")[:, AXIAL]
+        keep = ea <= eb.max()  # a path stopped early covers fewer strains
+        a, b = a[keep], np.interp(ea[keep], eb, b)
+        norm = np.sqrt(0.5 * (np.dot(a, a) + np.dot(b, b)))
+        diffs.append(float(np.linalg.norm(a - b) / max(norm, 1e-300)))
+        gaps.append(float(abs(conf[p] - conf[q])))
+    d = float(np.mean(diffs))
+    return {"pair_axial_rel_l2_mean": d, "pair_confinement_gap_mean": float(np.mean(gaps)),
+            "single_path_scatter": d / math.sqrt(2.0)}
+
+
 def evaluate(sur: "Surrogate", data, held: np.ndarray, train: np.ndarray, prepeak_strain: float = 0.025) -> Dict:
     """Per held-out path: relative L2 error of the axial stress along the path,
     for the network, the interpolation baseline and the confinement ensemble
@@ -480,7 +505,8 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
         "steps_per_path": int(np.max(data["steps"])),
         "generate_seconds": gen_s, "sim_seconds_per_path": sim_per_path,
         "train_seconds": train_s, "train_steps": train_steps, "final_loss": losses[-1],
-        **ev, "inference": inf, "inference_inside_envelope": inside,
+        **ev, "scatter_of_training_paths": pair_scatter(data, train),
+        "inference": inf, "inference_inside_envelope": inside,
         "speedup_per_path": sim_per_path / inf["seconds_per_path"],
         "paths_simulated_in_inference_time": inf["seconds"] / sim_per_path,
     }
@@ -510,12 +536,20 @@ def main(argv=None):
                          "instead of simulating")
     ap.add_argument("--only", default=None, metavar="A:B",
                     help="only simulate paths A..B-1 of the --paths set and save them (no training)")
+    ap.add_argument("--scatter", default=None, metavar="NPZ[,NPZ...]",
+                    help="only print the scatter between neighbouring-confinement paths of saved data "
+                         "(all but the last --held paths) and exit; runs on the host alone")
     ap.add_argument("--time-path", type=int, default=0, metavar="STEPS",
                     help="only time STEPS steps (after as many warm-up steps) of path 1 and exit")
     ap.add_argument("--time-inference", type=int, default=0, metavar="PATHS",
                     help="only time inference of PATHS random strain paths x 100 points with the "
                          "fused and the layer-by-layer kernels (random weights) and exit")
     a = ap.parse_args(argv)
+    if a.scatter:
+        data = load_data(a.scatter.split(","))
+        n_ok = len(data["offsets"]) - 1
+        print(json.dumps(pair_scatter(data, np.arange(0, n_ok - a.held))), flush=True)
+        return
     if a.time_inference:
         rng = np.random.default_rng(0)
         sur = Surrogate()
