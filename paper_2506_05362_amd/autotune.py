@@ -106,9 +106,10 @@ def tune(sim: "pd.Sim", steps: Optional[int] = None, use_cache: bool = True,
     path = path or cache_path()
     info = sim.info()
     key = shape_key(_arch(), info["n_nodes"], info["nnz"], np.diff(sim.wl.grain_begin))
-    # the wall-corner pass runs before every evaluation, which one persistent
-    # launch of several steps cannot host
-    if getattr(sim.wl.params, "wall_corners", False):
+    # the wall-corner pass runs before every evaluation, and an early candidate
+    # rebuild is decided on the host between steps: one persistent launch of
+    # several steps can host neither
+    if getattr(sim.wl.params, "wall_corners", False) or getattr(sim.wl.params, "adaptive_rebuild", False):
         persistent = False
     table = _load(path) if use_cache else {}
     if use_cache and key in table and (persistent or table[key]["config"]["loop"] != pd.LOOP_PERSISTENT):
