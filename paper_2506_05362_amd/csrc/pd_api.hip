@@ -1378,7 +1378,9 @@ pd_status pd_step(pd_ctx* c, int64_t n_steps) {
   int64_t left = n_steps;
   const int64_t step0 = c->step;
   const bool watch = early_rebuilds(c);
-  while (left > 0 && c->launch.loop == PD_LOOP_PERSISTENT) {
+  // (a mesh without nodes has no workgroup to carry the walls through a
+  // persistent launch: its steps take the launches below)
+  while (left > 0 && c->launch.loop == PD_LOOP_PERSISTENT && c->nslices > 0) {
     hipEvent_t e0, e1;
     TRY(next_events(c, &e0, &e1));
     int64_t k = 0;
