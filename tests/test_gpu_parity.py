@@ -661,6 +661,41 @@ def test_notched_plate_full_size_in_the_bench_configuration(oracle_lib):
 
 
 @pytest.mark.timeout(900)
+def test_large_aggregate_full_size_in_the_bench_configuration(oracle_lib):
+    """The benchmark's workload at full size (999 grains on one lattice,
+    9,261,000 nodes, 967,622,492 directed bonds, six walls) in the launch
+    sequence the benchmark times: lattice-mode tiles, 60 steps of graph replay,
+    then 40 direct launches bracketed by events.  After those 100 steps every
+    node's u, v, a and F lie within 1e-9 of the oracle and the walls' reactions
+    within 1e-6; the bond lists, broken sets, intact counts and damage are
+    compared in full (no bond breaks this early in the compression; breaking at
+    full size is checked on the plate)."""
+    from paper_2506_05362_amd import pd
+    wl = I.large_aggregate()
+    sim = gpu_sim(wl)
+    sim.set_launch(loop=pd.LOOP_GRAPH, bond_path=pd.BONDS_TILES)
+    assert sim.tile_info()["lattice"]
+    sim.step(60)
+    sim.set_timing(True)
+    sim.step(40)
+    launches, ms = sim.timing()
+    sim.set_timing(False)
+    assert launches == 40 and ms > 0
+    assert sim.loop_counts()["graph_steps"] == 60
+    print(f"gpu done: {ms / launches * 1e3:.1f} us per step kernel", flush=True)
+    ora = oracle_lib.Oracle(wl, flags=oracle_lib.CELL_LIST, threads=16)
+    for k in range(5):
+        assert ora.step(20) == 0
+        print(f"oracle step {ora.step_count}", flush=True)
+    assert_state_close(sim, ora, what="full-size large aggregate")
+    fo, _ = ora.walls()
+    assert np.abs(fo).max() > 0  # the platen and the walls carry load
+    assert rel_inf(sim.get("wall_force"), fo) <= 1e-6
+    assert_bonds_equal(sim, ora)
+    sim.close()
+
+
+@pytest.mark.timeout(900)
 def test_uneven_aggregate_full_size_matches_oracle(oracle_lib):
     """The uneven-grain aggregate at full size (100 grains of 2e3-5e4 nodes,
     1.72 M nodes) in the batched graph-replayed launch: after 100 steps state
