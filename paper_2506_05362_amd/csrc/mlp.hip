@@ -199,13 +199,17 @@ __global__ void k_adam(float* p, const float* g, float* m, float* v, int64_t n, 
 // small per-wavefront LDS tile, so layer 4 runs on the matrix cores as it goes.
 // Operands are rounded to BF16 exactly where the layer-by-layer path rounds
 // them (x, W1, activations, W2..W4); accumulation is FP32.
-// Each workgroup keeps a weight matrix in LDS and walks 64-row tiles of the
-// batch (4 wavefronts x 16 rows).
+// Each workgroup keeps a weight matrix in LDS and walks tiles of 16 rows per
+// wavefront.  The weights fill most of a CU's LDS, so one workgroup runs per
+// CU: eight wavefronts (two per SIMD) let one hide the latency of the other's
+// vector work (the exact-erf GELUs) and matrix-core chains.
 // ---------------------------------------------------------------------------
 
 constexpr int kH = 256;          // hidden width of the fused path
 constexpr int kWRow = kH + 8;    // LDS row of a transposed weight matrix (bf16), padded, 16-byte aligned
 constexpr int kTRow = 32 + 8;    // per-wavefront transpose tile row (bf16)
+constexpr int kIW = 8;           // wavefronts per workgroup
+constexpr int kIRows = 16 * kIW;  // batch rows per tile
 
 __device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
 
@@ -242,7 +246,7 @@ __device__ __forceinline__ void stage_weights_t(const short* src, int rows, shor
 }
 
 template <int DINP>
-__global__ __launch_bounds__(256) void k_infer_a(Infer a) {
+__global__ __launch_bounds__(64 * kIW) void k_infer_a(Infer a) {
   extern __shared__ __align__(16) char smem[];
   short* sW = reinterpret_cast<short*>(smem);                                   // [kH][kWRow]
   float* sW1 = reinterpret_cast<float*>(smem + sizeof(short) * kH * kWRow);     // [16][kH]
@@ -250,16 +254,16 @@ __global__ __launch_bounds__(256) void k_infer_a(Infer a) {
   float* sb2 = sb1 + kH;
   const int tid = threadIdx.x;
   stage_weights_t(a.W2t, kH, sW);
-  for (int i = tid; i < 16 * kH; i += 256) sW1[i] = i < a.din * kH ? bf16_to_f(to_bf16(a.W1[i])) : 0.0f;
-  for (int i = tid; i < kH; i += 256) {
+  for (int i = tid; i < 16 * kH; i += blockDim.x) sW1[i] = i < a.din * kH ? bf16_to_f(to_bf16(a.W1[i])) : 0.0f;
+  for (int i = tid; i < kH; i += blockDim.x) {
     sb1[i] = a.b1[i];
     sb2[i] = a.b2[i];
   }
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
-  const int64_t ntiles = (a.M + 63) / 64;
+  const int64_t ntiles = (a.M + kIRows - 1) / kIRows;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t r0 = t * 64 + wv * 16;
+    const int64_t r0 = t * kIRows + wv * 16;
     const int64_t row = r0 + lr;
     float xv[DINP];
 #pragma unroll
@@ -298,25 +302,25 @@ __global__ __launch_bounds__(256) void k_infer_a(Infer a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_infer_b(Infer a) {
+__global__ __launch_bounds__(64 * kIW) void k_infer_b(Infer a) {
   extern __shared__ __align__(16) char smem[];
   short* sW = reinterpret_cast<short*>(smem);                  // [kH][kWRow]
   short* sW4 = sW + kH * kWRow;                                // [16][kWRow]
-  short* sT = sW4 + 16 * kWRow;                                // [4][16][kTRow]
+  short* sT = sW4 + 16 * kWRow;                                // [kIW][16][kTRow]
   static_assert((kWRow * 2) % 16 == 0 && (kTRow * 2) % 16 == 0, "16-byte LDS rows");
-  float* sb3 = reinterpret_cast<float*>(sT + 4 * 16 * kTRow);  // [kH]
+  float* sb3 = reinterpret_cast<float*>(sT + kIW * 16 * kTRow);  // [kH]
   float* sb4 = sb3 + kH;                                       // [16]
   const int tid = threadIdx.x;
   stage_weights_t(a.W3t, kH, sW);
   stage_weights_t(a.W4t, 16, sW4);
-  for (int i = tid; i < kH; i += 256) sb3[i] = a.b3[i];
+  for (int i = tid; i < kH; i += blockDim.x) sb3[i] = a.b3[i];
   if (tid < 16) sb4[tid] = tid < a.dout ? a.b4[tid] : 0.0f;
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
   short* T = sT + wv * 16 * kTRow;
-  const int64_t ntiles = (a.M + 63) / 64;
+  const int64_t ntiles = (a.M + kIRows - 1) / kIRows;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
-    const int64_t r0 = t * 64 + wv * 16;
+    const int64_t r0 = t * kIRows + wv * 16;
     const int64_t row = r0 + lr;
     v4f acc[16];
 #pragma unroll
@@ -357,7 +361,7 @@ __global__ __launch_bounds__(256) void k_infer_b(Infer a) {
 }
 
 constexpr size_t kLdsA = sizeof(short) * kH * kWRow + sizeof(float) * (16 * kH + 2 * kH);
-constexpr size_t kLdsB = sizeof(short) * (kH * kWRow + 16 * kWRow + 4 * 16 * kTRow) + sizeof(float) * (kH + 16);
+constexpr size_t kLdsB = sizeof(short) * (kH * kWRow + 16 * kWRow + kIW * 16 * kTRow) + sizeof(float) * (kH + 16);
 
 }  // namespace
 
@@ -669,11 +673,11 @@ pd_status pdm_forward(pdm_net* n, const float* x, int64_t batch, float* y) {
       a.b4 = n->params + n->boff[3];
       a.H2 = n->H2;
       a.y = y + b0 * dout;
-      const int64_t tiles = (cb + 63) / 64;
+      const int64_t tiles = (cb + kIRows - 1) / kIRows;
       const unsigned grid = (unsigned)std::min<int64_t>(tiles, std::max(n->cus, 1));
-      if (din <= 8) hipLaunchKernelGGL(k_infer_a<8>, dim3(grid), dim3(256), kLdsA, n->stream, a);
-      else hipLaunchKernelGGL(k_infer_a<16>, dim3(grid), dim3(256), kLdsA, n->stream, a);
-      hipLaunchKernelGGL(k_infer_b, dim3(grid), dim3(256), kLdsB, n->stream, a);
+      if (din <= 8) hipLaunchKernelGGL(k_infer_a<8>, dim3(grid), dim3(64 * kIW), kLdsA, n->stream, a);
+      else hipLaunchKernelGGL(k_infer_a<16>, dim3(grid), dim3(64 * kIW), kLdsA, n->stream, a);
+      hipLaunchKernelGGL(k_infer_b, dim3(grid), dim3(64 * kIW), kLdsB, n->stream, a);
       HIPCHK(n, hipGetLastError());
     }
   } else {
