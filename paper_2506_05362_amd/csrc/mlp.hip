@@ -211,6 +211,14 @@ constexpr int kTRow = 32 + 8;    // per-wavefront transpose tile row (bf16)
 constexpr int kIW = 8;           // wavefronts per workgroup
 constexpr int kIRows = 16 * kIW;  // batch rows per tile
 
+// Order the LDS accesses of one wavefront's lanes (all of them converged here):
+// writes before the call are seen by reads after it in every lane.
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 __device__ __forceinline__ float bf16_to_f(short h) { return __uint_as_float(((uint32_t)(uint16_t)h) << 16); }
 
 struct Infer {
@@ -346,11 +354,11 @@ __global__ __launch_bounds__(64 * kIW) void k_infer_b(Infer a) {
 #pragma unroll
         for (int e = 0; e < 4; ++e) T[(4 * lg + e) * kTRow + 16 * h + lr] = to_bf16(gelu(acc[q][e] + sb3[col]));
       }
-      __syncthreads();
+      wave_sync();  // T is this wavefront's own tile: no wait for the others
       const v8s a4 = *reinterpret_cast<const v8s*>(T + lr * kTRow + 8 * lg);
       const v8s b4 = *reinterpret_cast<const v8s*>(sW4 + lr * kWRow + q2 * 32 + 8 * lg);
       acc4 = mfma_16x16x32(a4, b4, acc4);
-      __syncthreads();
+      wave_sync();
     }
 #pragma unroll
     for (int e = 0; e < 4; ++e) {
