@@ -257,18 +257,20 @@ template <int DINP>
 __global__ __launch_bounds__(64 * kIW) void k_infer_a(Infer a) {
   extern __shared__ __align__(16) char smem[];
   short* sW = reinterpret_cast<short*>(smem);                                   // [kH][kWRow]
-  float* sW1 = reinterpret_cast<float*>(smem + sizeof(short) * kH * kWRow);     // [16][kH]
-  float* sb1 = sW1 + 16 * kH;
+  float* sW1 = reinterpret_cast<float*>(smem + sizeof(short) * kH * kWRow);     // [DINP][kH]
+  float* sb1 = sW1 + DINP * kH;
   float* sb2 = sb1 + kH;
+  short* sT = reinterpret_cast<short*>(sb2 + kH);                               // [kIW][16][kTRow]
   const int tid = threadIdx.x;
   stage_weights_t(a.W2t, kH, sW);
-  for (int i = tid; i < 16 * kH; i += blockDim.x) sW1[i] = i < a.din * kH ? bf16_to_f(to_bf16(a.W1[i])) : 0.0f;
+  for (int i = tid; i < DINP * kH; i += blockDim.x) sW1[i] = i < a.din * kH ? bf16_to_f(to_bf16(a.W1[i])) : 0.0f;
   for (int i = tid; i < kH; i += blockDim.x) {
     sb1[i] = a.b1[i];
     sb2[i] = a.b2[i];
   }
   __syncthreads();
   const int wv = tid >> 6, lane = tid & 63, lr = lane & 15, lg = lane >> 4;
+  short* T = sT + wv * 16 * kTRow;
   const int64_t ntiles = (a.M + kIRows - 1) / kIRows;
   for (int64_t t = blockIdx.x; t < ntiles; t += gridDim.x) {
     const int64_t r0 = t * kIRows + wv * 16;
@@ -298,14 +300,20 @@ __global__ __launch_bounds__(64 * kIW) void k_infer_a(Infer a) {
         acc[q] = mfma_16x16x32(A, b, acc[q]);
       }
     }
+    // GELU of each pair of 16 x 16 tiles through this wavefront's LDS tile,
+    // so that every lane stores 16 contiguous bytes of one row of H2
 #pragma unroll
-    for (int q = 0; q < 16; ++q) {
-      const int col = q * 16 + lr;
+    for (int q2 = 0; q2 < 8; ++q2) {
 #pragma unroll
-      for (int e = 0; e < 4; ++e) {
-        const int64_t rr = r0 + 4 * lg + e;
-        if (rr < a.M) a.H2[rr * kH + col] = to_bf16(gelu(acc[q][e] + sb2[col]));
+      for (int h = 0; h < 2; ++h) {
+        const int q = 2 * q2 + h, col = q * 16 + lr;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) T[(4 * lg + e) * kTRow + 16 * h + lr] = to_bf16(gelu(acc[q][e] + sb2[col]));
       }
+      wave_sync();
+      const v8s hv = *reinterpret_cast<const v8s*>(T + lr * kTRow + 8 * lg);
+      if (row < a.M) *reinterpret_cast<v8s*>(a.H2 + row * kH + q2 * 32 + 8 * lg) = hv;
+      wave_sync();
     }
   }
 }
@@ -368,7 +376,10 @@ __global__ __launch_bounds__(64 * kIW) void k_infer_b(Infer a) {
   }
 }
 
-constexpr size_t kLdsA = sizeof(short) * kH * kWRow + sizeof(float) * (16 * kH + 2 * kH);
+template <int DINP>
+constexpr size_t lds_a() {
+  return sizeof(short) * (kH * kWRow + kIW * 16 * kTRow) + sizeof(float) * (DINP * kH + 2 * kH);
+}
 constexpr size_t kLdsB = sizeof(short) * (kH * kWRow + 16 * kWRow + kIW * 16 * kTRow) + sizeof(float) * (kH + 16);
 
 }  // namespace
@@ -583,14 +594,14 @@ pd_status pdm_create(pdm_net** out, const int32_t* dims, int32_t n_dims, int64_t
   TRY(alloc(n, &n->yhat, max_batch * dims[L]));
   if (n_dims == 5 && dims[1] == kH && dims[2] == kH && dims[3] == kH && dims[0] <= 16 && dims[4] <= 16) {
     int dev = 0, lds = 0;
+    const size_t need_a = dims[0] <= 8 ? lds_a<8>() : lds_a<16>();
     if (hipGetDevice(&dev) == hipSuccess &&
         hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) == hipSuccess &&
         hipDeviceGetAttribute(&n->cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
-        (size_t)lds >= kLdsA && (size_t)lds >= kLdsB &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_a<8>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsA) == hipSuccess &&
-        hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_a<16>),
-                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsA) == hipSuccess &&
+        (size_t)lds >= need_a && (size_t)lds >= kLdsB &&
+        hipFuncSetAttribute(dims[0] <= 8 ? reinterpret_cast<const void*>(&k_infer_a<8>)
+                                         : reinterpret_cast<const void*>(&k_infer_a<16>),
+                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)need_a) == hipSuccess &&
         hipFuncSetAttribute(reinterpret_cast<const void*>(&k_infer_b),
                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)kLdsB) == hipSuccess) {
       TRY(alloc(n, &n->W2t, (int64_t)kH * kH));
@@ -683,8 +694,8 @@ pd_status pdm_forward(pdm_net* n, const float* x, int64_t batch, float* y) {
       a.y = y + b0 * dout;
       const int64_t tiles = (cb + kIRows - 1) / kIRows;
       const unsigned grid = (unsigned)std::min<int64_t>(tiles, std::max(n->cus, 1));
-      if (din <= 8) hipLaunchKernelGGL(k_infer_a<8>, dim3(grid), dim3(64 * kIW), kLdsA, n->stream, a);
-      else hipLaunchKernelGGL(k_infer_a<16>, dim3(grid), dim3(64 * kIW), kLdsA, n->stream, a);
+      if (din <= 8) hipLaunchKernelGGL(k_infer_a<8>, dim3(grid), dim3(64 * kIW), lds_a<8>(), n->stream, a);
+      else hipLaunchKernelGGL(k_infer_a<16>, dim3(grid), dim3(64 * kIW), lds_a<16>(), n->stream, a);
       hipLaunchKernelGGL(k_infer_b, dim3(grid), dim3(64 * kIW), kLdsB, n->stream, a);
       HIPCHK(n, hipGetLastError());
     }

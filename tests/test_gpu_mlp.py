@@ -106,6 +106,25 @@ def test_fused_inference_matches_emulation_and_layer_path():
         assert np.linalg.norm(ym - emu[:m]) <= 2e-4 * np.linalg.norm(emu[:m])
 
 
+@pytest.mark.parametrize("din,dout", [(12, 16), (16, 1)])
+def test_fused_inference_wide_inputs_and_outputs(din, dout):
+    """The fused path's other instantiation (9 to 16 inputs) and the output
+    widths at its limits, against the BF16 emulation over a ragged batch."""
+    import torch
+    from paper_2506_05362_amd import mlp
+    dims = [din, 256, 256, 256, dout]
+    rng = np.random.default_rng(din)
+    p = (M.init_params(dims, seed=din) + rng.normal(0, 0.02, M.n_params(dims))).astype(np.float32).astype(np.float64)
+    net = mlp.Net(dims, max_batch=512)
+    net.set_params(p)
+    X = rng.normal(size=(700, din))
+    net.set_inference(True)
+    y = net.forward(torch.tensor(X, dtype=torch.float32)).cpu().numpy()
+    emu, _ = forward_bf16(p, dims, X)
+    assert np.linalg.norm(y - emu) <= 2e-4 * np.linalg.norm(emu)
+    assert np.abs(y - emu).max() <= 3e-3 * np.abs(emu).max()
+
+
 def test_fused_inference_unsupported_shape():
     import torch
     from paper_2506_05362_amd import mlp
