@@ -567,12 +567,17 @@ def main(argv=None):
         sp = path_specs(2)[1]
         wl = I.rve_aggregate(seed=sp.seed, confinement=sp.confinement,
                              **{**RVE_DEFAULTS, "n_grains": a.grains, "nodes_per_grain": a.nodes_per_grain})
-        sim = pd.Sim(wl)
+        sim = pd.Sim(wl, candidate_capacity_per_node=SIM_CAPACITY)
+        try:  # the launch the path generation uses
+            sim.set_launch(bond_path=pd.BONDS_TILES)
+        except pd.PDError:
+            pass
         sim.step(a.time_path)
         t0 = time.perf_counter()
         sim.step(a.time_path)  # returns when the GPU is done
         ms = (time.perf_counter() - t0) / a.time_path * 1e3
-        print(json.dumps({"ms_per_step": ms, **sim.info()}), flush=True)
+        print(json.dumps({"ms_per_step": ms, **sim.info(), **sim.loop_counts(),
+                          "bond_path": sim.get_launch()["bond_path"]}), flush=True)
         sim.close()
         return
     res = run(n_paths=a.paths, n_held=a.held, n_log=a.log_every, train_steps=a.train_steps,
