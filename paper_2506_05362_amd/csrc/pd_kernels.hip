@@ -1074,8 +1074,11 @@ __global__ __launch_bounds__(kTS * kWave) __attribute__((amdgpu_waves_per_eu(4))
   uint64_t* mrow_w = A.lmask + ((int64_t)t * kTS + wid) * kTileClasses;
   const PolyG PG = poly_in_registers();
   int nbroke = 0;  // bonds of this lane's node broken in this step
-  tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, mrow_r, mrow_w, PG, ui.x, ui.y,
-                  ui.z, G->abs_ratio, nbroke, fx, fy, fz);
+  // a layer beyond the last nodes of the box (the far ends of a lattice-mode
+  // box) has no bonds: its wavefront leaves the vector units to the others
+  if (__ballot(valid) != 0ull)
+    tile_bonds<ABS>(std::make_integer_sequence<int, kTileClasses>{}, L, Lz, tab, mrow_r, mrow_w, PG, ui.x, ui.y,
+                    ui.z, G->abs_ratio, nbroke, fx, fy, fz);
   // the prefetch's data is not needed; consuming it keeps the load
   asm volatile("" ::"v"(mpre.x ^ mpre.y ^ mpre.z ^ mpre.w));
   node_tail<MODE_STEP, EXTRA>(A, i, valid, ui, G, unpack_x(pi), unpack_y(pi), unpack_z(pi), fx, fy, fz, nbroke,
