@@ -295,6 +295,21 @@ class Surrogate:
         return self.ys.inv(y.cpu().numpy().astype(np.float64))
 
 
+class SurrogateEnsemble:
+    """The mean prediction of networks trained alike from different initial
+    weights and minibatch orders; the envelope is the first one's (all saw the
+    same inputs)."""
+
+    def __init__(self, members: List["Surrogate"]):
+        self.members = members
+
+    def predict(self, X: np.ndarray) -> np.ndarray:
+        return np.mean([m.predict(X) for m in self.members], axis=0)
+
+    def in_envelope(self, X: np.ndarray, pad: float = 0.05) -> np.ndarray:
+        return self.members[0].in_envelope(X, pad)
+
+
 def rel_l2(pred: np.ndarray, ref: np.ndarray) -> float:
     return float(np.linalg.norm(pred - ref) / max(np.linalg.norm(ref), 1e-300))
 
@@ -458,9 +473,12 @@ def load_data(files: List[str]) -> Dict[str, np.ndarray]:
 
 def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int = 4000,
         infer_paths: int = 100000, infer_T: int = 100, seed: int = 0, out: Optional[str] = None,
-        log=print, data_file: Optional[str] = None, only: Optional[tuple] = None, **rve_kw) -> Dict:
+        log=print, data_file: Optional[str] = None, only: Optional[tuple] = None, nets: int = 1,
+        **rve_kw) -> Dict:
     """The whole study; with only = (a, b), just simulate paths a..b-1 of the
-    n_paths path set and save them (to join later with data_file)."""
+    n_paths path set and save them (to join later with data_file).  nets > 1
+    trains that many networks (seeds seed, seed + 1, ...) and evaluates their
+    mean, beside the first one alone."""
     rve_kw = {**RVE_DEFAULTS, **rve_kw}
     t0 = time.perf_counter()
     if only is not None:
@@ -485,14 +503,27 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
     train = np.arange(0, n_ok - n_held)
     X = samples(data, train, "strain")
     Y = samples(data, train, "target")
-    sur = Surrogate(seed=seed)
+    members = []
     t1 = time.perf_counter()
-    losses = sur.fit(X, Y, steps=train_steps, seed=seed, log=log)
+    for k in range(max(1, nets)):
+        m = Surrogate(seed=seed + k)
+        lk = m.fit(X, Y, steps=train_steps, seed=seed + k, log=log if k == 0 else None)
+        if k == 0:
+            losses = lk
+        members.append(m)
     train_s = time.perf_counter() - t1
+    sur = members[0] if len(members) == 1 else SurrogateEnsemble(members)
     ev = evaluate(sur, data, held, train)
+    if len(members) > 1:
+        one = evaluate(members[0], data, held, train)
+        ev["first_network"] = {k: one[k] for k in ("axial_rel_l2", "axial_rel_l2_mean",
+                                                   "axial_rel_l2_prepeak_mean")}
     paths = inference_paths(data, train, infer_paths, T=infer_T)
     inside = float(sur.in_envelope(paths.reshape(-1, 6)).mean())
-    inf = time_inference(sur, paths)
+    inf = time_inference(members[0], paths)
+    if len(members) > 1:  # each network runs the whole batch
+        inf = {**inf, "networks": len(members), "seconds": inf["seconds"] * len(members),
+               "seconds_per_path": inf["seconds_per_path"] * len(members)}
     # GPU seconds of one full path: per-step cost of each run times its length
     per_path = data["seconds"] / np.maximum(data["steps_run"], 1) * data["steps"]
     sim_per_path = float(np.mean(per_path))
@@ -504,7 +535,7 @@ def run(n_paths: int = 64, n_held: int = 8, n_log: int = 400, train_steps: int =
         "nodes_mean": float(np.mean(data["nodes"])), "bonds_mean": float(np.mean(data["bonds"])),
         "steps_per_path": int(np.max(data["steps"])),
         "generate_seconds": gen_s, "sim_seconds_per_path": sim_per_path,
-        "train_seconds": train_s, "train_steps": train_steps, "final_loss": losses[-1],
+        "train_seconds": train_s, "train_steps": train_steps, "final_loss": losses[-1], "nets": len(members),
         **ev, "scatter_of_training_paths": pair_scatter(data, train),
         "inference": inf, "inference_inside_envelope": inside,
         "speedup_per_path": sim_per_path / inf["seconds_per_path"],
@@ -534,6 +565,8 @@ def main(argv=None):
     ap.add_argument("--data", default=None, metavar="NPZ[,NPZ...]",
                     help="train and evaluate on paths earlier runs saved (their _data.npz, joined in order) "
                          "instead of simulating")
+    ap.add_argument("--nets", type=int, default=1,
+                    help="train this many networks from different seeds and evaluate their mean")
     ap.add_argument("--only", default=None, metavar="A:B",
                     help="only simulate paths A..B-1 of the --paths set and save them (no training)")
     ap.add_argument("--scatter", default=None, metavar="NPZ[,NPZ...]",
@@ -584,7 +617,7 @@ def main(argv=None):
               infer_paths=a.infer_paths, out=a.out, n_grains=a.grains,
               nodes_per_grain=a.nodes_per_grain, platen_speed=a.platen_speed,
               log=lambda s: print(s, flush=True), data_file=a.data,
-              only=tuple(int(v) for v in a.only.split(":")) if a.only else None)
+              only=tuple(int(v) for v in a.only.split(":")) if a.only else None, nets=a.nets)
     print(json.dumps({k: v for k, v in res.items() if not isinstance(v, list)}), flush=True)
 
 
